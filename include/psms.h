@@ -1,0 +1,167 @@
+/* libpsms: Wilson-Dirac / domain-decomposition hot path of the stochastic
+ * fermion-determinant-ratio estimator (Finkenrath, Knechtli, Leder, "Fermions
+ * as Global Correction: the QCD Case"), for AMD MI355X (gfx950).
+ *
+ * Conventions for every call
+ * --------------------------
+ * Operator. D = 2 kappa (D_w + m_0) = 1 - kappa H, the Wilson-Dirac operator of
+ *   eq. Dw (Sec. 5) with kappa = 1/(2 m_0 + 8); periodic in space, antiperiodic
+ *   in time when geom.antiperiodic_t is set (Sec. 6). Gamma matrices in the
+ *   chiral basis gamma_0 = [[0,-1],[-1,0]], gamma_k = [[0,-i s_k],[i s_k,0]].
+ * Sites. Direction 0 is time; site index ((x0*L1 + x1)*L2 + x2)*L3 + x3.
+ * Spinor fields (every "in", "out", "b", "x", "noise"): nrhs consecutive fields,
+ *   each [V][4 spin][3 colour] complex FP64 stored as interleaved (re, im):
+ *   24*V doubles per field. FP64 at the boundary for every precision.
+ * Gauge fields: [V][4 mu][3][3] complex FP64 (row-major 3x3), U[x][mu] is the link
+ *   from x to x + mu.
+ * Blocks (Sec. 3, eq. domdec): non-overlapping boxes of size b[mu]; the block
+ *   containing the origin is black, colours alternate like a checker board.
+ *   Requirements: L[mu] % b[mu] == 0, L[mu]/b[mu] even, b[mu] even, L[mu] <= 255.
+ * Pointers. Any pointer may be host memory or device memory of the context's
+ *   device (e.g. a PyTorch tensor's data_ptr). Device pointers are used in place;
+ *   host buffers are staged. Work runs on the stream given to psms_create; calls
+ *   return after the results are in the caller's buffers (host outputs) or
+ *   enqueued (device outputs). The caller owns every buffer; nothing is freed
+ *   across the ABI. One context per stream and thread.
+ * Errors. Every call returns a psms_status; no exception crosses the ABI.
+ *   psms_last_error() gives a message for the last failure on the context.
+ */
+#ifndef PSMS_H
+#define PSMS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSMS_OK = 0,
+  PSMS_EINVAL = -1,    /* bad argument or geometry */
+  PSMS_ENOMEM = -2,    /* device allocation failed */
+  PSMS_EHIP = -3,      /* HIP runtime error */
+  PSMS_ENOTCONV = -4,  /* solver hit max_iter or stagnated; outputs hold the last iterate */
+  PSMS_ENOTSU3 = -5,   /* a link is not SU(3) (12-real compression needs it) */
+  PSMS_ENAN = -6       /* NaN or Inf met in a residual */
+} psms_status;
+
+typedef enum { PSMS_F64 = 0, PSMS_MIXED = 1 } psms_prec;  /* MIXED: FP32 12-real links, FP32/BF16 spinors inside, FP64 outside */
+typedef enum { PSMS_OP_FULL = 0, PSMS_OP_SCHUR = 1 } psms_op;
+typedef enum { PSMS_PC_NONE = 0, PSMS_PC_SAP = 1, PSMS_PC_NET = 2 } psms_pc;
+typedef enum { PSMS_SPINOR_F32 = 0, PSMS_SPINOR_BF16 = 1 } psms_inner_storage;
+
+typedef struct {
+  int L[4];            /* lattice extent, mu = 0 is time */
+  int b[4];            /* block extent */
+  int antiperiodic_t;  /* 1: fermions antiperiodic in time */
+  double kappa;        /* hopping parameter */
+} psms_geom;
+
+typedef struct {
+  double tol;          /* stop when the FP64 true residual |b - D x| / |b| <= tol, per right-hand side */
+  int max_iter;        /* outer iterations (FP64 path: GCR iterations; mixed: total inner iterations) */
+  int restart;         /* GCR restart length (Krylov basis size), <= 64 */
+  psms_prec prec;
+  psms_pc pc;          /* right preconditioner of the flexible GCR */
+  int sap_cycles;      /* Schwarz cycles per preconditioner application */
+  int block_iters;     /* minimal-residual iterations per block solve inside the Schwarz cycle */
+  double inner_tol;    /* mixed: relative residual reduction asked of each inner solve */
+  psms_inner_storage inner_storage;
+  int net_fallback;    /* PC_NET: fall back to SAP when the residual stalls */
+  int rhs_chunk;       /* psms_logdet_ratio: right-hand sides solved together (0: all) */
+} psms_solve_params;
+
+typedef struct {
+  int converged;
+  int outer_iters;        /* defect-correction steps (mixed) or restarts (FP64) */
+  int inner_iters;        /* total GCR iterations */
+  int used_fallback;
+  double true_rel_residual; /* max over right-hand sides */
+  double seconds;
+} psms_solve_stats;
+
+typedef struct psms_ctx psms_ctx;
+
+/* Fills params with defaults: tol 1e-10, max_iter 2000, restart 16, F64, SAP,
+ * 4 cycles, 4 block iterations, inner_tol 1e-2 (BF16 inner storage clamps it to
+ * >= 5e-3), F32 inner storage, fallback on, rhs_chunk 0. */
+void psms_default_params(psms_solve_params* params);
+
+/* Creates a context for the geometry on HIP device `device`, enqueueing work on
+ * `hip_stream` (hipStream_t, may be NULL for the default stream). */
+psms_status psms_create(const psms_geom* geom, int device, void* hip_stream, psms_ctx** out);
+void psms_destroy(psms_ctx* ctx);
+const char* psms_last_error(const psms_ctx* ctx);
+const char* psms_status_string(psms_status s);
+/* Device bytes held by the context (gauge copies and workspaces). */
+unsigned long long psms_device_bytes(const psms_ctx* ctx);
+
+/* Uploads gauge field U into slot (0 <= slot < 64), converting it to the internal
+ * layouts (FP64 and FP32 12-real). Returns PSMS_ENOTSU3 if some link deviates from
+ * SU(3) by more than 1e-6 (the FP64 copy is still loaded; mixed precision is then
+ * refused for this slot). */
+psms_status psms_gauge_load(psms_ctx* ctx, int slot, const double* U);
+
+/* out = D in (eq. Dw, rescaled), full lattice. prec MIXED applies the FP32 12-real
+ * link, FP32 spinor kernel (input rounded to FP32). */
+psms_status psms_apply_dw(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs, psms_prec prec);
+
+/* Even-odd preconditioned operator on even sites: out_e = in_e - kappa^2 H_eo H_oe in_e
+ * (the block-size-one case of eq. ddfactor). Odd sites of `in` are ignored, odd sites
+ * of `out` are set to zero. */
+psms_status psms_apply_dhat_ee(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs);
+
+/* out = D_bb in (colour 0) or D_ww in (colour 1): the block-diagonal part of D on the
+ * blocks of that colour with Dirichlet block boundaries (eq. domdec). Sites of the
+ * other colour are ignored in `in` and zero in `out`. */
+psms_status psms_apply_block(psms_ctx* ctx, int slot, int colour, const double* in, double* out, int nrhs);
+
+/* Inter-block hops (eq. domdec): from_colour 0 gives out = D_wb in (input on black
+ * sites, output on white sites), from_colour 1 gives out = D_bw in. */
+psms_status psms_apply_hop_bw(psms_ctx* ctx, int slot, int from_colour, const double* in, double* out, int nrhs);
+
+/* out = P in: the orthogonal projector of Sec. 4.4 onto the boundary sites of the
+ * black blocks ((1 + gamma_mu)/2 or (1 - gamma_mu)/2 where a site has a single
+ * neighbour in another block, at +mu or -mu; identity with two or more; zero elsewhere). */
+psms_status psms_apply_proj(psms_ctx* ctx, const double* in, double* out, int nrhs);
+
+/* Solves D x = b (flexible GCR with the chosen right preconditioner; mixed precision
+ * wraps FP32/BF16 inner solves in FP64 defect correction). x is an output only. */
+psms_status psms_solve(psms_ctx* ctx, int slot, const double* b, double* x, int nrhs, const psms_solve_params* params,
+                       psms_solve_stats* stats);
+
+/* Solves D_bb x = b (colour 0) or D_ww x = b (colour 1) block by block to params->tol
+ * relative residual per block (at most params->max_iter iterations). */
+psms_status psms_solve_block(psms_ctx* ctx, int slot, int colour, const double* b, double* x, int nrhs,
+                             const psms_solve_params* params, psms_solve_stats* stats);
+
+/* out = (1 - P Q) in with Q = D_bb^-1 D_bw D_ww^-1 D_wb (eq. detschur); `in` must lie in
+ * the range of P. Block inverses to params->tol. */
+psms_status psms_apply_schur(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs,
+                             const psms_solve_params* params, psms_solve_stats* stats);
+
+/* out = (1 - P Q)^-1 in = in - P [D^-1 (0 + D_wb in)]_black (eq. inverseschur): one
+ * full-lattice solve per right-hand side. */
+psms_status psms_apply_schur_inv(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs,
+                                 const psms_solve_params* params, psms_solve_stats* stats);
+
+/* Stochastic estimator (eq. stacc, eq. Deltaistoch). For every proposal slot_Up[p] and
+ * noise field eta_j: delta[p*nnoise + j] = |M xi_j|^2 - |xi_j|^2 with
+ *   op FULL : M = D(U')^-1 D(U),                 xi_j = eta_j;
+ *   op SCHUR: M = (1 - PQ(U'))^-1 (1 - PQ(U)),   xi_j = P eta_j.
+ * noise holds nnoise fields with density exp(-|eta|^2); n_interp must be 1.
+ * delta may be host or device memory (nprop*nnoise doubles). */
+psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise,
+                              int nnoise, int n_interp, const psms_solve_params* params, double* delta,
+                              psms_solve_stats* stats);
+
+/* Kernel timing with HIP events on the context's stream. enable=1 starts recording
+ * the launches of the named kernel families ("dslash", "block_mr", "blas", "net"),
+ * 0 stops. psms_profile_read gives the total milliseconds, launch count and
+ * algorithmic bytes moved since the last enable. */
+psms_status psms_profile(psms_ctx* ctx, int enable);
+psms_status psms_profile_read(psms_ctx* ctx, const char* family, double* total_ms, long long* launches,
+                              double* algorithmic_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSMS_H */

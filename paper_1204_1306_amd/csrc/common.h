@@ -1,0 +1,313 @@
+// Device-side building blocks of the Wilson-Dirac hot path on gfx950:
+// complex arithmetic, spinor/link storage formats, the block-major even-odd
+// site layout and the spin-projected nearest-neighbour hop.
+//
+// Operator (eq. Dw, Sec. 5, rescaled): D = 1 - kappa H with
+//   H psi(x) = sum_mu U(x,mu)(1-gamma_mu) psi(x+mu) + U(x-mu,mu)^+ (1+gamma_mu) psi(x-mu),
+// antiperiodic in time (Sec. 6). Chiral gamma basis:
+//   gamma_0 = [[0,-1],[-1,0]], gamma_k = [[0,-i s_k],[i s_k,0]], gamma_5 = diag(1,1,-1,-1).
+// (1 -+ gamma_mu) has rank two, so each hop projects the spinor to two spin
+// components, multiplies them by the 3x3 link and rebuilds the lower half.
+//
+// Internal layout (sites innermost, one component plane per storage unit):
+//   site (parity p, index s) with s = blk * Vbh + i, blk = colour * nblk_c + (lexB >> 1),
+//   i = locallex >> 1 (blocks sorted black first as in eq. domdec; even-odd inside blocks).
+//   spinor field: [rhs][p][unit k][Vh]; link field: [p][mu][unit k][Vh] holding U(x,mu).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psms {
+
+// ----------------------------------------------------------------- complex
+template <class T> struct cx { T re, im; };
+
+template <class T> __host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <class T> __host__ __device__ __forceinline__ cx<T> cjmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <class T> __host__ __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.im, -a.re}; }
+template <class T> __host__ __device__ __forceinline__ cx<T> scale(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+
+template <class T> struct Spinor { cx<T> v[4][3]; };   // [spin][colour]
+template <class T> struct SU3 { cx<T> m[3][3]; };      // [row][col]
+template <class T> struct Half { cx<T> h[2][3]; };     // projected two-spin vector
+
+template <class T> __host__ __device__ __forceinline__ void zero(Spinor<T>& s) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s.v[a][c] = {T(0), T(0)};
+}
+
+// ----------------------------------------------------------------- bf16
+// Round-to-nearest-even float -> bfloat16 from the IEEE-754 binary32 layout:
+// keep the top 16 bits, adding half an ulp of bf16 plus the tie-break bit.
+__host__ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
+
+// ----------------------------------------------------------------- storage formats
+// Spinor storage: F64 = 12 double2 planes, F32 = 6 float4 planes, BF16 = 3 uint4 planes.
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+struct StF64 {
+  using unit = double2;
+  using real = double;
+  static constexpr int NC = 12;
+  template <class T> __device__ __forceinline__ static void load(const unit* __restrict__ p, size_t Vh, int s, Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      double2 d = p[k * Vh + s];
+      o.v[k / 3][k % 3] = {T(d.x), T(d.y)};
+    }
+  }
+  template <class T> __device__ __forceinline__ static void store(unit* __restrict__ p, size_t Vh, int s, const Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k * Vh + s] = make_double2(double(o.v[k / 3][k % 3].re), double(o.v[k / 3][k % 3].im));
+  }
+};
+
+struct StF32 {
+  using unit = float4;
+  using real = float;
+  static constexpr int NC = 6;
+  template <class T> __device__ __forceinline__ static void load(const unit* __restrict__ p, size_t Vh, int s, Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float4 d = p[k * Vh + s];
+      o.v[(2 * k) / 3][(2 * k) % 3] = {T(d.x), T(d.y)};
+      o.v[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(d.z), T(d.w)};
+    }
+  }
+  template <class T> __device__ __forceinline__ static void store(unit* __restrict__ p, size_t Vh, int s, const Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      cx<T> a = o.v[(2 * k) / 3][(2 * k) % 3], b = o.v[(2 * k + 1) / 3][(2 * k + 1) % 3];
+      p[k * Vh + s] = make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
+    }
+  }
+};
+
+struct StBF16 {
+  using unit = uint4;
+  using real = float;
+  static constexpr int NC = 3;
+  template <class T> __device__ __forceinline__ static void load(const unit* __restrict__ p, size_t Vh, int s, Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 d = p[k * Vh + s];
+      uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int e = 4 * k + j;
+        o.v[e / 3][e % 3] = {T(bf16_to_f32(w[j] & 0xffffu)), T(bf16_to_f32(w[j] >> 16))};
+      }
+    }
+  }
+  template <class T> __device__ __forceinline__ static void store(unit* __restrict__ p, size_t Vh, int s, const Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int e = 4 * k + j;
+        w[j] = uint32_t(f32_to_bf16(float(o.v[e / 3][e % 3].re))) | (uint32_t(f32_to_bf16(float(o.v[e / 3][e % 3].im))) << 16);
+      }
+      p[k * Vh + s] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+};
+
+// Link storage: F64 = 9 double2 planes; F32C12 = rows 0 and 1 as 3 float4 planes,
+// row 2 rebuilt as conj(row0 x row1) (valid for SU(3) links only).
+struct LkF64 {
+  using unit = double2;
+  static constexpr int NC = 9;
+  template <class T> __device__ __forceinline__ static void load(const unit* __restrict__ p, size_t Vh, int s, SU3<T>& u) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      double2 d = p[k * Vh + s];
+      u.m[k / 3][k % 3] = {T(d.x), T(d.y)};
+    }
+  }
+};
+
+struct LkF32C12 {
+  using unit = float4;
+  static constexpr int NC = 3;
+  template <class T> __device__ __forceinline__ static void load(const unit* __restrict__ p, size_t Vh, int s, SU3<T>& u) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float4 d = p[k * Vh + s];
+      u.m[(2 * k) / 3][(2 * k) % 3] = {T(d.x), T(d.y)};
+      u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(d.z), T(d.w)};
+    }
+    // row2 = conj(row0 x row1)
+    const cx<T>(&r0)[3] = u.m[0];
+    const cx<T>(&r1)[3] = u.m[1];
+    cx<T> c0 = cmul(r0[1], r1[2]) - cmul(r0[2], r1[1]);
+    cx<T> c1 = cmul(r0[2], r1[0]) - cmul(r0[0], r1[2]);
+    cx<T> c2 = cmul(r0[0], r1[1]) - cmul(r0[1], r1[0]);
+    u.m[2][0] = {c0.re, -c0.im};
+    u.m[2][1] = {c1.re, -c1.im};
+    u.m[2][2] = {c2.re, -c2.im};
+  }
+};
+
+// ----------------------------------------------------------------- geometry
+struct Geo {
+  int L[4], b[4], NB[4];
+  int sB[4], sl[4];       // lexicographic strides of block coords and local coords
+  int Vh, Vbh, nblk, nblk_c;
+  int apbc;
+  const uint32_t* lcoord;  // [2][Vbh] local coords of (parity, i), 8 bits each
+  const uint32_t* bcoord;  // [nblk] block coords of blk, 8 bits each
+};
+
+// Everything the stencil needs about one site.
+struct SiteInfo {
+  int l[4], B[4];
+  int locallex, lexB, colour;
+};
+
+__device__ __forceinline__ void site_info(const Geo& g, int p, int s, SiteInfo& si) {
+  int blk = s / g.Vbh;
+  int i = s - blk * g.Vbh;
+  uint32_t lc = g.lcoord[p * g.Vbh + i];
+  uint32_t bc = g.bcoord[blk];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    si.l[m] = (lc >> (8 * m)) & 255;
+    si.B[m] = (bc >> (8 * m)) & 255;
+  }
+  si.colour = blk >= g.nblk_c ? 1 : 0;
+  si.locallex = 2 * i + (si.l[3] & 1);
+  si.lexB = 2 * (blk - si.colour * g.nblk_c) + (si.B[3] & 1);
+}
+
+// Neighbour x + dir*mu (dir = +1 or -1). Returns its index within the opposite
+// parity, whether the hop leaves the block and the boundary sign (-1 across the
+// time boundary with antiperiodic fermions).
+struct Nbr {
+  int s;
+  bool cross;
+  float sign;
+};
+
+__device__ __forceinline__ Nbr neighbour(const Geo& g, const SiteInfo& si, int mu, int dir) {
+  Nbr n;
+  int ll = si.locallex, lb = si.lexB, col = si.colour;
+  int lm = si.l[mu] + dir;
+  n.sign = 1.f;
+  if (lm >= 0 && lm < g.b[mu]) {
+    ll += dir * g.sl[mu];
+    n.cross = false;
+  } else {
+    n.cross = true;
+    ll -= dir * (g.b[mu] - 1) * g.sl[mu];
+    int Bm = si.B[mu] + dir;
+    if (Bm < 0) {
+      lb += (g.NB[mu] - 1) * g.sB[mu];
+      if (mu == 0 && g.apbc) n.sign = -1.f;
+    } else if (Bm >= g.NB[mu]) {
+      lb -= (g.NB[mu] - 1) * g.sB[mu];
+      if (mu == 0 && g.apbc) n.sign = -1.f;
+    } else {
+      lb += dir * g.sB[mu];
+    }
+    col ^= 1;
+  }
+  n.s = (col * g.nblk_c + (lb >> 1)) * g.Vbh + (ll >> 1);
+  return n;
+}
+
+// ----------------------------------------------------------------- SU(3) x vector
+template <class T> __device__ __forceinline__ void su3_mul(const SU3<T>& u, const cx<T> (&v)[3], cx<T> (&o)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o[a] = cmul(u.m[a][0], v[0]) + cmul(u.m[a][1], v[1]) + cmul(u.m[a][2], v[2]);
+}
+template <class T> __device__ __forceinline__ void su3_dag_mul(const SU3<T>& u, const cx<T> (&v)[3], cx<T> (&o)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o[a] = cjmul(u.m[0][a], v[0]) + cjmul(u.m[1][a], v[1]) + cjmul(u.m[2][a], v[2]);
+}
+
+// acc += c * U(x,mu) (1 - gamma_mu) psi   (psi = psi(x+mu), c includes the boundary sign)
+template <class T> __device__ __forceinline__ void hop_fwd(int mu, const SU3<T>& U, const Spinor<T>& p, T c, Spinor<T>& acc) {
+  cx<T> h0[3], h1[3], u0[3], u1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    switch (mu) {
+      case 0: h0[a] = p.v[0][a] + p.v[2][a]; h1[a] = p.v[1][a] + p.v[3][a]; break;
+      case 1: h0[a] = p.v[0][a] + times_i(p.v[3][a]); h1[a] = p.v[1][a] + times_i(p.v[2][a]); break;
+      case 2: h0[a] = p.v[0][a] + p.v[3][a]; h1[a] = p.v[1][a] - p.v[2][a]; break;
+      default: h0[a] = p.v[0][a] + times_i(p.v[2][a]); h1[a] = p.v[1][a] - times_i(p.v[3][a]); break;
+    }
+  }
+  su3_mul(U, h0, u0);
+  su3_mul(U, h1, u1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u0[a] = scale(c, u0[a]);
+    u1[a] = scale(c, u1[a]);
+    acc.v[0][a] = acc.v[0][a] + u0[a];
+    acc.v[1][a] = acc.v[1][a] + u1[a];
+    switch (mu) {
+      case 0: acc.v[2][a] = acc.v[2][a] + u0[a]; acc.v[3][a] = acc.v[3][a] + u1[a]; break;
+      case 1: acc.v[2][a] = acc.v[2][a] + times_mi(u1[a]); acc.v[3][a] = acc.v[3][a] + times_mi(u0[a]); break;
+      case 2: acc.v[2][a] = acc.v[2][a] - u1[a]; acc.v[3][a] = acc.v[3][a] + u0[a]; break;
+      default: acc.v[2][a] = acc.v[2][a] + times_mi(u0[a]); acc.v[3][a] = acc.v[3][a] + times_i(u1[a]); break;
+    }
+  }
+}
+
+// acc += c * U(x-mu,mu)^+ (1 + gamma_mu) psi   (psi = psi(x-mu))
+template <class T> __device__ __forceinline__ void hop_bwd(int mu, const SU3<T>& U, const Spinor<T>& p, T c, Spinor<T>& acc) {
+  cx<T> h0[3], h1[3], w0[3], w1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    switch (mu) {
+      case 0: h0[a] = p.v[0][a] - p.v[2][a]; h1[a] = p.v[1][a] - p.v[3][a]; break;
+      case 1: h0[a] = p.v[0][a] + times_mi(p.v[3][a]); h1[a] = p.v[1][a] + times_mi(p.v[2][a]); break;
+      case 2: h0[a] = p.v[0][a] - p.v[3][a]; h1[a] = p.v[1][a] + p.v[2][a]; break;
+      default: h0[a] = p.v[0][a] + times_mi(p.v[2][a]); h1[a] = p.v[1][a] + times_i(p.v[3][a]); break;
+    }
+  }
+  su3_dag_mul(U, h0, w0);
+  su3_dag_mul(U, h1, w1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    w0[a] = scale(c, w0[a]);
+    w1[a] = scale(c, w1[a]);
+    acc.v[0][a] = acc.v[0][a] + w0[a];
+    acc.v[1][a] = acc.v[1][a] + w1[a];
+    switch (mu) {
+      case 0: acc.v[2][a] = acc.v[2][a] - w0[a]; acc.v[3][a] = acc.v[3][a] - w1[a]; break;
+      case 1: acc.v[2][a] = acc.v[2][a] + times_i(w1[a]); acc.v[3][a] = acc.v[3][a] + times_i(w0[a]); break;
+      case 2: acc.v[2][a] = acc.v[2][a] + w1[a]; acc.v[3][a] = acc.v[3][a] - w0[a]; break;
+      default: acc.v[2][a] = acc.v[2][a] + times_i(w0[a]); acc.v[3][a] = acc.v[3][a] - times_i(w1[a]); break;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- reductions
+// Wave64 sum with DPP-free shuffles (__shfl_xor), deterministic order.
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace psms

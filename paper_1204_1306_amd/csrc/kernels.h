@@ -1,0 +1,97 @@
+// Host-side launchers of the HIP kernels (internal to libpsms; not the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace psms {
+
+constexpr int MAXPROP = 16;  // proposals (gauge fields) addressed by one launch
+
+enum HopSel : int { HOP_ALL = 0, HOP_INTRA = 1, HOP_CROSS = 2 };
+enum LinkFmt : int { LK_F64 = 0, LK_F32C12 = 1 };
+
+// A batch of spinor fields: nprop groups of nrhs fields, [prop][rhs][p][unit][Vh].
+struct FieldBatch {
+  void* p;
+  Prec prec;
+  int nprop, nrhs;
+};
+
+size_t units_per_field(Prec prec, int Vh);        // storage units of one full-lattice field
+size_t bytes_per_field(Prec prec, int Vh);
+
+struct DslashParams {
+  int sel;                 // HopSel
+  int p0, np;              // output parities [p0, p0 + np)
+  int blk0, nb;            // output blocks [blk0, blk0 + nb)
+  double cdiag, chop;      // out = cdiag * in(x) + chop * (H_sel in)(x) [+ out if accumulate]
+  int accumulate;
+};
+
+// out = cdiag * in + chop * H_sel in (+ out), on the selected parities/blocks.
+void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& in,
+                   const FieldBatch& out, const DslashParams& dp, int nr_pref);
+
+// boundary layout [rhs][V][4][3] complex double  <->  internal batch
+void launch_pack(hipStream_t st, const Geo& g, const double* src, const FieldBatch& dst);
+void launch_unpack(hipStream_t st, const Geo& g, const FieldBatch& src, double* dst);
+// links [V][4][3][3] complex double -> internal F64 or F32C12
+void launch_pack_links(hipStream_t st, const Geo& g, const double* U, void* dst, int linkfmt);
+// max over links of |U U^+ - 1| (per-workgroup maxima in partial, host reduces)
+void launch_unitarity(hipStream_t st, const Geo& g, const double* U, double* partial, int nwg);
+
+// out = P in (projector of the Schur complement, black block boundaries)
+void launch_project(hipStream_t st, const Geo& g, const FieldBatch& in, const FieldBatch& out);
+
+// --- BLAS-1 on batches (per-RHS complex coefficients read from device arrays)
+// y = a[r] * x + b[r] * y   (a, b: complex per rhs; nullptr a -> 0, nullptr b -> 1)
+void launch_axpby(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const double2* b,
+                  const FieldBatch& y, int coef_sign);
+// y = x (precision conversion allowed), optionally scaled by real s[r]
+void launch_copy(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const double* s);
+void launch_zero(hipStream_t st, const FieldBatch& y, int Vh);
+// zero the sites of one parity in every field of the batch
+void launch_zero_parity(hipStream_t st, const FieldBatch& y, int Vh, int parity);
+// zero every site whose block colour differs from keep_colour
+void launch_keep_colour(hipStream_t st, const Geo& g, const FieldBatch& y, int keep_colour);
+// y -= sum_{j<m} c[r][j] * X_j, X_j = basis + j * vstride units; c laid out [rhs][cstride]
+void launch_lincomb(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const double2* c,
+                    int cstride, const FieldBatch& y, int sign);
+
+// Deterministic two-pass reductions. out[r*k + j] (double2) or out[r] (double).
+struct Reducer {
+  double* partial;   // scratch, >= nrhs_total * nwg * 2 * kmax doubles
+  int nwg;           // workgroups per rhs in pass one
+};
+void reduce_norm2(hipStream_t st, const Geo& g, const FieldBatch& x, const Reducer& R, double* out);
+// out[r*m + j] = (X_j, y)_r for j < m, X_j = basis + j*vstride
+void reduce_multidot(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m,
+                     const FieldBatch& y, const Reducer& R, double2* out);
+
+// --- block solver (Schwarz / Dirichlet block inverses, minimal residual)
+struct BlockMRParams {
+  int colour;
+  int niter;
+  double tol;     // >0: stop a block when |r_b| <= tol |rho_b(initial)|
+  double kappa;
+};
+// For every block of the colour: delta = MR approximation of D_b^-1 rho_b, x += delta,
+// rho_b <- rho_b - D_b delta. pbuf is scratch of the same shape.
+void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& rho,
+                     const FieldBatch& x, const FieldBatch& delta, const FieldBatch& pbuf, const BlockMRParams& bp,
+                     int* iters_out);
+
+// --- flexible GCR scalar kernels and mixed-storage site-level ops
+void gcr_proj(hipStream_t st, const double2* c, const double* nw, int k, int m, int nrhs, double2* a, double2* T);
+void gcr_alpha(hipStream_t st, const double2* d, const double* nw, int k, int m, int nrhs, const int* active, double2* alpha,
+               double2* neg_alpha);
+void gcr_backsub(hipStream_t st, const double2* T, const double2* alpha, int n, int m, int nrhs, double2* beta);
+void scatter_col(hipStream_t st, const double* src, int k, int m, int nrhs, double* dst);
+void defect_scales(hipStream_t st, const double* v, const int* active, int nrhs, double* inv, double2* sq);
+void launch_axpy_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, int sgn);
+void reduce_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double2* out);
+
+}  // namespace psms

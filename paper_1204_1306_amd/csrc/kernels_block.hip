@@ -1,0 +1,197 @@
+// Block solves for the Schwarz preconditioner and the Dirichlet block inverses
+// D_bb^-1, D_ww^-1 of the Schur complement (eq. ddfactor). One workgroup owns one
+// block of one right-hand side: all blocks of a colour, all right-hand sides and
+// all proposals run in a single launch. The block operator D_b is the principal
+// sub-matrix of D on the block (hops leaving the block are dropped: Dirichlet).
+// Minimal-residual iteration; the workgroup reduces its own inner products, so
+// no grid-wide synchronisation is needed.
+#include "kernels.h"
+
+namespace psms {
+
+struct BlockArgs {
+  Geo g;
+  const void* links[MAXPROP];
+  void* rho;
+  void* x;
+  void* delta;
+  void* pbuf;
+  size_t rhs_stride;  // units
+  int nrhs, colour, niter;
+  double tol, kappa;
+  int* iters;
+};
+
+// (D_b r)(x) for one site: r(x) - kappa * sum of the intra-block hops.
+template <class S, class LK, class T>
+__device__ __forceinline__ void block_op_site(const Geo& g, const typename LK::unit* __restrict__ lk,
+                                              const typename S::unit* __restrict__ r, int p, int s, T mk, Spinor<T>& out) {
+  const size_t Vh = g.Vh;
+  SiteInfo si;
+  site_info(g, p, s, si);
+  zero(out);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    Nbr n = neighbour(g, si, mu, +1);
+    if (!n.cross) {
+      SU3<T> U;
+      LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+      Spinor<T> nb;
+      S::load(r + size_t(1 - p) * S::NC * Vh, Vh, n.s, nb);
+      hop_fwd(mu, U, nb, mk, out);
+    }
+    n = neighbour(g, si, mu, -1);
+    if (!n.cross) {
+      SU3<T> U;
+      LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+      Spinor<T> nb;
+      S::load(r + size_t(1 - p) * S::NC * Vh, Vh, n.s, nb);
+      hop_bwd(mu, U, nb, mk, out);
+    }
+  }
+  Spinor<T> d;
+  S::load(r + size_t(p) * S::NC * Vh, Vh, s, d);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.v[a][c] = out.v[a][c] + d.v[a][c];
+}
+
+__device__ __forceinline__ double wg_sum(double v, double* sm) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) t += sm[k];
+  return t;
+}
+
+template <class S, class LK, class T>
+__global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
+  __shared__ double sm[16];
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int blk = a.colour * g.nblk_c + blockIdx.x;
+  const int prop = blockIdx.z;
+  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  using unit = typename S::unit;
+  unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  unit* x = reinterpret_cast<unit*>(a.x) + roff;
+  unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
+  unit* pb = reinterpret_cast<unit*>(a.pbuf) + roff;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const int nsite = 2 * g.Vbh;
+  const T mk = T(-a.kappa);
+
+  // delta = 0, |rho_b|^2
+  double b2 = 0.0;
+  for (int j = threadIdx.x; j < nsite; j += blockDim.x) {
+    int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
+    Spinor<T> v, z;
+    S::load(rho + size_t(p) * S::NC * Vh, Vh, s, v);
+    zero(z);
+    S::store(dl + size_t(p) * S::NC * Vh, Vh, s, z);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) b2 += double(v.v[q][c].re) * v.v[q][c].re + double(v.v[q][c].im) * v.v[q][c].im;
+  }
+  b2 = wg_sum(b2, sm);
+  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
+
+  int it = 0;
+  if (b2 > 0.0) {
+    for (; it < a.niter; ++it) {
+      // p = D_b r,  (p, r) and |p|^2
+      double prr = 0.0, pri = 0.0, pp = 0.0;
+      for (int j = threadIdx.x; j < nsite; j += blockDim.x) {
+        int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
+        Spinor<T> Dr, r;
+        block_op_site<S, LK, T>(g, lk, rho, p, s, mk, Dr);
+        S::load(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+        S::store(pb + size_t(p) * S::NC * Vh, Vh, s, Dr);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double ar = Dr.v[q][c].re, ai = Dr.v[q][c].im, br = r.v[q][c].re, bi = r.v[q][c].im;
+            prr += ar * br + ai * bi;
+            pri += ar * bi - ai * br;
+            pp += ar * ar + ai * ai;
+          }
+      }
+      prr = wg_sum(prr, sm);
+      pri = wg_sum(pri, sm);
+      pp = wg_sum(pp, sm);
+      if (!(pp > 0.0)) break;
+      const cx<T> alpha = {T(prr / pp), T(pri / pp)};
+      double rr = 0.0;
+      for (int j = threadIdx.x; j < nsite; j += blockDim.x) {
+        int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
+        Spinor<T> r, pv, d;
+        S::load(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+        S::load(pb + size_t(p) * S::NC * Vh, Vh, s, pv);
+        S::load(dl + size_t(p) * S::NC * Vh, Vh, s, d);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            d.v[q][c] = d.v[q][c] + cmul(alpha, r.v[q][c]);
+            r.v[q][c] = r.v[q][c] - cmul(alpha, pv.v[q][c]);
+            rr += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+          }
+        S::store(dl + size_t(p) * S::NC * Vh, Vh, s, d);
+        S::store(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+      }
+      rr = wg_sum(rr, sm);  // also orders the rho stores before the next sweep reads them
+      if (rr <= stop2) { ++it; break; }
+    }
+  }
+  // x += delta
+  for (int j = threadIdx.x; j < nsite; j += blockDim.x) {
+    int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
+    Spinor<T> d, xv;
+    S::load(dl + size_t(p) * S::NC * Vh, Vh, s, d);
+    S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
+    S::store(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+  }
+  if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
+}
+
+template <class S, class LK, class T>
+static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
+  dim3 grid(a.g.nblk_c, a.nrhs, nprop);
+  int threads = 2 * a.g.Vbh < 256 ? ((2 * a.g.Vbh + 63) / 64) * 64 : 256;
+  hipLaunchKernelGGL((k_block_mr<S, LK, T>), grid, dim3(threads), 0, st, a);
+}
+
+void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& rho,
+                     const FieldBatch& x, const FieldBatch& delta, const FieldBatch& pbuf, const BlockMRParams& bp,
+                     int* iters_out) {
+  BlockArgs a;
+  a.g = g;
+  for (int i = 0; i < MAXPROP; ++i) a.links[i] = i < rho.nprop ? links[i] : nullptr;
+  a.rho = rho.p;
+  a.x = x.p;
+  a.delta = delta.p;
+  a.pbuf = pbuf.p;
+  a.rhs_stride = units_per_field(rho.prec, g.Vh);
+  a.nrhs = rho.nrhs;
+  a.colour = bp.colour;
+  a.niter = bp.niter;
+  a.tol = bp.tol;
+  a.kappa = bp.kappa;
+  a.iters = iters_out;
+  if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);
+  else if (rho.prec == P_F32 && linkfmt == LK_F32C12) block_go<StF32, LkF32C12, float>(st, a, rho.nprop);
+  else if (rho.prec == P_BF16 && linkfmt == LK_F32C12) block_go<StBF16, LkF32C12, float>(st, a, rho.nprop);
+}
+
+}  // namespace psms

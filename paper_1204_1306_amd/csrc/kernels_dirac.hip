@@ -1,0 +1,365 @@
+// Wilson-Dirac stencil kernels (eq. Dw), the Schur projector P (Sec. 4.4) and
+// the boundary <-> internal layout conversions.
+#include "kernels.h"
+
+namespace psms {
+
+size_t units_per_field(Prec prec, int Vh) {
+  int nc = prec == P_F64 ? 12 : prec == P_F32 ? 6 : 3;
+  return size_t(2) * nc * Vh;
+}
+size_t bytes_per_field(Prec prec, int Vh) { return units_per_field(prec, Vh) * 16; }
+
+// ----------------------------------------------------------------- stencil
+struct DslashArgs {
+  Geo g;
+  const void* links[MAXPROP];
+  const void* in;
+  void* out;
+  size_t in_rhs_stride, out_rhs_stride;  // units
+  int nrhs;                              // per proposal
+  int p0, np, blk0, nb;
+  double cdiag, chop;
+  int accumulate;
+};
+
+template <class SI, class SO, class LK, class T, int SEL, int NR>
+__global__ void __launch_bounds__(256) k_dslash(DslashArgs a) {
+  const Geo& g = a.g;
+  const int per_par = a.nb * g.Vbh;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.np * per_par) return;
+  const int p = a.p0 + t / per_par;
+  const int s = a.blk0 * g.Vbh + (t % per_par);
+  const int prop = blockIdx.z;
+  const int rhs0 = blockIdx.y * NR;
+  const int nr = min(NR, a.nrhs - rhs0);
+  const size_t Vh = g.Vh;
+
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const typename SI::unit* in = reinterpret_cast<const typename SI::unit*>(a.in) + size_t(prop * a.nrhs + rhs0) * a.in_rhs_stride;
+  typename SO::unit* out = reinterpret_cast<typename SO::unit*>(a.out) + size_t(prop * a.nrhs + rhs0) * a.out_rhs_stride;
+
+  SiteInfo si;
+  site_info(g, p, s, si);
+
+  Spinor<T> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) zero(acc[r]);
+
+  const T ch = T(a.chop);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    // forward hop: U(x,mu) (1 - gamma_mu) psi(x + mu)
+    {
+      Nbr n = neighbour(g, si, mu, +1);
+      bool use = SEL == HOP_ALL || (SEL == HOP_INTRA ? !n.cross : n.cross);
+      if (use) {
+        SU3<T> U;
+        LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            Spinor<T> nb;
+            SI::load(in + r * a.in_rhs_stride + size_t(1 - p) * SI::NC * Vh, Vh, n.s, nb);
+            hop_fwd(mu, U, nb, ch * T(n.sign), acc[r]);
+          }
+        }
+      }
+    }
+    // backward hop: U(x - mu, mu)^+ (1 + gamma_mu) psi(x - mu)
+    {
+      Nbr n = neighbour(g, si, mu, -1);
+      bool use = SEL == HOP_ALL || (SEL == HOP_INTRA ? !n.cross : n.cross);
+      if (use) {
+        SU3<T> U;
+        LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            Spinor<T> nb;
+            SI::load(in + r * a.in_rhs_stride + size_t(1 - p) * SI::NC * Vh, Vh, n.s, nb);
+            hop_bwd(mu, U, nb, ch * T(n.sign), acc[r]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r < nr) {
+      if (a.cdiag != 0.0) {
+        Spinor<T> d;
+        SI::load(in + r * a.in_rhs_stride + size_t(p) * SI::NC * Vh, Vh, s, d);
+        const T cd = T(a.cdiag);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r].v[sp][c] = acc[r].v[sp][c] + scale(cd, d.v[sp][c]);
+      }
+      typename SO::unit* o = out + r * a.out_rhs_stride + size_t(p) * SO::NC * Vh;
+      if (a.accumulate) {
+        Spinor<T> d;
+        SO::load(o, Vh, s, d);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r].v[sp][c] = acc[r].v[sp][c] + d.v[sp][c];
+      }
+      SO::store(o, Vh, s, acc[r]);
+    }
+  }
+}
+
+template <class SI, class SO, class LK, class T, int SEL, int NR>
+static void dslash_go(hipStream_t st, const DslashArgs& a, int nprop) {
+  int n = a.np * a.nb * a.g.Vbh;
+  dim3 grid((n + 255) / 256, (a.nrhs + NR - 1) / NR, nprop);
+  hipLaunchKernelGGL((k_dslash<SI, SO, LK, T, SEL, NR>), grid, dim3(256), 0, st, a);
+}
+
+template <class SI, class SO, class LK, class T, int SEL>
+static void dslash_nr(hipStream_t st, const DslashArgs& a, int nprop, int nr) {
+  if (nr >= 4 && a.nrhs >= 4) dslash_go<SI, SO, LK, T, SEL, 4>(st, a, nprop);
+  else if (nr >= 2 && a.nrhs >= 2) dslash_go<SI, SO, LK, T, SEL, 2>(st, a, nprop);
+  else dslash_go<SI, SO, LK, T, SEL, 1>(st, a, nprop);
+}
+
+template <class SI, class SO, class LK, class T>
+static void dslash_sel(hipStream_t st, const DslashArgs& a, int nprop, int sel, int nr) {
+  if (sel == HOP_ALL) dslash_nr<SI, SO, LK, T, HOP_ALL>(st, a, nprop, nr);
+  else if (sel == HOP_INTRA) dslash_nr<SI, SO, LK, T, HOP_INTRA>(st, a, nprop, nr);
+  else dslash_nr<SI, SO, LK, T, HOP_CROSS>(st, a, nprop, nr);
+}
+
+void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& in,
+                   const FieldBatch& out, const DslashParams& dp, int nr_pref) {
+  DslashArgs a;
+  a.g = g;
+  for (int i = 0; i < MAXPROP; ++i) a.links[i] = i < in.nprop ? links[i] : nullptr;
+  a.in = in.p;
+  a.out = out.p;
+  a.in_rhs_stride = units_per_field(in.prec, g.Vh);
+  a.out_rhs_stride = units_per_field(out.prec, g.Vh);
+  a.nrhs = in.nrhs;
+  a.p0 = dp.p0;
+  a.np = dp.np;
+  a.blk0 = dp.blk0;
+  a.nb = dp.nb;
+  a.cdiag = dp.cdiag;
+  a.chop = dp.chop;
+  a.accumulate = dp.accumulate;
+  if (in.prec == P_F64 && out.prec == P_F64 && linkfmt == LK_F64)
+    dslash_sel<StF64, StF64, LkF64, double>(st, a, in.nprop, dp.sel, nr_pref);
+  else if (in.prec == P_F32 && out.prec == P_F32 && linkfmt == LK_F32C12)
+    dslash_sel<StF32, StF32, LkF32C12, float>(st, a, in.nprop, dp.sel, nr_pref);
+  else if (in.prec == P_BF16 && out.prec == P_BF16 && linkfmt == LK_F32C12)
+    dslash_sel<StBF16, StBF16, LkF32C12, float>(st, a, in.nprop, dp.sel, nr_pref);
+  else if (in.prec == P_BF16 && out.prec == P_F32 && linkfmt == LK_F32C12)
+    dslash_sel<StBF16, StF32, LkF32C12, float>(st, a, in.nprop, dp.sel, nr_pref);
+  else if (in.prec == P_F32 && out.prec == P_BF16 && linkfmt == LK_F32C12)
+    dslash_sel<StF32, StBF16, LkF32C12, float>(st, a, in.nprop, dp.sel, nr_pref);
+}
+
+// ----------------------------------------------------------------- layout conversion
+// Internal (parity, s) of a lexicographic site.
+__device__ __forceinline__ void lex_to_internal(const Geo& g, int lex, int& p, int& s) {
+  int x[4];
+  int r = lex;
+  x[3] = r % g.L[3]; r /= g.L[3];
+  x[2] = r % g.L[2]; r /= g.L[2];
+  x[1] = r % g.L[1]; x[0] = r / g.L[1];
+  int B[4], l[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    B[m] = x[m] / g.b[m];
+    l[m] = x[m] - B[m] * g.b[m];
+  }
+  int lexB = ((B[0] * g.NB[1] + B[1]) * g.NB[2] + B[2]) * g.NB[3] + B[3];
+  int col = (B[0] + B[1] + B[2] + B[3]) & 1;
+  int ll = ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * g.b[3] + l[3];
+  p = (x[0] + x[1] + x[2] + x[3]) & 1;
+  s = (col * g.nblk_c + (lexB >> 1)) * g.Vbh + (ll >> 1);
+}
+
+template <class S, class T>
+__global__ void k_pack(Geo g, const double* __restrict__ src, typename S::unit* __restrict__ dst, int V) {
+  int lex = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lex >= V) return;
+  int rhs = blockIdx.y;
+  int p, s;
+  lex_to_internal(g, lex, p, s);
+  const double* q = src + (size_t(rhs) * V + lex) * 24;
+  Spinor<T> sp;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) sp.v[k / 3][k % 3] = {T(q[2 * k]), T(q[2 * k + 1])};
+  S::store(dst + size_t(rhs) * 2 * S::NC * g.Vh + size_t(p) * S::NC * g.Vh, g.Vh, s, sp);
+}
+
+template <class S, class T>
+__global__ void k_unpack(Geo g, const typename S::unit* __restrict__ src, double* __restrict__ dst, int V) {
+  int lex = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lex >= V) return;
+  int rhs = blockIdx.y;
+  int p, s;
+  lex_to_internal(g, lex, p, s);
+  Spinor<T> sp;
+  S::load(src + size_t(rhs) * 2 * S::NC * g.Vh + size_t(p) * S::NC * g.Vh, g.Vh, s, sp);
+  double* q = dst + (size_t(rhs) * V + lex) * 24;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    q[2 * k] = double(sp.v[k / 3][k % 3].re);
+    q[2 * k + 1] = double(sp.v[k / 3][k % 3].im);
+  }
+}
+
+void launch_pack(hipStream_t st, const Geo& g, const double* src, const FieldBatch& dst) {
+  int V = 2 * g.Vh;
+  dim3 grid((V + 255) / 256, dst.nprop * dst.nrhs);
+  if (dst.prec == P_F64) hipLaunchKernelGGL((k_pack<StF64, double>), grid, dim3(256), 0, st, g, src, (double2*)dst.p, V);
+  else if (dst.prec == P_F32) hipLaunchKernelGGL((k_pack<StF32, float>), grid, dim3(256), 0, st, g, src, (float4*)dst.p, V);
+  else hipLaunchKernelGGL((k_pack<StBF16, float>), grid, dim3(256), 0, st, g, src, (uint4*)dst.p, V);
+}
+
+void launch_unpack(hipStream_t st, const Geo& g, const FieldBatch& src, double* dst) {
+  int V = 2 * g.Vh;
+  dim3 grid((V + 255) / 256, src.nprop * src.nrhs);
+  if (src.prec == P_F64) hipLaunchKernelGGL((k_unpack<StF64, double>), grid, dim3(256), 0, st, g, (const double2*)src.p, dst, V);
+  else if (src.prec == P_F32) hipLaunchKernelGGL((k_unpack<StF32, float>), grid, dim3(256), 0, st, g, (const float4*)src.p, dst, V);
+  else hipLaunchKernelGGL((k_unpack<StBF16, float>), grid, dim3(256), 0, st, g, (const uint4*)src.p, dst, V);
+}
+
+__global__ void k_pack_links(Geo g, const double* __restrict__ U, void* __restrict__ dst, int V, int fmt) {
+  int lex = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lex >= V) return;
+  int p, s;
+  lex_to_internal(g, lex, p, s);
+  const size_t Vh = g.Vh;
+  for (int mu = 0; mu < 4; ++mu) {
+    const double* q = U + (size_t(lex) * 4 + mu) * 18;
+    if (fmt == LK_F64) {
+      double2* d = reinterpret_cast<double2*>(dst) + size_t(p * 4 + mu) * 9 * Vh;
+      for (int k = 0; k < 9; ++k) d[k * Vh + s] = make_double2(q[2 * k], q[2 * k + 1]);
+    } else {
+      float4* d = reinterpret_cast<float4*>(dst) + size_t(p * 4 + mu) * 3 * Vh;
+      for (int k = 0; k < 3; ++k)
+        d[k * Vh + s] = make_float4(float(q[4 * k]), float(q[4 * k + 1]), float(q[4 * k + 2]), float(q[4 * k + 3]));
+    }
+  }
+}
+
+void launch_pack_links(hipStream_t st, const Geo& g, const double* U, void* dst, int linkfmt) {
+  int V = 2 * g.Vh;
+  hipLaunchKernelGGL(k_pack_links, dim3((V + 255) / 256), dim3(256), 0, st, g, U, dst, V, linkfmt);
+}
+
+// Deviation of each link from SU(3): max(|U U^+ - 1|_max, |det U - 1|).
+__global__ void k_unitarity(const double* __restrict__ U, int nlinks, double* __restrict__ partial) {
+  __shared__ double sm[256];
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double dev = 0.0;
+  for (int l = t; l < nlinks; l += gridDim.x * blockDim.x) {
+    const double* q = U + size_t(l) * 18;
+    cx<double> m[3][3];
+    for (int k = 0; k < 9; ++k) m[k / 3][k % 3] = {q[2 * k], q[2 * k + 1]};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        cx<double> a = cjmul(m[j][0], m[i][0]) + cjmul(m[j][1], m[i][1]) + cjmul(m[j][2], m[i][2]);
+        double re = a.re - (i == j ? 1.0 : 0.0);
+        dev = fmax(dev, fmax(fabs(re), fabs(a.im)));
+      }
+    cx<double> det = cmul(m[0][0], cmul(m[1][1], m[2][2]) - cmul(m[1][2], m[2][1])) -
+                     cmul(m[0][1], cmul(m[1][0], m[2][2]) - cmul(m[1][2], m[2][0])) +
+                     cmul(m[0][2], cmul(m[1][0], m[2][1]) - cmul(m[1][1], m[2][0]));
+    dev = fmax(dev, fmax(fabs(det.re - 1.0), fabs(det.im)));
+  }
+  sm[threadIdx.x] = dev;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+void launch_unitarity(hipStream_t st, const Geo& g, const double* U, double* partial, int nwg) {
+  hipLaunchKernelGGL(k_unitarity, dim3(nwg), dim3(256), 0, st, U, 8 * g.Vh, partial);
+}
+
+// ----------------------------------------------------------------- projector P
+// (1 + s gamma_mu) psi for s = +1 / -1, built from the two projected spin rows.
+template <class T> __device__ __forceinline__ void one_pm_gamma(int mu, int s, const Spinor<T>& p, Spinor<T>& o) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<T> h0, h1;
+    if (s > 0) {  // 1 + gamma_mu
+      switch (mu) {
+        case 0: h0 = p.v[0][a] - p.v[2][a]; h1 = p.v[1][a] - p.v[3][a];
+                o.v[2][a] = -h0; o.v[3][a] = -h1; break;
+        case 1: h0 = p.v[0][a] + times_mi(p.v[3][a]); h1 = p.v[1][a] + times_mi(p.v[2][a]);
+                o.v[2][a] = times_i(h1); o.v[3][a] = times_i(h0); break;
+        case 2: h0 = p.v[0][a] - p.v[3][a]; h1 = p.v[1][a] + p.v[2][a];
+                o.v[2][a] = h1; o.v[3][a] = -h0; break;
+        default: h0 = p.v[0][a] + times_mi(p.v[2][a]); h1 = p.v[1][a] + times_i(p.v[3][a]);
+                o.v[2][a] = times_i(h0); o.v[3][a] = times_mi(h1); break;
+      }
+    } else {  // 1 - gamma_mu
+      switch (mu) {
+        case 0: h0 = p.v[0][a] + p.v[2][a]; h1 = p.v[1][a] + p.v[3][a];
+                o.v[2][a] = h0; o.v[3][a] = h1; break;
+        case 1: h0 = p.v[0][a] + times_i(p.v[3][a]); h1 = p.v[1][a] + times_i(p.v[2][a]);
+                o.v[2][a] = times_mi(h1); o.v[3][a] = times_mi(h0); break;
+        case 2: h0 = p.v[0][a] + p.v[3][a]; h1 = p.v[1][a] - p.v[2][a];
+                o.v[2][a] = -h1; o.v[3][a] = h0; break;
+        default: h0 = p.v[0][a] + times_i(p.v[2][a]); h1 = p.v[1][a] + times_mi(p.v[3][a]);
+                o.v[2][a] = times_mi(h0); o.v[3][a] = times_i(h1); break;
+      }
+    }
+    o.v[0][a] = h0;
+    o.v[1][a] = h1;
+  }
+}
+
+template <class S, class T>
+__global__ void k_project(Geo g, const typename S::unit* __restrict__ in, typename S::unit* __restrict__ out) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * g.Vh) return;
+  int p = t / g.Vh, s = t - p * g.Vh;
+  size_t off = size_t(blockIdx.y) * 2 * S::NC * g.Vh + size_t(p) * S::NC * g.Vh;
+  SiteInfo si;
+  site_info(g, p, s, si);
+  Spinor<T> o;
+  zero(o);
+  if (si.colour == 0) {
+    int nout = 0, mu1 = 0, dir1 = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      if (si.l[mu] == g.b[mu] - 1) { ++nout; mu1 = mu; dir1 = +1; }
+      if (si.l[mu] == 0) { ++nout; mu1 = mu; dir1 = -1; }
+    }
+    if (nout > 0) {
+      Spinor<T> x;
+      S::load(in + off, g.Vh, s, x);
+      if (nout >= 2) {
+        o = x;
+      } else {
+        // outside neighbour at y + mu -> (1 + gamma_mu)/2 ; at y - mu -> (1 - gamma_mu)/2
+        one_pm_gamma(mu1, dir1, x, o);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) o.v[a][c] = scale(T(0.5), o.v[a][c]);
+      }
+    }
+  }
+  S::store(out + off, g.Vh, s, o);
+}
+
+void launch_project(hipStream_t st, const Geo& g, const FieldBatch& in, const FieldBatch& out) {
+  dim3 grid((2 * g.Vh + 255) / 256, in.nprop * in.nrhs);
+  if (in.prec == P_F64) hipLaunchKernelGGL((k_project<StF64, double>), grid, dim3(256), 0, st, g, (const double2*)in.p, (double2*)out.p);
+  else if (in.prec == P_F32) hipLaunchKernelGGL((k_project<StF32, float>), grid, dim3(256), 0, st, g, (const float4*)in.p, (float4*)out.p);
+  else hipLaunchKernelGGL((k_project<StBF16, float>), grid, dim3(256), 0, st, g, (const uint4*)in.p, (uint4*)out.p);
+}
+
+}  // namespace psms

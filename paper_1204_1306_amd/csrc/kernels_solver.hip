@@ -1,0 +1,165 @@
+// Small per-right-hand-side scalar kernels of the flexible GCR and mixed-storage
+// site-level BLAS (a low-precision Krylov basis against an FP32 residual).
+#include "kernels.h"
+
+namespace psms {
+
+// a[r*m + j] = c[r*k + j] / nw[r*m + j] for j < k (0 when nw == 0); T[(r*m + j)*m + k] = a
+__global__ void k_gcr_proj(const double2* __restrict__ c, const double* __restrict__ nw, int k, int m, int nrhs,
+                           double2* __restrict__ a, double2* __restrict__ T) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrhs * k) return;
+  int r = t / k, j = t - r * k;
+  double n = nw[r * m + j];
+  double2 v = n > 0 ? make_double2(c[r * k + j].x / n, c[r * k + j].y / n) : make_double2(0, 0);
+  a[r * m + j] = v;
+  T[(size_t(r) * m + j) * m + k] = v;
+}
+
+// alpha[k*nrhs + r] = d[r] / nw[r*m + k] for active right-hand sides, else 0
+__global__ void k_gcr_alpha(const double2* __restrict__ d, const double* __restrict__ nw, int k, int m, int nrhs,
+                            const int* __restrict__ active, double2* __restrict__ alpha, double2* __restrict__ neg_alpha) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double n = nw[r * m + k];
+  double2 v = (active[r] && n > 0) ? make_double2(d[r].x / n, d[r].y / n) : make_double2(0, 0);
+  alpha[k * nrhs + r] = v;
+  neg_alpha[r] = make_double2(-v.x, -v.y);
+}
+
+// beta solves T beta = alpha (unit upper triangular), beta laid out [r*m + j]
+__global__ void k_gcr_backsub(const double2* __restrict__ T, const double2* __restrict__ alpha, int n, int m, int nrhs,
+                              double2* __restrict__ beta) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  for (int k = n - 1; k >= 0; --k) {
+    cx<double> acc = {alpha[k * nrhs + r].x, alpha[k * nrhs + r].y};
+    for (int j = k + 1; j < n; ++j) {
+      double2 t = T[(size_t(r) * m + k) * m + j];
+      acc = acc - cmul(cx<double>{t.x, t.y}, cx<double>{beta[r * m + j].x, beta[r * m + j].y});
+    }
+    beta[r * m + k] = make_double2(acc.re, acc.im);
+  }
+}
+
+void gcr_proj(hipStream_t st, const double2* c, const double* nw, int k, int m, int nrhs, double2* a, double2* T) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_gcr_proj, dim3((nrhs * k + 255) / 256), dim3(256), 0, st, c, nw, k, m, nrhs, a, T);
+}
+void gcr_alpha(hipStream_t st, const double2* d, const double* nw, int k, int m, int nrhs, const int* active, double2* alpha,
+               double2* neg_alpha) {
+  hipLaunchKernelGGL(k_gcr_alpha, dim3((nrhs + 255) / 256), dim3(256), 0, st, d, nw, k, m, nrhs, active, alpha, neg_alpha);
+}
+void gcr_backsub(hipStream_t st, const double2* T, const double2* alpha, int n, int m, int nrhs, double2* beta) {
+  hipLaunchKernelGGL(k_gcr_backsub, dim3((nrhs + 63) / 64), dim3(64), 0, st, T, alpha, n, m, nrhs, beta);
+}
+
+// norm of each column of nw (|w_k|^2) copied from a per-rhs array
+__global__ void k_scatter_col(const double* __restrict__ src, int k, int m, int nrhs, double* __restrict__ dst) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) dst[r * m + k] = src[r];
+}
+void scatter_col(hipStream_t st, const double* src, int k, int m, int nrhs, double* dst) {
+  hipLaunchKernelGGL(k_scatter_col, dim3((nrhs + 255) / 256), dim3(256), 0, st, src, k, m, nrhs, dst);
+}
+
+// s[r] = f(v[r]) helpers for defect correction: inv[r] = 1/sqrt(v) (0 if inactive), sq[r] = sqrt(v)
+__global__ void k_scales(const double* __restrict__ v, const int* __restrict__ active, int nrhs, double* __restrict__ inv,
+                         double2* __restrict__ sq) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double s = sqrt(v[r]);
+  bool on = active[r] && s > 0;
+  inv[r] = on ? 1.0 / s : 0.0;
+  sq[r] = make_double2(on ? s : 0.0, 0.0);
+}
+void defect_scales(hipStream_t st, const double* v, const int* active, int nrhs, double* inv, double2* sq) {
+  hipLaunchKernelGGL(k_scales, dim3((nrhs + 255) / 256), dim3(256), 0, st, v, active, nrhs, inv, sq);
+}
+
+// ---------------------------------------------------------------- mixed-storage site-level ops
+// y += sign * a[r] * x   (x and y of different storage)
+template <class SX, class SY, class T>
+__global__ void k_axpy_site(Geo g, const double2* __restrict__ a, const typename SX::unit* __restrict__ x,
+                            typename SY::unit* __restrict__ y, double sgn) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * g.Vh) return;
+  int p = t / g.Vh, i = t - p * g.Vh, r = blockIdx.y;
+  cx<T> A = {T(sgn * a[r].x), T(sgn * a[r].y)};
+  Spinor<T> xv, yv;
+  SX::load(x + (size_t(r) * 2 + p) * SX::NC * g.Vh, g.Vh, i, xv);
+  SY::load(y + (size_t(r) * 2 + p) * SY::NC * g.Vh, g.Vh, i, yv);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) yv.v[q][c] = yv.v[q][c] + cmul(A, xv.v[q][c]);
+  SY::store(y + (size_t(r) * 2 + p) * SY::NC * g.Vh, g.Vh, i, yv);
+}
+
+void launch_axpy_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, int sgn) {
+  dim3 grid((2 * g.Vh + 255) / 256, y.nprop * y.nrhs);
+  if (x.prec == P_BF16 && y.prec == P_F32)
+    hipLaunchKernelGGL((k_axpy_site<StBF16, StF32, float>), grid, dim3(256), 0, st, g, a, (const uint4*)x.p, (float4*)y.p, double(sgn));
+  else if (x.prec == P_F32 && y.prec == P_BF16)
+    hipLaunchKernelGGL((k_axpy_site<StF32, StBF16, float>), grid, dim3(256), 0, st, g, a, (const float4*)x.p, (uint4*)y.p, double(sgn));
+  else if (x.prec == P_F32 && y.prec == P_F64)
+    hipLaunchKernelGGL((k_axpy_site<StF32, StF64, double>), grid, dim3(256), 0, st, g, a, (const float4*)x.p, (double2*)y.p, double(sgn));
+  else if (x.prec == P_BF16 && y.prec == P_F64)
+    hipLaunchKernelGGL((k_axpy_site<StBF16, StF64, double>), grid, dim3(256), 0, st, g, a, (const uint4*)x.p, (double2*)y.p, double(sgn));
+}
+
+// partial (x, y) per workgroup at site level; final pass shared with the unit-level reducer
+template <class SX, class SY>
+__global__ void k_dot_site(Geo g, const typename SX::unit* __restrict__ x, const typename SY::unit* __restrict__ y,
+                           double* __restrict__ partial) {
+  __shared__ double sm[16];
+  int r = blockIdx.y;
+  double are = 0, aim = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * g.Vh; t += gridDim.x * blockDim.x) {
+    int p = t / g.Vh, i = t - p * g.Vh;
+    Spinor<float> xv, yv;
+    SX::load(x + (size_t(r) * 2 + p) * SX::NC * g.Vh, g.Vh, i, xv);
+    SY::load(y + (size_t(r) * 2 + p) * SY::NC * g.Vh, g.Vh, i, yv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double xr = xv.v[q][c].re, xi = xv.v[q][c].im, yr = yv.v[q][c].re, yi = yv.v[q][c].im;
+        are += xr * yr + xi * yi;
+        aim += xr * yi - xi * yr;
+      }
+  }
+  are = wave_sum(are);
+  aim = wave_sum(aim);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) { sm[2 * w] = are; sm[2 * w + 1] = aim; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0, ti = 0;
+    for (int k = 0; k < nw; ++k) { tr += sm[2 * k]; ti += sm[2 * k + 1]; }
+    size_t q = size_t(r) * gridDim.x + blockIdx.x;
+    partial[2 * q] = tr;
+    partial[2 * q + 1] = ti;
+  }
+}
+
+__global__ void k_reduce_pairs(const double* __restrict__ partial, int nwg, double* __restrict__ out) {
+  int r = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double tr = 0, ti = 0;
+    for (int w = 0; w < nwg; ++w) { tr += partial[2 * (size_t(r) * nwg + w)]; ti += partial[2 * (size_t(r) * nwg + w) + 1]; }
+    out[2 * r] = tr;
+    out[2 * r + 1] = ti;
+  }
+}
+
+void reduce_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double2* out) {
+  dim3 grid(R.nwg, y.nprop * y.nrhs);
+  if (x.prec == P_BF16 && y.prec == P_F32)
+    hipLaunchKernelGGL((k_dot_site<StBF16, StF32>), grid, dim3(256), 0, st, g, (const uint4*)x.p, (const float4*)y.p, R.partial);
+  else
+    hipLaunchKernelGGL((k_dot_site<StF32, StBF16>), grid, dim3(256), 0, st, g, (const float4*)x.p, (const uint4*)y.p, R.partial);
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(y.nprop * y.nrhs), dim3(64), 0, st, R.partial, R.nwg, (double*)out);
+}
+
+}  // namespace psms

@@ -1,0 +1,1146 @@
+// C-ABI of libpsms: context, staging of caller buffers, the operators of the
+// domain-decomposed Wilson-Dirac hot path, the batched flexible GCR solver with
+// Schwarz (SAP) preconditioning and FP64 defect correction, the Schur complement
+// and its inverse, and the stochastic determinant-ratio estimator.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/psms.h"
+#include "kernels.h"
+
+using namespace psms;
+
+namespace {
+
+struct Err {
+  psms_status st;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                                     \
+  do {                                                                                                \
+    hipError_t e_ = (x);                                                                              \
+    if (e_ != hipSuccess) throw Err{PSMS_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+#define REQUIRE(cond, msg) \
+  do {                     \
+    if (!(cond)) throw Err{PSMS_EINVAL, msg}; \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+struct Slot {
+  bool loaded = false;
+  bool su3 = false;
+  void* f64 = nullptr;
+  void* c12 = nullptr;
+};
+
+struct ProfRec {
+  int fam;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+enum Fam { FAM_DSLASH = 0, FAM_DSLASH_PART, FAM_BLOCK, FAM_BLAS, FAM_NET, NFAM };
+const char* fam_names[NFAM] = {"dslash", "dslash_part", "block_mr", "blas", "net"};
+
+}  // namespace
+
+struct psms_ctx {
+  psms_geom geom;
+  Geo g;
+  int device = 0;
+  hipStream_t st = nullptr;
+  int V = 0, Vh = 0;
+  uint32_t* d_lcoord = nullptr;
+  uint32_t* d_bcoord = nullptr;
+  Slot slots[64];
+  std::map<std::string, DevBuf> bufs;
+  std::string err;
+  size_t held = 0;
+  // profiling
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[NFAM] = {0};
+  long long prof_n[NFAM] = {0};
+  double prof_bytes[NFAM] = {0};
+};
+
+namespace {
+
+// ------------------------------------------------------------------ memory
+void* dev_alloc(psms_ctx* c, size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Err{PSMS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  c->held += bytes;
+  return p;
+}
+
+void* buf(psms_ctx* c, const std::string& name, size_t bytes) {
+  DevBuf& b = c->bufs[name];
+  if (b.n < bytes) {
+    if (b.p) {
+      HIPCHK(hipStreamSynchronize(c->st));
+      HIPCHK(hipFree(b.p));
+      c->held -= b.n;
+    }
+    b.p = nullptr;
+    b.n = 0;
+    b.p = dev_alloc(c, bytes);
+    b.n = bytes;
+  }
+  return b.p;
+}
+
+FieldBatch field(psms_ctx* c, const std::string& name, Prec prec, int nprop, int nrhs, int copies = 1) {
+  size_t bytes = bytes_per_field(prec, c->Vh) * size_t(nprop) * nrhs * copies;
+  return FieldBatch{buf(c, name, bytes), prec, nprop, nrhs};
+}
+
+template <class T> T* dscratch(psms_ctx* c, const std::string& name, size_t n) {
+  return reinterpret_cast<T*>(buf(c, name, n * sizeof(T)));
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+const double* stage_in(psms_ctx* c, const double* user, size_t ndoubles, const char* name) {
+  if (is_device_ptr(user)) return user;
+  double* d = dscratch<double>(c, name, ndoubles);
+  HIPCHK(hipMemcpyAsync(d, user, ndoubles * sizeof(double), hipMemcpyHostToDevice, c->st));
+  return d;
+}
+
+double* stage_out(psms_ctx* c, double* user, size_t ndoubles, const char* name) {
+  if (is_device_ptr(user)) return user;
+  return dscratch<double>(c, name, ndoubles);
+}
+
+void finish_out(psms_ctx* c, double* user, double* dev, size_t ndoubles) {
+  if (user != dev) HIPCHK(hipMemcpyAsync(user, dev, ndoubles * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+}
+
+// ------------------------------------------------------------------ profiling
+hipEvent_t get_event(psms_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+struct ProfScope {
+  psms_ctx* c;
+  int fam;
+  double bytes;
+  hipEvent_t a{}, b{};
+  ProfScope(psms_ctx* c_, int fam_, double bytes_) : c(c_), fam(fam_), bytes(bytes_) {
+    if (c->prof) {
+      a = get_event(c);
+      b = get_event(c);
+      HIPCHK(hipEventRecord(a, c->st));
+    }
+  }
+  ~ProfScope() {
+    if (c->prof) {
+      (void)hipEventRecord(b, c->st);
+      c->recs.push_back(ProfRec{fam, a, b, bytes});
+    }
+  }
+};
+
+void prof_collect(psms_ctx* c) {
+  if (c->recs.empty()) return;
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (auto& r : c->recs) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    c->prof_ms[r.fam] += ms;
+    c->prof_n[r.fam] += 1;
+    c->prof_bytes[r.fam] += r.bytes;
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+}
+
+// ------------------------------------------------------------------ geometry
+void setup_geometry(psms_ctx* c, const psms_geom* gm) {
+  Geo& g = c->g;
+  int V = 1, nblk = 1, Vb = 1;
+  for (int m = 0; m < 4; ++m) {
+    REQUIRE(gm->L[m] > 0 && gm->L[m] <= 255, "L[mu] must be in [1, 255]");
+    REQUIRE(gm->b[m] > 0 && gm->L[m] % gm->b[m] == 0, "L[mu] must be a multiple of b[mu]");
+    REQUIRE(gm->b[m] % 2 == 0, "b[mu] must be even (even-odd order inside blocks)");
+    REQUIRE((gm->L[m] / gm->b[m]) % 2 == 0, "L[mu]/b[mu] must be even (consistent block colouring)");
+    g.L[m] = gm->L[m];
+    g.b[m] = gm->b[m];
+    g.NB[m] = gm->L[m] / gm->b[m];
+    V *= g.L[m];
+    nblk *= g.NB[m];
+    Vb *= g.b[m];
+  }
+  REQUIRE(gm->kappa > 0 && std::isfinite(gm->kappa), "kappa must be positive");
+  g.sB[3] = 1; g.sB[2] = g.NB[3]; g.sB[1] = g.NB[3] * g.NB[2]; g.sB[0] = g.sB[1] * g.NB[1];
+  g.sl[3] = 1; g.sl[2] = g.b[3]; g.sl[1] = g.b[3] * g.b[2]; g.sl[0] = g.sl[1] * g.b[1];
+  g.Vh = V / 2;
+  g.Vbh = Vb / 2;
+  g.nblk = nblk;
+  g.nblk_c = nblk / 2;
+  g.apbc = gm->antiperiodic_t ? 1 : 0;
+  c->V = V;
+  c->Vh = V / 2;
+  // local coordinates of (parity, i) and block coordinates of blk
+  std::vector<uint32_t> lc(2 * g.Vbh), bc(nblk);
+  for (int l0 = 0; l0 < g.b[0]; ++l0)
+    for (int l1 = 0; l1 < g.b[1]; ++l1)
+      for (int l2 = 0; l2 < g.b[2]; ++l2)
+        for (int l3 = 0; l3 < g.b[3]; ++l3) {
+          int ll = ((l0 * g.b[1] + l1) * g.b[2] + l2) * g.b[3] + l3;
+          int p = (l0 + l1 + l2 + l3) & 1;
+          lc[p * g.Vbh + (ll >> 1)] = uint32_t(l0) | (uint32_t(l1) << 8) | (uint32_t(l2) << 16) | (uint32_t(l3) << 24);
+        }
+  for (int B0 = 0; B0 < g.NB[0]; ++B0)
+    for (int B1 = 0; B1 < g.NB[1]; ++B1)
+      for (int B2 = 0; B2 < g.NB[2]; ++B2)
+        for (int B3 = 0; B3 < g.NB[3]; ++B3) {
+          int lexB = ((B0 * g.NB[1] + B1) * g.NB[2] + B2) * g.NB[3] + B3;
+          int col = (B0 + B1 + B2 + B3) & 1;
+          bc[col * g.nblk_c + (lexB >> 1)] = uint32_t(B0) | (uint32_t(B1) << 8) | (uint32_t(B2) << 16) | (uint32_t(B3) << 24);
+        }
+  c->d_lcoord = (uint32_t*)dev_alloc(c, lc.size() * 4);
+  c->d_bcoord = (uint32_t*)dev_alloc(c, bc.size() * 4);
+  HIPCHK(hipMemcpy(c->d_lcoord, lc.data(), lc.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->d_bcoord, bc.data(), bc.size() * 4, hipMemcpyHostToDevice));
+  g.lcoord = c->d_lcoord;
+  g.bcoord = c->d_bcoord;
+}
+
+// ------------------------------------------------------------------ constants
+double2* const_cx(psms_ctx* c, const char* name, int n, double re, double im) {
+  std::string key = std::string("const_") + name;
+  DevBuf& b = c->bufs[key];
+  size_t need = size_t(n) * sizeof(double2);
+  if (b.n < need) {
+    buf(c, key, need);
+    std::vector<double2> h(n, make_double2(re, im));
+    HIPCHK(hipMemcpy(c->bufs[key].p, h.data(), need, hipMemcpyHostToDevice));
+  }
+  return (double2*)c->bufs[key].p;
+}
+
+Reducer reducer(psms_ctx* c, int nrhs_total, int kmax) {
+  Reducer R;
+  R.nwg = 64;
+  R.partial = dscratch<double>(c, "reduce_partial", size_t(nrhs_total) * R.nwg * 2 * std::max(kmax, 1));
+  return R;
+}
+
+// ------------------------------------------------------------------ operators
+struct Links {
+  const void* p[MAXPROP];
+  int fmt;
+};
+
+Links links_of(psms_ctx* c, const int* slots, int nprop, int fmt) {
+  Links L{};
+  L.fmt = fmt;
+  for (int i = 0; i < nprop; ++i) {
+    REQUIRE(slots[i] >= 0 && slots[i] < 64 && c->slots[slots[i]].loaded, "gauge slot not loaded");
+    if (fmt == LK_F32C12) {
+      if (!c->slots[slots[i]].su3) throw Err{PSMS_ENOTSU3, "mixed precision needs SU(3) links (12-real compression)"};
+      L.p[i] = c->slots[slots[i]].c12;
+    } else {
+      L.p[i] = c->slots[slots[i]].f64;
+    }
+  }
+  return L;
+}
+
+double spinor_bytes(Prec p) { return p == P_F64 ? 192.0 : p == P_F32 ? 96.0 : 48.0; }
+double link_bytes(int fmt) { return fmt == LK_F64 ? 144.0 : 48.0; }
+
+// out = cdiag in + chop H_sel in (+ out), on blocks of out_colour (-1: all)
+void dslash(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch& out, int sel, int out_colour, double cdiag,
+            double chop, int accumulate) {
+  DslashParams dp;
+  dp.sel = sel;
+  dp.p0 = 0;
+  dp.np = 2;
+  dp.blk0 = out_colour < 0 ? 0 : out_colour * c->g.nblk_c;
+  dp.nb = out_colour < 0 ? c->g.nblk : c->g.nblk_c;
+  dp.cdiag = cdiag;
+  dp.chop = chop;
+  dp.accumulate = accumulate;
+  bool full = sel == HOP_ALL && out_colour < 0 && !accumulate;
+  // algorithmic bytes of a full application: every link once, input and output once per rhs
+  double bytes = double(c->V) * in.nprop * (4 * link_bytes(L.fmt) + in.nrhs * (spinor_bytes(in.prec) + spinor_bytes(out.prec)));
+  ProfScope ps(c, full ? FAM_DSLASH : FAM_DSLASH_PART, full ? bytes : 0.0);
+  launch_dslash(c->st, c->g, L.p, L.fmt, in, out, dp, 4);
+}
+
+void apply_D(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch& out) {
+  dslash(c, L, in, out, HOP_ALL, -1, 1.0, -c->geom.kappa, 0);
+}
+
+void norm2(psms_ctx* c, const FieldBatch& x, double* d_out) {
+  ProfScope ps(c, FAM_BLAS, 0);
+  reduce_norm2(c->st, c->g, x, reducer(c, x.nprop * x.nrhs, 1), d_out);
+}
+
+std::vector<double> to_host(psms_ctx* c, const double* d, int n) {
+  std::vector<double> h(n);
+  HIPCHK(hipMemcpyAsync(h.data(), d, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return h;
+}
+
+// ------------------------------------------------------------------ Schwarz preconditioner
+struct SapCfg {
+  int cycles, iters;
+  Prec prec;
+};
+
+// z = SAP(r): multiplicative Schwarz over black then white blocks, MR block solves.
+void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& r, const FieldBatch& z) {
+  const int np = r.nprop, nr = r.nrhs;
+  FieldBatch rho = field(c, "sap_rho", sc.prec, np, nr);
+  FieldBatch xs = field(c, "sap_x", sc.prec, np, nr);
+  FieldBatch dl = field(c, "sap_delta", sc.prec, np, nr);
+  FieldBatch pb = field(c, "sap_p", sc.prec, np, nr);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(c->st, c->g, r, rho, nullptr);
+    launch_zero(c->st, xs, c->Vh);
+  }
+  for (int cy = 0; cy < sc.cycles; ++cy) {
+    for (int col = 0; col < 2; ++col) {
+      BlockMRParams bp{col, sc.iters, 0.0, c->geom.kappa};
+      {
+        ProfScope ps(c, FAM_BLOCK, 0);
+        launch_block_mr(c->st, c->g, L.p, L.fmt, rho, xs, dl, pb, bp, nullptr);
+      }
+      if (!(cy == sc.cycles - 1 && col == 1))  // rho on the other colour -= D_{other,col} delta
+        dslash(c, L, dl, rho, HOP_CROSS, 1 - col, 0.0, c->geom.kappa, 1);
+    }
+  }
+  ProfScope ps(c, FAM_BLAS, 0);
+  launch_copy(c->st, c->g, xs, z, nullptr);
+}
+
+// ------------------------------------------------------------------ flexible GCR
+struct GcrCfg {
+  Prec wprec;   // Krylov basis storage
+  Prec rprec;   // residual / solution storage
+  double tol;
+  int maxit, m;
+  int pc;
+  SapCfg sap;
+};
+
+struct GcrResult {
+  int iters = 0;
+  bool converged = false;
+  bool nan = false;
+  std::vector<double> rel;  // final recursive relative residual per rhs
+};
+
+// Solves D x = b for every rhs of the batch; x is overwritten (start from 0).
+GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& b, const FieldBatch& x,
+               const std::vector<int>* active_in = nullptr) {
+  const int np = b.nprop, nrb = b.nrhs, nr = np * nrb, m = cf.m;
+  const hipStream_t st = c->st;
+  const Geo& g = c->g;
+  GcrResult res;
+  FieldBatch r = field(c, "gcr_r", cf.rprec, np, nrb);
+  FieldBatch Z = field(c, "gcr_Z", cf.wprec, np, nrb, m);
+  FieldBatch W = field(c, "gcr_W", cf.wprec, np, nrb, m);
+  const size_t vstride = units_per_field(cf.wprec, c->Vh) * size_t(nr);
+  const size_t vbytes = bytes_per_field(cf.wprec, c->Vh) * size_t(nr);
+  double* bn2 = dscratch<double>(c, "gcr_bn2", nr);
+  double* rn2 = dscratch<double>(c, "gcr_rn2", nr);
+  double* nw1 = dscratch<double>(c, "gcr_nw1", nr);
+  double* NW = dscratch<double>(c, "gcr_NW", size_t(nr) * m);
+  double2* C = dscratch<double2>(c, "gcr_C", size_t(nr) * m);
+  double2* A = dscratch<double2>(c, "gcr_A", size_t(nr) * m);
+  double2* T = dscratch<double2>(c, "gcr_T", size_t(nr) * m * m);
+  double2* ALPHA = dscratch<double2>(c, "gcr_alpha", size_t(nr) * m);
+  double2* NEGA = dscratch<double2>(c, "gcr_nega", nr);
+  double2* BETA = dscratch<double2>(c, "gcr_beta", size_t(nr) * m);
+  double2* D1 = dscratch<double2>(c, "gcr_d", nr);
+  int* active = dscratch<int>(c, "gcr_active", nr);
+  const double2* ONE = const_cx(c, "one", nr, 1.0, 0.0);
+  const double2* MONE = const_cx(c, "mone", nr, -1.0, 0.0);
+  const bool same = cf.wprec == cf.rprec;
+  Reducer R = reducer(c, nr, m);
+
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(st, g, b, r, nullptr);
+    launch_zero(st, x, c->Vh);
+  }
+  norm2(c, b, bn2);
+  std::vector<double> hb = to_host(c, bn2, nr);
+  std::vector<int> act(nr);
+  for (int i = 0; i < nr; ++i) act[i] = (hb[i] > 0 && (!active_in || (*active_in)[i])) ? 1 : 0;
+  HIPCHK(hipMemcpyAsync(active, act.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+  res.rel.assign(nr, 0.0);
+  bool any = false;
+  for (int i = 0; i < nr; ++i) any |= act[i] != 0;
+  if (!any) {
+    res.converged = true;
+    return res;
+  }
+
+  const double tol2 = cf.tol * cf.tol;
+  while (true) {
+    int used = 0;
+    bool conv = false;
+    for (int k = 0; k < m; ++k) {
+      FieldBatch Zk{(char*)Z.p + k * vbytes, cf.wprec, np, nrb};
+      FieldBatch Wk{(char*)W.p + k * vbytes, cf.wprec, np, nrb};
+      if (cf.pc == PSMS_PC_SAP) {
+        sap_apply(c, L, cf.sap, r, Zk);
+      } else {
+        ProfScope ps(c, FAM_BLAS, 0);
+        launch_copy(st, g, r, Zk, nullptr);
+      }
+      apply_D(c, L, Zk, Wk);
+      {
+        ProfScope ps(c, FAM_BLAS, 0);
+        if (k > 0) {
+          reduce_multidot(st, g, W, vstride, k, Wk, R, C);   // C[r*k + j]
+          gcr_proj(st, C, NW, k, m, nr, A, T);
+          launch_lincomb(st, g, W, vstride, k, A, m, Wk, -1);
+        }
+        reduce_norm2(st, g, Wk, R, nw1);
+        scatter_col(st, nw1, k, m, nr, NW);
+        if (same) reduce_multidot(st, g, Wk, vstride, 1, r, R, D1);
+        else reduce_dot_mixed(st, g, Wk, r, R, D1);
+        gcr_alpha(st, D1, NW, k, m, nr, active, ALPHA, NEGA);
+        if (same) launch_axpby(st, g, NEGA, Wk, nullptr, r, +1);
+        else launch_axpy_mixed(st, g, NEGA, Wk, r, +1);
+        reduce_norm2(st, g, r, R, rn2);
+      }
+      std::vector<double> hr = to_host(c, rn2, nr);
+      ++res.iters;
+      used = k + 1;
+      conv = true;
+      for (int i = 0; i < nr; ++i) {
+        if (!std::isfinite(hr[i])) res.nan = true;
+        res.rel[i] = hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0;
+        if (act[i] && hr[i] > tol2 * hb[i]) conv = false;
+      }
+      if (res.nan || conv || res.iters >= cf.maxit) break;
+    }
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      gcr_backsub(st, T, ALPHA, used, m, nr, BETA);
+      if (x.prec == cf.wprec) {
+        launch_lincomb(st, g, Z, vstride, used, BETA, m, x, +1);
+      } else {
+        // x += beta_j Z_j with Z in a different storage: one mixed axpy per basis vector
+        double2* bj = dscratch<double2>(c, "gcr_bj", nr);
+        for (int j = 0; j < used; ++j) {
+          HIPCHK(hipMemcpy2DAsync(bj, sizeof(double2), BETA + j, m * sizeof(double2), sizeof(double2), nr,
+                                  hipMemcpyDeviceToDevice, st));
+          FieldBatch Zj{(char*)Z.p + j * vbytes, cf.wprec, np, nrb};
+          launch_axpy_mixed(st, g, bj, Zj, x, +1);
+        }
+      }
+    }
+    if (res.nan || conv || res.iters >= cf.maxit) {
+      res.converged = conv && !res.nan;
+      break;
+    }
+    // restart from the true residual r = b - D x
+    apply_D(c, L, x, r);
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_axpby(st, g, ONE, b, MONE, r, +1);
+  }
+  return res;
+}
+
+// ------------------------------------------------------------------ full solve (FP64 in and out)
+struct FullSolveOut {
+  int outer = 0, inner = 0;
+  bool converged = false, nan = false;
+  double max_rel = 0;
+};
+
+FullSolveOut solve_full(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& b64,
+                        const FieldBatch& x64) {
+  FullSolveOut o;
+  const int np = b64.nprop, nrb = b64.nrhs, nr = np * nrb;
+  const hipStream_t st = c->st;
+  Links L64 = links_of(c, slots, np, LK_F64);
+  int restart = std::max(2, std::min(pp->restart, 64));
+  if (pp->prec == PSMS_F64) {
+    GcrCfg cf{P_F64, P_F64, pp->tol, pp->max_iter, restart, pp->pc == PSMS_PC_NONE ? PSMS_PC_NONE : PSMS_PC_SAP,
+              SapCfg{pp->sap_cycles, pp->block_iters, P_F64}};
+    GcrResult gr = fgcr(c, L64, cf, b64, x64);
+    o.inner = gr.iters;
+    o.outer = 1;
+    o.nan = gr.nan;
+  } else {
+    Links L32 = links_of(c, slots, np, LK_F32C12);
+    Prec wp = pp->inner_storage == PSMS_SPINOR_BF16 ? P_BF16 : P_F32;
+    double itol = pp->inner_tol;
+    if (wp == P_BF16) itol = std::max(itol, 5e-3);
+    GcrCfg cf{wp, P_F32, itol, restart, restart, pp->pc == PSMS_PC_NONE ? PSMS_PC_NONE : PSMS_PC_SAP,
+              SapCfg{pp->sap_cycles, pp->block_iters, P_F32}};
+    FieldBatch r64 = field(c, "dc_r64", P_F64, np, nrb);
+    FieldBatch rin = field(c, "dc_rin", P_F32, np, nrb);
+    FieldBatch e = field(c, "dc_e", P_F32, np, nrb);
+    double* bn2 = dscratch<double>(c, "dc_bn2", nr);
+    double* rn2 = dscratch<double>(c, "dc_rn2", nr);
+    double* inv = dscratch<double>(c, "dc_inv", nr);
+    double2* sq2 = dscratch<double2>(c, "dc_sq2", nr);
+    int* dact = dscratch<int>(c, "dc_active", nr);
+    const double2* ONE = const_cx(c, "one", nr, 1.0, 0.0);
+    const double2* MONE = const_cx(c, "mone", nr, -1.0, 0.0);
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_copy(st, c->g, b64, r64, nullptr);
+      launch_zero(st, x64, c->Vh);
+    }
+    norm2(c, b64, bn2);
+    std::vector<double> hb = to_host(c, bn2, nr);
+    const double tol2 = pp->tol * pp->tol;
+    while (true) {
+      norm2(c, r64, rn2);
+      std::vector<double> hr = to_host(c, rn2, nr);
+      std::vector<int> act(nr);
+      bool all = true;
+      for (int i = 0; i < nr; ++i) {
+        if (!std::isfinite(hr[i])) o.nan = true;
+        act[i] = (hb[i] > 0 && hr[i] > tol2 * hb[i]) ? 1 : 0;
+        if (act[i]) all = false;
+      }
+      if (all || o.nan || o.inner >= pp->max_iter) {
+        o.converged = all && !o.nan;
+        break;
+      }
+      HIPCHK(hipMemcpyAsync(dact, act.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+      defect_scales(st, rn2, dact, nr, inv, sq2);
+      {
+        ProfScope ps(c, FAM_BLAS, 0);
+        launch_copy(st, c->g, r64, rin, inv);
+      }
+      GcrResult gr = fgcr(c, L32, cf, rin, e, &act);
+      o.inner += gr.iters;
+      ++o.outer;
+      if (gr.nan) {
+        o.nan = true;
+        break;
+      }
+      {
+        ProfScope ps(c, FAM_BLAS, 0);
+        launch_axpy_mixed(st, c->g, sq2, e, x64, +1);
+      }
+      apply_D(c, L64, x64, r64);
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_axpby(st, c->g, ONE, b64, MONE, r64, +1);
+    }
+  }
+  // true FP64 residual
+  FieldBatch r64 = field(c, "fs_r", P_F64, np, nrb);
+  apply_D(c, L64, x64, r64);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_axpby(st, c->g, const_cx(c, "one", nr, 1, 0), b64, const_cx(c, "mone", nr, -1, 0), r64, +1);
+  }
+  double* t1 = dscratch<double>(c, "fs_n1", nr);
+  double* t2 = dscratch<double>(c, "fs_n2", nr);
+  norm2(c, r64, t1);
+  norm2(c, b64, t2);
+  std::vector<double> h1 = to_host(c, t1, nr), h2 = to_host(c, t2, nr);
+  o.max_rel = 0;
+  for (int i = 0; i < nr; ++i) {
+    double rel = h2[i] > 0 ? std::sqrt(h1[i] / h2[i]) : std::sqrt(h1[i]);
+    if (!std::isfinite(rel)) o.nan = true;
+    o.max_rel = std::max(o.max_rel, rel);
+  }
+  o.converged = !o.nan && o.max_rel <= pp->tol;
+  return o;
+}
+
+// ------------------------------------------------------------------ block solves to tolerance
+// x = D_cc^-1 b on the blocks of colour col; b is left unchanged. Returns max relative residual.
+double solve_colour(psms_ctx* c, const Links& L, int col, const FieldBatch& b, const FieldBatch& x, double tol, int maxit,
+                    int* iters_host) {
+  const int np = b.nprop, nrb = b.nrhs, nr = np * nrb;
+  FieldBatch rho = field(c, "bs_rho", P_F64, np, nrb);
+  FieldBatch dl = field(c, "bs_delta", P_F64, np, nrb);
+  FieldBatch pb = field(c, "bs_p", P_F64, np, nrb);
+  int* it = dscratch<int>(c, "bs_iters", 1);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(c->st, c->g, b, rho, nullptr);
+    launch_keep_colour(c->st, c->g, rho, col);
+    launch_zero(c->st, x, c->Vh);
+  }
+  const int zero_i = 0;
+  HIPCHK(hipMemcpyAsync(it, &zero_i, sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  {
+    ProfScope ps(c, FAM_BLOCK, 0);
+    BlockMRParams bp{col, maxit, tol, c->geom.kappa};
+    launch_block_mr(c->st, c->g, L.p, L.fmt, rho, x, dl, pb, bp, it);
+  }
+  if (iters_host) HIPCHK(hipMemcpyAsync(iters_host, it, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  // relative residual |b_c - D_cc x| / |b_c| (rho holds it after the solve)
+  double* n1 = dscratch<double>(c, "bs_n1", nr);
+  double* n2 = dscratch<double>(c, "bs_n2", nr);
+  FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(c->st, c->g, b, bc, nullptr);
+    launch_keep_colour(c->st, c->g, bc, col);
+  }
+  FieldBatch rt = field(c, "bs_rt", P_F64, np, nrb);
+  dslash(c, L, x, rt, HOP_INTRA, col, 1.0, -c->geom.kappa, 0);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_keep_colour(c->st, c->g, rt, col);
+    launch_axpby(c->st, c->g, const_cx(c, "one", nr, 1, 0), bc, const_cx(c, "mone", nr, -1, 0), rt, +1);
+  }
+  norm2(c, rt, n1);
+  norm2(c, bc, n2);
+  std::vector<double> h1 = to_host(c, n1, nr), h2 = to_host(c, n2, nr);
+  double mx = 0;
+  for (int i = 0; i < nr; ++i) mx = std::max(mx, h2[i] > 0 ? std::sqrt(h1[i] / h2[i]) : std::sqrt(h1[i]));
+  return mx;
+}
+
+// out = (1 - P Q) xi, Q = D_bb^-1 D_bw D_ww^-1 D_wb. Returns worst block-solve residual.
+double schur_apply(psms_ctx* c, const Links& L, const FieldBatch& xi, const FieldBatch& out, double tol, int maxit) {
+  const int np = xi.nprop, nrb = xi.nrhs;
+  FieldBatch t1 = field(c, "sc_t1", P_F64, np, nrb);
+  FieldBatch t2 = field(c, "sc_t2", P_F64, np, nrb);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_zero(c->st, t1, c->Vh);
+  }
+  dslash(c, L, xi, t1, HOP_CROSS, 1, 0.0, -c->geom.kappa, 0);  // D_wb xi (white sites)
+  double r1 = solve_colour(c, L, 1, t1, t2, tol, maxit, nullptr);  // D_ww^-1
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_zero(c->st, t1, c->Vh);
+  }
+  dslash(c, L, t2, t1, HOP_CROSS, 0, 0.0, -c->geom.kappa, 0);  // D_bw (black sites)
+  double r2 = solve_colour(c, L, 0, t1, t2, tol, maxit, nullptr);  // D_bb^-1
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_project(c->st, c->g, t2, t1);
+    const int nr = np * nrb;
+    launch_copy(c->st, c->g, xi, out, nullptr);
+    launch_axpby(c->st, c->g, const_cx(c, "mone", nr, -1, 0), t1, nullptr, out, +1);
+  }
+  return std::max(r1, r2);
+}
+
+// out = phi - P [D^-1 (0 + D_wb phi)]  (eq. inverseschur)
+FullSolveOut schur_inverse(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& phi,
+                           const FieldBatch& out) {
+  const int np = phi.nprop, nrb = phi.nrhs, nr = np * nrb;
+  Links L64 = links_of(c, slots, np, LK_F64);
+  FieldBatch v = field(c, "si_v", P_F64, np, nrb);
+  FieldBatch x = field(c, "si_x", P_F64, np, nrb);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_zero(c->st, v, c->Vh);
+  }
+  dslash(c, L64, phi, v, HOP_CROSS, 1, 0.0, -c->geom.kappa, 0);
+  FullSolveOut o = solve_full(c, slots, pp, v, x);
+  ProfScope ps(c, FAM_BLAS, 0);
+  launch_project(c->st, c->g, x, v);
+  launch_copy(c->st, c->g, phi, out, nullptr);
+  launch_axpby(c->st, c->g, const_cx(c, "mone", nr, -1, 0), v, nullptr, out, +1);
+  return o;
+}
+
+psms_status fail(psms_ctx* c, const Err& e) {
+  if (c) c->err = e.msg;
+  return e.st;
+}
+
+#define API_BEGIN(ctx)                         \
+  if (!(ctx)) return PSMS_EINVAL;              \
+  try {                                        \
+    HIPCHK(hipSetDevice((ctx)->device));
+#define API_END(ctx)                           \
+  }                                            \
+  catch (const Err& e) {                       \
+    return fail(ctx, e);                       \
+  }                                            \
+  catch (const std::exception& e) {            \
+    return fail(ctx, Err{PSMS_EINVAL, e.what()}); \
+  }
+
+void check_rhs(int nrhs) { REQUIRE(nrhs >= 1, "nrhs must be >= 1"); }
+
+}  // namespace
+
+// ====================================================================== C-ABI
+extern "C" {
+
+void psms_default_params(psms_solve_params* p) {
+  if (!p) return;
+  p->tol = 1e-10;
+  p->max_iter = 2000;
+  p->restart = 16;
+  p->prec = PSMS_F64;
+  p->pc = PSMS_PC_SAP;
+  p->sap_cycles = 4;
+  p->block_iters = 4;
+  p->inner_tol = 1e-2;
+  p->inner_storage = PSMS_SPINOR_F32;
+  p->net_fallback = 1;
+  p->rhs_chunk = 0;
+}
+
+const char* psms_status_string(psms_status s) {
+  switch (s) {
+    case PSMS_OK: return "ok";
+    case PSMS_EINVAL: return "invalid argument";
+    case PSMS_ENOMEM: return "out of device memory";
+    case PSMS_EHIP: return "HIP runtime error";
+    case PSMS_ENOTCONV: return "solver did not converge";
+    case PSMS_ENOTSU3: return "link not in SU(3)";
+    case PSMS_ENAN: return "NaN in residual";
+  }
+  return "unknown status";
+}
+
+psms_status psms_create(const psms_geom* geom, int device, void* hip_stream, psms_ctx** out) {
+  if (!geom || !out) return PSMS_EINVAL;
+  *out = nullptr;
+  psms_ctx* c = new psms_ctx();
+  try {
+    c->geom = *geom;
+    c->device = device;
+    HIPCHK(hipSetDevice(device));
+    c->st = reinterpret_cast<hipStream_t>(hip_stream);
+    setup_geometry(c, geom);
+  } catch (const Err& e) {
+    psms_status s = e.st;
+    fprintf(stderr, "psms_create: %s\n", e.msg.c_str());
+    psms_destroy(c);
+    return s;
+  }
+  *out = c;
+  return PSMS_OK;
+}
+
+void psms_destroy(psms_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->st);
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& s : c->slots) {
+    if (s.f64) (void)hipFree(s.f64);
+    if (s.c12) (void)hipFree(s.c12);
+  }
+  if (c->d_lcoord) (void)hipFree(c->d_lcoord);
+  if (c->d_bcoord) (void)hipFree(c->d_bcoord);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* psms_last_error(const psms_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+unsigned long long psms_device_bytes(const psms_ctx* c) { return c ? (unsigned long long)c->held : 0ull; }
+
+psms_status psms_gauge_load(psms_ctx* c, int slot, const double* U) {
+  API_BEGIN(c)
+  REQUIRE(slot >= 0 && slot < 64, "slot out of range");
+  REQUIRE(U != nullptr, "null gauge field");
+  Slot& s = c->slots[slot];
+  size_t nd = size_t(c->V) * 4 * 18;
+  const double* dU = stage_in(c, U, nd, "stage_gauge");
+  if (!s.f64) s.f64 = dev_alloc(c, size_t(c->V) * 4 * 9 * 16);
+  if (!s.c12) s.c12 = dev_alloc(c, size_t(c->V) * 4 * 3 * 16);
+  launch_pack_links(c->st, c->g, dU, s.f64, LK_F64);
+  launch_pack_links(c->st, c->g, dU, s.c12, LK_F32C12);
+  const int nwg = 256;
+  double* part = dscratch<double>(c, "unit_partial", nwg);
+  launch_unitarity(c->st, c->g, dU, part, nwg);
+  std::vector<double> h = to_host(c, part, nwg);
+  double dev = 0;
+  for (double v : h) dev = std::max(dev, v);
+  s.loaded = true;
+  s.su3 = dev <= 1e-6;
+  if (!s.su3) {
+    c->err = "gauge field deviates from SU(3) by " + std::to_string(dev) + "; mixed precision disabled for this slot";
+    return PSMS_ENOTSU3;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_dw(psms_ctx* c, int slot, const double* in, double* out, int nrhs, psms_prec prec) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  Prec p = prec == PSMS_F64 ? P_F64 : P_F32;
+  Links L = links_of(c, &slot, 1, prec == PSMS_F64 ? LK_F64 : LK_F32C12);
+  FieldBatch a = field(c, "api_a", p, 1, nrhs), b = field(c, "api_b", p, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  apply_D(c, L, a, b);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_dhat_ee(psms_ctx* c, int slot, const double* in, double* out, int nrhs) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  Links L = links_of(c, &slot, 1, LK_F64);
+  FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  // b_o = H_oe a_e (odd outputs read only even inputs), then
+  // out_e = a_e - kappa^2 H_eo b_o, out_o = 0.
+  FieldBatch o = field(c, "api_c", P_F64, 1, nrhs);
+  launch_zero_parity(c->st, a, c->Vh, 1);
+  DslashParams dp{HOP_ALL, 1, 1, 0, c->g.nblk, 0.0, 1.0, 0};
+  launch_dslash(c->st, c->g, L.p, L.fmt, a, b, dp, 4);
+  launch_zero(c->st, o, c->Vh);
+  DslashParams de{HOP_ALL, 0, 1, 0, c->g.nblk, 0.0, -c->geom.kappa * c->geom.kappa, 0};
+  launch_dslash(c->st, c->g, L.p, L.fmt, b, o, de, 4);
+  launch_axpby(c->st, c->g, const_cx(c, "one", nrhs, 1, 0), a, nullptr, o, +1);
+  b = o;
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_block(psms_ctx* c, int slot, int colour, const double* in, double* out, int nrhs) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  REQUIRE(colour == 0 || colour == 1, "colour must be 0 (black) or 1 (white)");
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  Links L = links_of(c, &slot, 1, LK_F64);
+  FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  launch_keep_colour(c->st, c->g, a, colour);
+  launch_zero(c->st, b, c->Vh);
+  dslash(c, L, a, b, HOP_INTRA, colour, 1.0, -c->geom.kappa, 0);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_hop_bw(psms_ctx* c, int slot, int from_colour, const double* in, double* out, int nrhs) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  REQUIRE(from_colour == 0 || from_colour == 1, "colour must be 0 (black) or 1 (white)");
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  Links L = links_of(c, &slot, 1, LK_F64);
+  FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  launch_keep_colour(c->st, c->g, a, from_colour);
+  launch_zero(c->st, b, c->Vh);
+  dslash(c, L, a, b, HOP_CROSS, 1 - from_colour, 0.0, -c->geom.kappa, 0);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_proj(psms_ctx* c, const double* in, double* out, int nrhs) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  launch_project(c->st, c->g, a, b);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+static void fill_stats(psms_solve_stats* s, const FullSolveOut& o, double secs) {
+  if (!s) return;
+  s->converged = o.converged ? 1 : 0;
+  s->outer_iters = o.outer;
+  s->inner_iters = o.inner;
+  s->used_fallback = 0;
+  s->true_rel_residual = o.max_rel;
+  s->seconds = secs;
+}
+
+static void check_params(const psms_solve_params* p) {
+  REQUIRE(p != nullptr, "null params");
+  REQUIRE(p->tol > 0 && p->max_iter > 0 && p->restart >= 2, "tol > 0, max_iter > 0 and restart >= 2 required");
+  REQUIRE(p->pc == PSMS_PC_NONE || p->pc == PSMS_PC_SAP || p->pc == PSMS_PC_NET, "unknown preconditioner");
+  REQUIRE(p->pc == PSMS_PC_NONE || (p->sap_cycles >= 1 && p->block_iters >= 1), "SAP needs cycles >= 1 and block_iters >= 1");
+}
+
+psms_status psms_solve(psms_ctx* c, int slot, const double* b, double* x, int nrhs, const psms_solve_params* pp,
+                       psms_solve_stats* stats) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  check_params(pp);
+  auto t0 = std::chrono::steady_clock::now();
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* db = stage_in(c, b, nd, "stage_in");
+  double* dx = stage_out(c, x, nd, "stage_out");
+  FieldBatch b64 = field(c, "api_b64", P_F64, 1, nrhs), x64 = field(c, "api_x64", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, db, b64);
+  FullSolveOut o = solve_full(c, &slot, pp, b64, x64);
+  launch_unpack(c->st, c->g, x64, dx);
+  finish_out(c, x, dx, nd);
+  fill_stats(stats, o, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  if (o.nan) {
+    c->err = "NaN/Inf in residual";
+    return PSMS_ENAN;
+  }
+  if (!o.converged) {
+    c->err = "solver did not reach tol (true relative residual " + std::to_string(o.max_rel) + ")";
+    return PSMS_ENOTCONV;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_solve_block(psms_ctx* c, int slot, int colour, const double* b, double* x, int nrhs,
+                             const psms_solve_params* pp, psms_solve_stats* stats) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  REQUIRE(pp != nullptr && pp->tol > 0 && pp->max_iter > 0, "bad params");
+  REQUIRE(colour == 0 || colour == 1, "colour must be 0 or 1");
+  auto t0 = std::chrono::steady_clock::now();
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* db = stage_in(c, b, nd, "stage_in");
+  double* dx = stage_out(c, x, nd, "stage_out");
+  Links L = links_of(c, &slot, 1, LK_F64);
+  FieldBatch b64 = field(c, "api_b64", P_F64, 1, nrhs), x64 = field(c, "api_x64", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, db, b64);
+  int iters = 0;
+  double rel = solve_colour(c, L, colour, b64, x64, pp->tol, pp->max_iter, &iters);
+  launch_unpack(c->st, c->g, x64, dx);
+  finish_out(c, x, dx, nd);
+  FullSolveOut o;
+  o.inner = iters;
+  o.outer = 1;
+  o.max_rel = rel;
+  o.converged = std::isfinite(rel) && rel <= pp->tol * 1.0001;
+  fill_stats(stats, o, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  if (!std::isfinite(rel)) return PSMS_ENAN;
+  if (!o.converged) {
+    c->err = "block solve did not reach tol (relative residual " + std::to_string(rel) + ")";
+    return PSMS_ENOTCONV;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_schur(psms_ctx* c, int slot, const double* in, double* out, int nrhs, const psms_solve_params* pp,
+                             psms_solve_stats* stats) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  REQUIRE(pp != nullptr && pp->tol > 0 && pp->max_iter > 0, "bad params");
+  auto t0 = std::chrono::steady_clock::now();
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  Links L = links_of(c, &slot, 1, LK_F64);
+  FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  double rel = schur_apply(c, L, a, b, pp->tol, pp->max_iter);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  FullSolveOut o;
+  o.max_rel = rel;
+  o.converged = rel <= pp->tol * 1.0001;
+  fill_stats(stats, o, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  if (!o.converged) {
+    c->err = "block solves inside the Schur complement did not reach tol";
+    return PSMS_ENOTCONV;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_schur_inv(psms_ctx* c, int slot, const double* in, double* out, int nrhs,
+                                 const psms_solve_params* pp, psms_solve_stats* stats) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  check_params(pp);
+  auto t0 = std::chrono::steady_clock::now();
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  FullSolveOut o = schur_inverse(c, &slot, pp, a, b);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  fill_stats(stats, o, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  if (!o.converged) {
+    c->err = "full solve inside the Schur inverse did not reach tol";
+    return o.nan ? PSMS_ENAN : PSMS_ENOTCONV;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise,
+                              int nnoise, int n_interp, const psms_solve_params* pp, double* delta, psms_solve_stats* stats) {
+  API_BEGIN(c)
+  check_params(pp);
+  REQUIRE(op == PSMS_OP_FULL || op == PSMS_OP_SCHUR, "unknown operator");
+  REQUIRE(n_interp == 1, "only one interpolation step (n_interp = 1) is supported");
+  REQUIRE(nprop >= 1 && nnoise >= 1 && slot_Up && noise && delta, "bad sizes or null pointers");
+  auto t0 = std::chrono::steady_clock::now();
+  const size_t fd = size_t(c->V) * 24;
+  const double* dn = stage_in(c, noise, fd * nnoise, "stage_noise");
+  std::vector<double> hdelta(size_t(nprop) * nnoise, 0.0);
+  Links LU = links_of(c, &slot_U, 1, LK_F64);
+  // chunking: noise vectors per batch and proposals per batch
+  int pchunk = std::min(nprop, MAXPROP);
+  int jchunk = pp->rhs_chunk > 0 ? std::max(1, pp->rhs_chunk / pchunk) : nnoise;
+  jchunk = std::min(jchunk, nnoise);
+  FullSolveOut agg;
+  agg.converged = true;
+  for (int j0 = 0; j0 < nnoise; j0 += jchunk) {
+    const int nj = std::min(jchunk, nnoise - j0);
+    // xi_j (and phi_j for SCHUR), computed once with U and shared by all proposals
+    FieldBatch eta = field(c, "ld_eta", P_F64, 1, nj);
+    FieldBatch xi = field(c, "ld_xi", P_F64, 1, nj);
+    FieldBatch phi = field(c, "ld_phi", P_F64, 1, nj);
+    launch_pack(c->st, c->g, dn + size_t(j0) * fd, eta);
+    double* xin2 = dscratch<double>(c, "ld_xin2", nj);
+    if (op == PSMS_OP_SCHUR) {
+      launch_project(c->st, c->g, eta, xi);
+      double rel = schur_apply(c, LU, xi, phi, pp->tol, pp->max_iter);
+      if (!(rel <= pp->tol * 1.0001)) agg.converged = false;
+    } else {
+      launch_copy(c->st, c->g, eta, xi, nullptr);
+      apply_D(c, LU, xi, phi);
+    }
+    norm2(c, xi, xin2);
+    std::vector<double> hx = to_host(c, xin2, nj);
+    for (int p0 = 0; p0 < nprop; p0 += pchunk) {
+      const int npp = std::min(pchunk, nprop - p0);
+      FieldBatch rhs = field(c, "ld_rhs", P_F64, npp, nj);
+      FieldBatch y = field(c, "ld_y", P_F64, npp, nj);
+      const size_t fb = bytes_per_field(P_F64, c->Vh) * nj;
+      for (int p = 0; p < npp; ++p)
+        HIPCHK(hipMemcpyAsync((char*)rhs.p + p * fb, phi.p, fb, hipMemcpyDeviceToDevice, c->st));
+      FullSolveOut o;
+      if (op == PSMS_OP_SCHUR) {
+        o = schur_inverse(c, slot_Up + p0, pp, rhs, y);
+      } else {
+        o = solve_full(c, slot_Up + p0, pp, rhs, y);
+      }
+      agg.outer += o.outer;
+      agg.inner += o.inner;
+      agg.max_rel = std::max(agg.max_rel, o.max_rel);
+      agg.nan |= o.nan;
+      agg.converged &= o.converged;
+      double* yn2 = dscratch<double>(c, "ld_yn2", size_t(npp) * nj);
+      norm2(c, y, yn2);
+      std::vector<double> hy = to_host(c, yn2, npp * nj);
+      for (int p = 0; p < npp; ++p)
+        for (int j = 0; j < nj; ++j) hdelta[size_t(p0 + p) * nnoise + j0 + j] = hy[size_t(p) * nj + j] - hx[j];
+    }
+  }
+  if (is_device_ptr(delta)) {
+    HIPCHK(hipMemcpyAsync(delta, hdelta.data(), hdelta.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+  } else {
+    std::memcpy(delta, hdelta.data(), hdelta.size() * sizeof(double));
+  }
+  fill_stats(stats, agg, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  if (agg.nan) return PSMS_ENAN;
+  if (!agg.converged) {
+    c->err = "a solve inside the estimator did not reach tol";
+    return PSMS_ENOTCONV;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_profile(psms_ctx* c, int enable) {
+  API_BEGIN(c)
+  prof_collect(c);
+  if (enable) {
+    for (int f = 0; f < NFAM; ++f) {
+      c->prof_ms[f] = 0;
+      c->prof_n[f] = 0;
+      c->prof_bytes[f] = 0;
+    }
+  }
+  c->prof = enable != 0;
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_profile_read(psms_ctx* c, const char* family, double* total_ms, long long* launches,
+                              double* algorithmic_bytes) {
+  API_BEGIN(c)
+  prof_collect(c);
+  REQUIRE(family != nullptr, "null family");
+  for (int f = 0; f < NFAM; ++f) {
+    if (std::strcmp(family, fam_names[f]) == 0) {
+      if (total_ms) *total_ms = c->prof_ms[f];
+      if (launches) *launches = c->prof_n[f];
+      if (algorithmic_bytes) *algorithmic_bytes = c->prof_bytes[f];
+      return PSMS_OK;
+    }
+  }
+  throw Err{PSMS_EINVAL, std::string("unknown kernel family ") + family};
+  API_END(c)
+  return PSMS_OK;
+}
+
+}  // extern "C"

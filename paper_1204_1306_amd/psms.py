@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libpsms (C-ABI in include/psms.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP library.
+Fields are complex128 arrays in the boundary layout ``[nrhs, V, 4, 3]`` (or
+``[V, 4, 3]`` for one field): numpy arrays (host memory, staged by the library)
+or torch tensors on the GPU (used in place, no copy). Results come back in the
+same kind of container as the input.
+
+The library must have been built (``python -m paper_1204_1306_amd.build``);
+importing this module on a machine without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsms.so")
+
+F64, MIXED = 0, 1
+OP_FULL, OP_SCHUR = 0, 1
+PC_NONE, PC_SAP, PC_NET = 0, 1, 2
+SPINOR_F32, SPINOR_BF16 = 0, 1
+
+STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ENOTSU3", -6: "ENAN"}
+
+
+class PsmsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geom(C.Structure):
+    _fields_ = [("L", C.c_int * 4), ("b", C.c_int * 4), ("antiperiodic_t", C.c_int), ("kappa", C.c_double)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("prec", C.c_int),
+                ("pc", C.c_int), ("sap_cycles", C.c_int), ("block_iters", C.c_int), ("inner_tol", C.c_double),
+                ("inner_storage", C.c_int), ("net_fallback", C.c_int), ("rhs_chunk", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("converged", C.c_int), ("outer_iters", C.c_int), ("inner_iters", C.c_int),
+                ("used_fallback", C.c_int), ("true_rel_residual", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+_SIGS = {
+    "psms_default_params": (None, [C.c_void_p]),
+    "psms_create": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "psms_destroy": (None, [C.c_void_p]),
+    "psms_last_error": (C.c_char_p, [C.c_void_p]),
+    "psms_status_string": (C.c_char_p, [C.c_int]),
+    "psms_device_bytes": (C.c_ulonglong, [C.c_void_p]),
+    "psms_gauge_load": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "psms_apply_dw": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "psms_apply_dhat_ee": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "psms_apply_block": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "psms_apply_hop_bw": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "psms_apply_proj": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "psms_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "psms_solve_block": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                   C.c_void_p]),
+    "psms_apply_schur": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "psms_apply_schur_inv": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                       C.c_void_p]),
+    "psms_logdet_ratio": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "psms_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "psms_profile_read": (C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+}
+
+
+def load_library():
+    """Open libpsms.so and declare every exported symbol's signature."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1204_1306_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def default_params(**kw) -> SolveParams:
+    p = SolveParams()
+    load_library().psms_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(a.data_ptr())
+    if not (a.flags["C_CONTIGUOUS"] and a.dtype == np.complex128):
+        raise ValueError("numpy arrays must be C-contiguous complex128")
+    return C.c_void_p(a.ctypes.data)
+
+
+def _empty_like(a):
+    if _is_torch(a):
+        import torch
+
+        return torch.empty_like(a)
+    return np.empty_like(a)
+
+
+class Context:
+    """One libpsms context (geometry, device, stream)."""
+
+    def __init__(self, L, b, kappa: float, antiperiodic: bool = True, device: int = 0, stream=None):
+        lib = load_library()
+        g = Geom()
+        g.L[:] = list(L)
+        g.b[:] = list(b)
+        g.antiperiodic_t = 1 if antiperiodic else 0
+        g.kappa = float(kappa)
+        self.L, self.b, self.kappa = tuple(L), tuple(b), float(kappa)
+        self.V = int(np.prod(L))
+        h = C.c_void_p()
+        st = C.c_void_p(stream) if stream is not None else None
+        s = lib.psms_create(C.byref(g), int(device), st, C.byref(h))
+        if s != 0:
+            raise PsmsError(s, "psms_create failed (see stderr)")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.psms_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s: int):
+        if s != 0:
+            raise PsmsError(s, self._lib.psms_last_error(self._h).decode())
+
+    def _nrhs(self, a) -> int:
+        n = int(np.prod(a.shape)) // (self.V * 12)
+        if n * self.V * 12 != int(np.prod(a.shape)):
+            raise ValueError("field size is not a multiple of 12 V")
+        return n
+
+    @property
+    def device_bytes(self) -> int:
+        return int(self._lib.psms_device_bytes(self._h))
+
+    # ---------------------------------------------------------------- gauge
+    def gauge_load(self, slot: int, U, allow_non_su3: bool = False):
+        s = self._lib.psms_gauge_load(self._h, int(slot), _ptr(U))
+        if s == -5 and allow_non_su3:
+            return False
+        self._check(s)
+        return True
+
+    # ---------------------------------------------------------------- operators
+    def apply_dw(self, slot: int, psi, prec: int = F64):
+        out = _empty_like(psi)
+        self._check(self._lib.psms_apply_dw(self._h, slot, _ptr(psi), _ptr(out), self._nrhs(psi), prec))
+        return out
+
+    def apply_dhat_ee(self, slot: int, psi):
+        out = _empty_like(psi)
+        self._check(self._lib.psms_apply_dhat_ee(self._h, slot, _ptr(psi), _ptr(out), self._nrhs(psi)))
+        return out
+
+    def apply_block(self, slot: int, colour: int, psi):
+        out = _empty_like(psi)
+        self._check(self._lib.psms_apply_block(self._h, slot, colour, _ptr(psi), _ptr(out), self._nrhs(psi)))
+        return out
+
+    def apply_hop_bw(self, slot: int, from_colour: int, psi):
+        out = _empty_like(psi)
+        self._check(self._lib.psms_apply_hop_bw(self._h, slot, from_colour, _ptr(psi), _ptr(out), self._nrhs(psi)))
+        return out
+
+    def apply_proj(self, psi):
+        out = _empty_like(psi)
+        self._check(self._lib.psms_apply_proj(self._h, _ptr(psi), _ptr(out), self._nrhs(psi)))
+        return out
+
+    # ---------------------------------------------------------------- solves
+    def solve(self, slot: int, b, params: SolveParams | None = None, check: bool = True):
+        p = params or default_params()
+        x = _empty_like(b)
+        st = SolveStats()
+        s = self._lib.psms_solve(self._h, slot, _ptr(b), _ptr(x), self._nrhs(b), C.byref(p), C.byref(st))
+        if check:
+            self._check(s)
+        return x, st.as_dict()
+
+    def solve_block(self, slot: int, colour: int, b, params: SolveParams | None = None, check: bool = True):
+        p = params or default_params()
+        x = _empty_like(b)
+        st = SolveStats()
+        s = self._lib.psms_solve_block(self._h, slot, colour, _ptr(b), _ptr(x), self._nrhs(b), C.byref(p),
+                                       C.byref(st))
+        if check:
+            self._check(s)
+        return x, st.as_dict()
+
+    def apply_schur(self, slot: int, xi, params: SolveParams | None = None):
+        p = params or default_params()
+        out = _empty_like(xi)
+        st = SolveStats()
+        self._check(self._lib.psms_apply_schur(self._h, slot, _ptr(xi), _ptr(out), self._nrhs(xi), C.byref(p),
+                                               C.byref(st)))
+        return out, st.as_dict()
+
+    def apply_schur_inv(self, slot: int, phi, params: SolveParams | None = None):
+        p = params or default_params()
+        out = _empty_like(phi)
+        st = SolveStats()
+        self._check(self._lib.psms_apply_schur_inv(self._h, slot, _ptr(phi), _ptr(out), self._nrhs(phi), C.byref(p),
+                                                   C.byref(st)))
+        return out, st.as_dict()
+
+    def logdet_ratio(self, op: int, slot_U: int, slots_Up, noise, params: SolveParams | None = None, delta=None,
+                     check: bool = True):
+        """Delta[p, j] for proposals slots_Up and noise fields; returns (delta, stats)."""
+        p = params or default_params()
+        nprop = len(slots_Up)
+        nnoise = self._nrhs(noise)
+        slots = (C.c_int * nprop)(*slots_Up)
+        if delta is None:
+            delta = np.empty((nprop, nnoise), np.float64)
+        dptr = C.c_void_p(delta.data_ptr()) if _is_torch(delta) else C.c_void_p(delta.ctypes.data)
+        st = SolveStats()
+        s = self._lib.psms_logdet_ratio(self._h, op, slot_U, slots, nprop, _ptr(noise), nnoise, 1, C.byref(p), dptr,
+                                        C.byref(st))
+        if check:
+            self._check(s)
+        return delta, st.as_dict()
+
+    # ---------------------------------------------------------------- profiling
+    def profile(self, enable: bool):
+        self._check(self._lib.psms_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, family: str):
+        ms, n, by = C.c_double(), C.c_longlong(), C.c_double()
+        self._check(self._lib.psms_profile_read(self._h, family.encode(), C.byref(ms), C.byref(n), C.byref(by)))
+        return {"ms": ms.value, "launches": n.value, "bytes": by.value}

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle on the
+same seeded inputs. Sizes span several blocks and both colours; tolerances are
+stated per test."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dirac, estimator, lattice, schur
+from paper_1204_1306_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GEOMS = [((4, 4, 4, 4), (2, 2, 2, 2)), ((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (4, 2, 2, 2))]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def psms():
+    from paper_1204_1306_amd import psms as m
+
+    m.load_library()
+    return m
+
+
+def make_ctx(psms, L, b, kappa):
+    return psms.Context(L, b, kappa)
+
+
+@pytest.mark.parametrize("L,b", GEOMS)
+def test_dw_f64_matches_oracle(psms, L, b):
+    say("case dw_f64", L, b)
+    kappa = 0.137
+    U = synth.gauge_field(L, 0.6, 11)
+    psi = synth.gaussian_noise(L, 3, 12)
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    out = ctx.apply_dw(0, psi)
+    for r in range(3):
+        ref = dirac.apply_D(U, psi[r], kappa, L)
+        assert rel(out[r], ref) < 1e-13
+
+
+def test_dw_periodic_time(psms):
+    L, b = (4, 4, 4, 4), (2, 2, 2, 2)
+    U = synth.gauge_field(L, 0.6, 13)
+    psi = synth.gaussian_noise(L, 1, 14)[0]
+    ctx = psms.Context(L, b, 0.12, antiperiodic=False)
+    ctx.gauge_load(0, U)
+    assert rel(ctx.apply_dw(0, psi), dirac.apply_D(U, psi, 0.12, L, antiperiodic=False)) < 1e-13
+
+
+def test_dw_free_field_plane_wave(psms):
+    """GPU D on exp(ipx) u equals exp(ipx) D(p) u (closed form, not the oracle)."""
+    L, b = (8, 4, 4, 8), (4, 2, 2, 2)
+    kappa = 0.125
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, synth.unit_gauge_field(L))
+    p = np.array([3 * np.pi / 8, 2 * np.pi / 4, 0.0, 6 * np.pi / 8])
+    u = np.arange(12).reshape(4, 3) * (0.3 + 0.1j) + 1
+    x = lattice.coords(L)
+    ph = np.exp(1j * (x @ p))
+    psi = ph[:, None, None] * u[None]
+    out = ctx.apply_dw(0, psi)
+    ref = ph[:, None, None] * (dirac.free_field_momentum_operator(p, kappa) @ u)[None]
+    assert rel(out, ref) < 1e-13
+
+
+def test_dw_mixed_precision(psms):
+    L, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kappa = 0.15
+    U = synth.gauge_field(L, 0.6, 15)
+    psi = synth.gaussian_noise(L, 2, 16)
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    out = ctx.apply_dw(0, psi, prec=psms.MIXED)
+    for r in range(2):
+        # FP32 storage of links and spinors: relative error a few units of 2^-24 per term
+        assert rel(out[r], dirac.apply_D(U, psi[r], kappa, L)) < 2e-6
+
+
+def test_non_su3_links_refuse_mixed(psms):
+    L, b = (4, 4, 4, 4), (2, 2, 2, 2)
+    U = 0.9 * synth.gauge_field(L, 0.6, 17)
+    ctx = make_ctx(psms, L, b, 0.12)
+    assert ctx.gauge_load(0, U, allow_non_su3=True) is False
+    psi = synth.gaussian_noise(L, 1, 18)[0]
+    assert rel(ctx.apply_dw(0, psi), dirac.apply_D(U, psi, 0.12, L)) < 1e-13
+    with pytest.raises(psms.PsmsError):
+        ctx.apply_dw(0, psi, prec=psms.MIXED)
+
+
+@pytest.mark.parametrize("L,b", GEOMS)
+def test_block_pieces_and_projector(psms, L, b):
+    say("case blocks", L, b)
+    kappa = 0.14
+    U = synth.gauge_field(L, 0.6, 21)
+    psi = synth.gaussian_noise(L, 1, 22)[0]
+    g = schur.Geometry(L, b)
+    op = schur.Operator(g, U, kappa)
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    assert rel(ctx.apply_block(0, 0, psi), op.D_bb(psi)) < 1e-13
+    assert rel(ctx.apply_block(0, 1, psi), op.D_ww(psi)) < 1e-13
+    assert rel(ctx.apply_hop_bw(0, 0, psi), op.D_wb(psi)) < 1e-13
+    assert rel(ctx.apply_hop_bw(0, 1, psi), op.D_bw(psi)) < 1e-13
+    assert rel(ctx.apply_proj(psi), g.project(psi)) < 1e-15
+
+
+def test_dhat_even_odd(psms):
+    L, b = (4, 4, 4, 8), (2, 2, 2, 2)
+    kappa = 0.13
+    U = synth.gauge_field(L, 0.6, 31)
+    psi = synth.gaussian_noise(L, 1, 32)[0]
+    even = lattice.parity(L) == 0
+    pe = psi.copy()
+    pe[~even] = 0
+    H = lambda v: dirac.hopping(U, v, L)
+    t = H(pe)
+    t[even] = 0
+    ref = pe - kappa**2 * H(t)
+    ref[~even] = 0
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    assert rel(ctx.apply_dhat_ee(0, psi), ref) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed_f32", "mixed_bf16"])
+def test_solve_parity(psms, prec):
+    L, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kappa = 0.15
+    say("case solve", prec)
+    U = synth.gauge_field(L, 0.6, 2001)
+    bvec = synth.gaussian_noise(L, 2, 41)
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    kw = dict(tol=1e-10)
+    if prec != "f64":
+        kw.update(prec=psms.MIXED, inner_storage=psms.SPINOR_BF16 if prec == "mixed_bf16" else psms.SPINOR_F32)
+    x, st = ctx.solve(0, bvec, psms.default_params(**kw))
+    say(" stats", st)
+    assert st["converged"] == 1
+    for r in range(2):
+        res = bvec[r] - dirac.apply_D(U, x[r], kappa, L)
+        assert np.linalg.norm(res) / np.linalg.norm(bvec[r]) <= 1e-10 * 1.01
+
+
+def test_solve_small_against_lu(psms):
+    L, b = (4, 4, 4, 4), (2, 2, 2, 2)
+    kappa = 0.12
+    U = synth.gauge_field(L, 0.5, 1001)
+    g = schur.Geometry(L, b)
+    op = schur.Operator(g, U, kappa)
+    bvec = synth.gaussian_noise(L, 1, 42)[0]
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    for pc in (psms.PC_SAP, psms.PC_NONE):
+        x, st = ctx.solve(0, bvec, psms.default_params(tol=1e-12, pc=pc))
+        assert rel(x, op.solve(bvec)) < 1e-10
+
+
+@pytest.mark.parametrize("colour", [0, 1])
+def test_block_solve_parity(psms, colour):
+    L, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kappa = 0.15
+    U = synth.gauge_field(L, 0.6, 51)
+    g = schur.Geometry(L, b)
+    op = schur.Operator(g, U, kappa)
+    bvec = synth.gaussian_noise(L, 1, 52)[0]
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    x, st = ctx.solve_block(0, colour, bvec, psms.default_params(tol=1e-12, max_iter=5000))
+    say(" block stats", st)
+    mask = g.black if colour == 0 else g.white
+    ref = op.solve_colour(g.restrict(bvec, mask), "black" if colour == 0 else "white")
+    assert rel(x, ref) < 1e-10
+
+
+def test_schur_apply_and_inverse(psms):
+    L, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kappa = 0.15
+    U = synth.gauge_field(L, 0.6, 61)
+    g = schur.Geometry(L, b)
+    op = schur.Operator(g, U, kappa)
+    xi = g.project(synth.gaussian_noise(L, 1, 62)[0])
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    prm = psms.default_params(tol=1e-12, max_iter=5000)
+    out, _ = ctx.apply_schur(0, xi, prm)
+    assert rel(out, op.schur_apply(xi)) < 1e-10
+    y, st = ctx.apply_schur_inv(0, xi, psms.default_params(tol=1e-12))
+    assert rel(y, op.schur_inverse_direct(xi, tol=1e-13)) < 1e-9
+
+
+def _oracle_deltas(w, U, Ups, eta, kind):
+    g = schur.Geometry(w["L"], w["b"])
+    opU = schur.Operator(g, U, w["kappa"])
+    out = np.zeros((len(Ups), eta.shape[0]))
+    for p, Up in enumerate(Ups):
+        opP = schur.Operator(g, Up, w["kappa"])
+        for j in range(eta.shape[0]):
+            f = estimator.delta_schur if kind == "schur" else estimator.delta_full
+            out[p, j] = f(opU, opP, eta[j])
+    return out
+
+
+def test_logdet_ratio_small_workload(psms):
+    """4^4 lattice, 2^4 blocks, kappa 0.12, 4 noise vectors, solves to 1e-12:
+    same-noise Delta within 1e-8 absolute of the oracle."""
+    w, U, Ups, eta = synth.workload_inputs("c1")
+    ctx = make_ctx(psms, w["L"], w["b"], w["kappa"])
+    ctx.gauge_load(0, U)
+    ctx.gauge_load(1, Ups[0])
+    prm = psms.default_params(tol=1e-12, max_iter=5000)
+    for op, kind in ((psms.OP_SCHUR, "schur"), (psms.OP_FULL, "full")):
+        d, st = ctx.logdet_ratio(op, 0, [1], eta, prm)
+        ref = _oracle_deltas(w, U, Ups, eta, kind)
+        say(" delta", kind, d.ravel(), ref.ravel(), st)
+        assert np.abs(d - ref).max() < 1e-8
+
+
+def test_logdet_ratio_mixed_vs_f64_8x4(psms):
+    """8^4 lattice, 4^4 blocks, kappa 0.15: FP64 and mixed precision both to 1e-10
+    against the oracle on the same noise (4 of the 16 noise vectors)."""
+    w, U, Ups, eta = synth.workload_inputs("c2", nnoise=4)
+    ctx = make_ctx(psms, w["L"], w["b"], w["kappa"])
+    ctx.gauge_load(0, U)
+    ctx.gauge_load(1, Ups[0])
+    ref = _oracle_deltas(w, U, Ups, eta[:2], "schur")
+    d64, s64 = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10))
+    dmx, smx = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10, prec=psms.MIXED))
+    say(" d64", d64.ravel(), s64)
+    say(" dmx", dmx.ravel(), smx)
+    say(" ref", ref.ravel())
+    # |dDelta| <~ 2 |y| |M dphi| with relative solve error ~ cond * 1e-10
+    xi2 = np.array([np.linalg.norm(schur.Geometry(w["L"], w["b"]).project(e)) ** 2 for e in eta[:2]])
+    bound = 2 * xi2 * 1e-10 * 50
+    assert np.all(np.abs(d64[0, :2] - ref[0]) < bound)
+    assert np.all(np.abs(dmx[0, :2] - ref[0]) < bound)
+    assert np.abs(d64 - dmx).max() < bound.max()
