@@ -1,0 +1,273 @@
+"""Benchmark of the stochastic determinant-ratio estimator on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+for every proposal U'_p and Gaussian noise vector eta_j of the workload,
+Delta_pj = |M xi_j|^2 - |xi_j|^2 with M the Schur-complement ratio operator
+(projector, block solves with U, inter-block hops, one full-lattice solve with
+U' per pair, FP64 accumulation). Inputs (gauge fields, noise) are resident in
+HBM before the timed region.
+
+Prints one JSON line. ``value`` is seconds per det-ratio estimate of the fast
+configuration (mixed precision, batched); the plain FP64 Schwarz-GCR time per
+estimate on the same GPU, the D_w bandwidth, the roofline of the dominant
+kernel and the CPU oracle baseline are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D_w GB/s vs HBM peak; s per det-ratio estimate, learned/mixed vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mode_params(psms, mode: str, tol: float):
+    if mode == "plain":
+        return psms.default_params(tol=tol, prec=psms.F64, pc=psms.PC_SAP)
+    if mode == "mixed":
+        return psms.default_params(tol=tol, prec=psms.MIXED, pc=psms.PC_SAP, inner_storage=psms.SPINOR_F32,
+                                   inner_tol=1e-3)
+    if mode == "mixed_bf16":
+        return psms.default_params(tol=tol, prec=psms.MIXED, pc=psms.PC_SAP, inner_storage=psms.SPINOR_BF16,
+                                   inner_tol=1e-2)
+    raise ValueError(mode)
+
+
+def setup(workload: str, nprop=None, nnoise=None):
+    import torch
+
+    from paper_1204_1306_amd import psms, synth
+
+    w, U, Ups, eta = synth.workload_inputs(workload, nprop=nprop, nnoise=nnoise)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = psms.Context(w["L"], w["b"], w["kappa"], stream=stream)
+    dev = torch.device("cuda:0")
+    ctx.gauge_load(0, torch.from_numpy(U).to(dev))
+    for p, Up in enumerate(Ups):
+        ctx.gauge_load(1 + p, torch.from_numpy(Up).to(dev))
+    noise = torch.from_numpy(eta).to(dev)
+    delta = torch.empty((len(Ups), eta.shape[0]), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    return psms, ctx, w, noise, delta, len(Ups)
+
+
+def run_steps(psms, ctx, w, noise, delta, nprop, params, steps, warmup, profile=False):
+    import torch
+
+    slots = list(range(1, 1 + nprop))
+    for _ in range(warmup):
+        ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise, params, delta=delta)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise, params, delta=delta)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fam = {}
+    if profile:
+        for f in ("dslash", "dslash_part", "block_mr", "blas"):
+            fam[f] = ctx.profile_read(f)
+        ctx.profile(False)
+    return dt, stats, fam, delta.cpu().numpy()
+
+
+def dw_bandwidth(psms, L, b, kappa, reps=20, nrhs=1):
+    """Standalone full-lattice D_w launches on device-resident fields (FP64 and mixed)
+    on an L lattice (32^4 by default: its working set exceeds the 256 MB Infinity Cache)."""
+    import torch
+
+    from paper_1204_1306_amd import synth
+
+    dev = torch.device("cuda:0")
+    ctx = psms.Context(L, b, kappa, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.gauge_load(0, torch.from_numpy(synth.gauge_field(L, 0.6, 5001)).to(dev))
+    psi = torch.from_numpy(synth.gaussian_noise(L, nrhs, 7)).to(dev)
+    out = {"lattice": "x".join(map(str, L)), "nrhs": nrhs}
+    for name, prec in (("f64", psms.F64), ("mixed", psms.MIXED)):
+        ctx.apply_dw(0, psi, prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.apply_dw(0, psi, prec)
+        torch.cuda.synchronize()
+        r = ctx.profile_read("dslash")
+        ctx.profile(False)
+        out[name] = {"gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9, "us_per_launch": 1e3 * r["ms"] / r["launches"],
+                     "bytes_per_launch": r["bytes"] / r["launches"]}
+    return out
+
+
+def cpu_baseline(workload: str, budget_s: float = 20.0):
+    """The CPU oracle on a bounded sample of the workload (one estimate, truncated).
+
+    Sample: the oracle's Schur estimator for one (proposal, noise) pair, with the
+    full solve by CG on the normal equations run for a bounded number of
+    iterations; the time is scaled to a full estimate by the number of CG
+    iterations the observed residual decay needs to reach the workload tolerance."""
+    import threading
+
+    from oracle import schur
+    from oracle.solvers import norm2
+    from paper_1204_1306_amd import synth
+
+    w, U, Ups, eta = synth.workload_inputs(workload, nprop=1, nnoise=1)
+    g = schur.Geometry(w["L"], w["b"])
+    opU = schur.Operator(g, U, w["kappa"], direct=False)
+    opP = schur.Operator(g, Ups[0], w["kappa"], direct=False)
+    xi = g.project(eta[0])
+    # block part: dense LU factor + solve of a few blocks of each colour, scaled to all blocks
+    nsample = min(2, g.V // int(np.prod(w["b"])) // 2)
+    t0 = time.perf_counter()
+    for colour, mask in (("black", g.black), ("white", g.white)):
+        for k in np.unique(g.block[mask])[:nsample]:
+            m = g.block == k
+            lu = schur.DenseLU(opU.sub_matrix(m, m).toarray())
+            lu.solve(xi.reshape(-1)[g.dofs(m)])
+    t_blk = (time.perf_counter() - t0) / (2 * nsample)
+    nblk = g.V // int(np.prod(w["b"]))
+    t_schur = t_blk * nblk
+    phi = xi
+    v = opP.D_wb(phi)
+    # CG on the normal equations, bounded by the time budget
+    bn = np.sqrt(norm2(v))
+    x = np.zeros_like(v)
+    r = v.copy()
+    z = opP.Ddag(r)
+    p = z.copy()
+    zz = norm2(z)
+    it = 0
+    hist = []
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s and it < 5000 and (not hist or hist[-1] > w["tol"]):
+        q = opP.D(p)
+        a = zz / norm2(q)
+        x += a * p
+        r -= a * q
+        it += 1
+        hist.append(np.sqrt(norm2(r)) / bn)
+        z = opP.Ddag(r)
+        zn = norm2(z)
+        p = z + (zn / zz) * p
+        zz = zn
+    t_cg = time.perf_counter() - t1
+    per_it = t_cg / max(it, 1)
+    # iterations to reach tol from the average log-decay over the second half of the run
+    h = np.array(hist)
+    k0 = len(h) // 2
+    rate = (np.log(h[-1]) - np.log(h[k0])) / max(len(h) - 1 - k0, 1)
+    need = it if h[-1] <= w["tol"] else it + (np.log(w["tol"]) - np.log(h[-1])) / min(rate, -1e-12)
+    est = t_schur + per_it * need
+    import os as _os
+
+    try:
+        cores = len(_os.sched_getaffinity(0))
+    except Exception:
+        cores = _os.cpu_count()
+    blas_threads = _os.environ.get("OMP_NUM_THREADS", str(cores))
+    return {"value": float(est), "unit": "s/estimate", "cores": int(blas_threads) if blas_threads.isdigit() else cores,
+            "kind": "oracle",
+            "sample": (f"one {workload} Schur estimate: block solves by dense LU per block "
+                       f"({nsample} blocks per colour timed, {t_blk:.2f} s each, x {nblk} blocks = {t_schur:.1f} s), then {it} CG-on-normal-equations iterations of the full solve "
+                       f"({t_cg:.1f} s, residual {h[-1]:.2e}); scaled to {need:.0f} iterations for tol {w['tol']:g} "
+                       f"from the observed residual decay")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--mode", default="mixed")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--nprop", type=int, default=None)
+    ap.add_argument("--nnoise", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--dw-lattice", default="32,32,32,32")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only (WORLD_SIZE > 1).", file=sys.stderr)
+        sys.exit(2)
+
+    psms, ctx, w, noise, delta, nprop = setup(args.workload, args.nprop, args.nnoise)
+    nnoise = noise.shape[0]
+    nest = nprop * nnoise
+    log(f"workload {args.workload}: L={w['L']} b={w['b']} kappa={w['kappa']} {nprop} proposals x {nnoise} noise")
+
+    fast = mode_params(psms, args.mode, w["tol"])
+    dt, stats, fam, d_fast = run_steps(psms, ctx, w, noise, delta, nprop, fast, args.steps, args.warmup, profile=True)
+    ms_per_step = 1e3 * dt / args.steps
+    log(f"{args.mode}: {ms_per_step:.1f} ms/step, stats {stats[-1]}")
+
+    plain = mode_params(psms, "plain", w["tol"])
+    dtp, stp, _, d_plain = run_steps(psms, ctx, w, noise, delta, nprop, plain, args.plain_steps, 0)
+    s_plain = dtp / args.plain_steps / nest
+    log(f"plain f64: {1e3 * dtp / args.plain_steps:.1f} ms/step, stats {stp[-1]}")
+
+    dwL = tuple(int(v) for v in args.dw_lattice.split(","))
+    dw = dw_bandwidth(psms, dwL, tuple(max(2, v // 4) for v in dwL), w["kappa"])
+    log(f"D_w: {dw}")
+
+    # roofline of the dominant kernel family over the timed region
+    dom = max((f for f in fam if fam[f]["launches"] > 0 and fam[f]["bytes"] > 0), key=lambda f: fam[f]["ms"])
+    ach = fam[dom]["bytes"] / (fam[dom]["ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "us_per_launch": round(1e3 * fam[dom]["ms"] / fam[dom]["launches"], 2),
+            "time_share": round(fam[dom]["ms"] / max(sum(f["ms"] for f in fam.values()), 1e-9), 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(args.workload, args.cpu_budget)
+        except Exception as e:  # the baseline is context; report why it is missing
+            cpu = {"value": None, "error": repr(e)}
+
+    value = dt / args.steps / nest
+    line = {
+        "metric": METRIC, "value": value, "unit": "s/estimate", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if args.mode == "mixed" else ("bf16+f32+f64" if "bf16" in args.mode else "f64"),
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {'x'.join(map(str, w['L']))} lattice, {'x'.join(map(str, w['b']))} blocks, "
+                               f"kappa {w['kappa']}, {nprop} proposals x {nnoise} noise, Schur ratio, tol {w['tol']:g}",
+                   "mode": args.mode, "estimates_per_step": nest},
+        "plain_f64_s_per_estimate": s_plain,
+        "speedup_vs_plain_f64": s_plain / value,
+        "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
+        "dw_lattice": dw["lattice"],
+        "dw_gbs": {k: round(v["gbs"], 1) for k, v in dw.items() if isinstance(v, dict)},
+        "dw_us_per_launch": {k: round(v["us_per_launch"], 2) for k, v in dw.items() if isinstance(v, dict)},
+        "dw_frac_of_hbm_peak": {k: round(v["gbs"] / HBM_PEAK_GBS, 4) for k, v in dw.items() if isinstance(v, dict)},
+        "solver": {"fast": stats[-1], "plain": stp[-1]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,21 @@ psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* 
                               int nnoise, int n_interp, const psms_solve_params* params, double* delta,
                               psms_solve_stats* stats);
 
+/* Launch tuning of the context. Keys: "dslash_variant_f64", "dslash_variant_f32",
+ * "dslash_variant_bf16" (full-lattice stencil form, 0..5: one lane or two wave groups
+ * per site, times three register budgets) and "nr_f64", "nr_low" (right-hand sides per
+ * stencil thread: 1, 2 or 4). Unknown keys or values give PSMS_EINVAL. Results do not
+ * depend on the tuning; only speed does. */
+psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);
+psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);
+
+/* Autotuner: times every stencil form and right-hand-side blocking on this context's
+ * geometry with gauge slot `slot` (HIP events, mean of repeated launches) and keeps the
+ * fastest. If cache_path names a JSON-lines file holding an entry for this GPU
+ * architecture and geometry, that entry is used instead and nothing is timed; a fresh
+ * result is appended to the file. cache_path may be NULL. */
+psms_status psms_autotune(psms_ctx* ctx, int slot, const char* cache_path);
+
 /* Kernel timing with HIP events on the context's stream. enable=1 starts recording
  * the launches of the named kernel families ("dslash", "block_mr", "blas", "net"),
  * 0 stops. psms_profile_read gives the total milliseconds, launch count and

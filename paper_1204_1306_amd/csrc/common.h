@@ -175,6 +175,7 @@ struct Geo {
   int apbc;
   const uint32_t* lcoord;  // [2][Vbh] local coords of (parity, i), 8 bits each
   const uint32_t* bcoord;  // [nblk] block coords of blk, 8 bits each
+  const int* border;       // [nblk] blocks in Morton order of their block coordinates
 };
 
 // Everything the stencil needs about one site.

@@ -29,6 +29,8 @@ struct DslashParams {
   int blk0, nb;            // output blocks [blk0, blk0 + nb)
   double cdiag, chop;      // out = cdiag * in(x) + chop * (H_sel in)(x) [+ out if accumulate]
   int accumulate;
+  int variant = 0;         // full-lattice stencil form (HOP_ALL only), see dslash_variant
+  int xcd_map = 1;         // remap workgroups to per-XCD contiguous tile ranges
 };
 
 // out = cdiag * in + chop * H_sel in (+ out), on the selected parities/blocks.

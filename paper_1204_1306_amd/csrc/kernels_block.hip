@@ -165,8 +165,165 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
 }
 
+// LDS-resident variant for blocks of VB sites (one thread per site, VB <= 256).
+// The block's forward links are staged once in LDS (12-real links as float4
+// planes, or FP64 links left in global memory / L2 when LK is LkF64); the
+// residual lives in registers and is exchanged through LDS for the hops. Each
+// MR iteration touches no global memory.
+template <class LK> struct LdsLinks {
+  static constexpr bool on = false;
+};
+template <> struct LdsLinks<LkF32C12> {
+  static constexpr bool on = true;
+};
+
+template <class S, class LK, class T, int VB>
+__global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
+  constexpr bool LL = LdsLinks<LK>::on;
+  __shared__ cx<T> r_lds[12][VB];
+  __shared__ float4 lk_lds[LL ? 4 * 3 : 1][LL ? VB : 1];
+  __shared__ double sm[3][16];
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int blk = a.colour * g.nblk_c + blockIdx.x;
+  const int prop = blockIdx.z;
+  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  using unit = typename S::unit;
+  unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  unit* x = reinterpret_cast<unit*>(a.x) + roff;
+  unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const T mk = T(-a.kappa);
+  const int t = threadIdx.x;
+  const int Vbh = VB / 2;
+  const int p = t < Vbh ? 0 : 1;
+  const int s = blk * Vbh + (t - p * Vbh);
+
+  // neighbour thread of each hop inside the block (-1: leaves the block)
+  int nbt[8];
+  int nbs[8];
+  {
+    SiteInfo si;
+    site_info(g, p, s, si);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        Nbr n = neighbour(g, si, mu, d == 0 ? +1 : -1);
+        nbs[2 * mu + d] = n.s;
+        nbt[2 * mu + d] = n.cross ? -1 : (1 - p) * Vbh + (n.s - blk * Vbh);
+      }
+    }
+  }
+  if constexpr (LL) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) lk_lds[mu * 3 + k][t] = reinterpret_cast<const float4*>(lk)[(size_t(p * 4 + mu) * 3 + k) * Vh + s];
+  }
+  Spinor<T> r, d;
+  S::load(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+  zero(d);
+  double b2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b2 += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+  b2 = wg_sum(b2, sm[0]);
+  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
+
+  int it = 0;
+  if (b2 > 0.0) {
+    for (; it < a.niter; ++it) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) r_lds[k][t] = r.v[k / 3][k % 3];
+      __syncthreads();
+      Spinor<T> pv = r;
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+        for (int dd = 0; dd < 2; ++dd) {
+          const int tn = nbt[2 * mu + dd];
+          if (tn >= 0) {
+            SU3<T> U;
+            const int lt = dd == 0 ? t : tn;  // forward hop: own link; backward: neighbour's
+            if constexpr (LL) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                float4 v = lk_lds[mu * 3 + k][lt];
+                U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
+                U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
+              }
+              cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
+              cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
+              cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
+              U.m[2][0] = {c0.re, -c0.im};
+              U.m[2][1] = {c1.re, -c1.im};
+              U.m[2][2] = {c2.re, -c2.im};
+            } else {
+              const int lp = dd == 0 ? p : 1 - p;
+              const int ls = dd == 0 ? s : nbs[2 * mu + dd];
+              LK::load(lk + size_t(lp * 4 + mu) * LK::NC * Vh, Vh, ls, U);
+            }
+            Spinor<T> nb;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = r_lds[k][tn];
+            if (dd == 0) hop_fwd(mu, U, nb, mk, pv);
+            else hop_bwd(mu, U, nb, mk, pv);
+          }
+        }
+      }
+      double prr = 0.0, pri = 0.0, pp = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double ar = pv.v[q][c].re, ai = pv.v[q][c].im, br = r.v[q][c].re, bi = r.v[q][c].im;
+          prr += ar * br + ai * bi;
+          pri += ar * bi - ai * br;
+          pp += ar * ar + ai * ai;
+        }
+      prr = wg_sum(prr, sm[0]);
+      pri = wg_sum(pri, sm[1]);
+      pp = wg_sum(pp, sm[2]);
+      if (!(pp > 0.0)) break;
+      const cx<T> alpha = {T(prr / pp), T(pri / pp)};
+      double rr = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          d.v[q][c] = d.v[q][c] + cmul(alpha, r.v[q][c]);
+          r.v[q][c] = r.v[q][c] - cmul(alpha, pv.v[q][c]);
+          rr += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+        }
+      if (stop2 > 0) {
+        rr = wg_sum(rr, sm[0]);
+        if (rr <= stop2) {
+          ++it;
+          break;
+        }
+      }
+    }
+  }
+  S::store(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+  S::store(dl + size_t(p) * S::NC * Vh, Vh, s, d);
+  Spinor<T> xv;
+  S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
+  S::store(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+  if (a.iters && t == 0) atomicMax(a.iters, it);
+}
+
 template <class S, class LK, class T>
 static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
+  if (2 * a.g.Vbh == 256) {
+    hipLaunchKernelGGL((k_block_mr_lds<S, LK, T, 256>), dim3(a.g.nblk_c, a.nrhs, nprop), dim3(256), 0, st, a);
+    return;
+  }
   dim3 grid(a.g.nblk_c, a.nrhs, nprop);
   int threads = 2 * a.g.Vbh < 256 ? ((2 * a.g.Vbh + 63) / 64) * 64 : 256;
   hipLaunchKernelGGL((k_block_mr<S, LK, T>), grid, dim3(threads), 0, st, a);

@@ -21,16 +21,42 @@ struct DslashArgs {
   int p0, np, blk0, nb;
   double cdiag, chop;
   int accumulate;
+  int xcd_map;  // 1: remap workgroups to per-XCD contiguous tile ranges
 };
 
-template <class SI, class SO, class LK, class T, int SEL, int NR>
-__global__ void __launch_bounds__(256) k_dslash(DslashArgs a) {
+// Workgroup -> site tile. Workgroups are dispatched round-robin over the 8 XCDs,
+// so workgroup w is given tile q = (w % 8) * (nwg / 8) + w / 8: every XCD sweeps a
+// contiguous slab of tiles and keeps its neighbours in its own L2. Inside the
+// sweep the two parities alternate tile by tile and, when all blocks are
+// processed, the blocks follow the host-built schedule g.border (black block bi,
+// then white block bi: neighbours along direction 3), so that the data one tile
+// reads is the data the next one needs.
+__device__ __forceinline__ bool tile_site(const DslashArgs& a, int& p, int& s) {
   const Geo& g = a.g;
-  const int per_par = a.nb * g.Vbh;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.np * per_par) return;
-  const int p = a.p0 + t / per_par;
-  const int s = a.blk0 * g.Vbh + (t % per_par);
+  const int nwg = gridDim.x;
+  const int w = blockIdx.x;
+  const int q = (a.xcd_map && (nwg & 7) == 0) ? (w & 7) * (nwg >> 3) + (w >> 3) : w;
+  const int tpp = (a.nb * g.Vbh + 255) >> 8;  // tiles per parity
+  const int tp = q % a.np;
+  const int tq = q / a.np;
+  if (tq >= tpp) return false;
+  const int o = (tq << 8) + threadIdx.x;
+  if (o >= a.nb * g.Vbh) return false;
+  p = a.p0 + tp;
+  if (a.nb == g.nblk) {
+    const int bp = o / g.Vbh;
+    s = g.border[bp] * g.Vbh + (o - bp * g.Vbh);
+  } else {
+    s = a.blk0 * g.Vbh + o;
+  }
+  return true;
+}
+
+template <class SI, class SO, class LK, class T, int SEL, int NR, int W = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k_dslash(DslashArgs a) {
+  const Geo& g = a.g;
+  int p, s;
+  if (!tile_site(a, p, s)) return;
   const int prop = blockIdx.z;
   const int rhs0 = blockIdx.y * NR;
   const int nr = min(NR, a.nrhs - rhs0);
@@ -43,9 +69,22 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs a) {
   SiteInfo si;
   site_info(g, p, s, si);
 
+  // the diagonal term seeds the accumulator: the site's own spinor is read first,
+  // close in time to the neighbouring tile's reads of the same lines
   Spinor<T> acc[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) zero(acc[r]);
+  for (int r = 0; r < NR; ++r) {
+    if (a.cdiag != 0.0 && r < nr) {
+      SI::load(in + r * a.in_rhs_stride + size_t(p) * SI::NC * Vh, Vh, s, acc[r]);
+      const T cd = T(a.cdiag);
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r].v[sp][c] = scale(cd, acc[r].v[sp][c]);
+    } else {
+      zero(acc[r]);
+    }
+  }
 
   const T ch = T(a.chop);
 #pragma unroll
@@ -88,15 +127,6 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs a) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r < nr) {
-      if (a.cdiag != 0.0) {
-        Spinor<T> d;
-        SI::load(in + r * a.in_rhs_stride + size_t(p) * SI::NC * Vh, Vh, s, d);
-        const T cd = T(a.cdiag);
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[r].v[sp][c] = acc[r].v[sp][c] + scale(cd, d.v[sp][c]);
-      }
       typename SO::unit* o = out + r * a.out_rhs_stride + size_t(p) * SO::NC * Vh;
       if (a.accumulate) {
         Spinor<T> d;
@@ -111,10 +141,128 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs a) {
   }
 }
 
+// Split form of the full-lattice stencil (see k_dslash_split).
+template <class SI, class SO, class LK, class T, int W = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k_dslash_split(DslashArgs a) {
+  // 128 sites per workgroup; waves 0-1 sum the forward hops, waves 2-3 the backward
+  // hops of the same sites (wave-uniform branch), the halves meet in LDS.
+  __shared__ cx<T> part[12][128];
+  const Geo& g = a.g;
+  const int nwg = gridDim.x;
+  const int w = blockIdx.x;
+  const int q = (a.xcd_map && (nwg & 7) == 0) ? (w & 7) * (nwg >> 3) + (w >> 3) : w;
+  const int tpp = (a.nb * g.Vbh + 127) >> 7;
+  const int tp = q % a.np;
+  const int tq = q / a.np;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);  // wave-uniform
+  const int l = threadIdx.x & 127;
+  const int o = (tq << 7) + l;
+  const bool valid = tq < tpp && o < a.nb * g.Vbh;
+  int p = a.p0 + tp, s = 0;
+  if (valid) {
+    if (a.nb == g.nblk) {
+      const int bp = o / g.Vbh;
+      s = g.border[bp] * g.Vbh + (o - bp * g.Vbh);
+    } else {
+      s = a.blk0 * g.Vbh + o;
+    }
+  }
+  const int prop = blockIdx.z;
+  const size_t Vh = g.Vh;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const typename SI::unit* in = reinterpret_cast<const typename SI::unit*>(a.in) + size_t(prop * a.nrhs + blockIdx.y) * a.in_rhs_stride;
+  typename SO::unit* out = reinterpret_cast<typename SO::unit*>(a.out) + size_t(prop * a.nrhs + blockIdx.y) * a.out_rhs_stride;
+  Spinor<T> acc;
+  zero(acc);
+  if (valid) {
+    SiteInfo si;
+    site_info(g, p, s, si);
+    const T ch = T(a.chop);
+    const typename SI::unit* nin = in + size_t(1 - p) * SI::NC * Vh;
+    if (h == 0 && a.cdiag != 0.0) {
+      SI::load(in + size_t(p) * SI::NC * Vh, Vh, s, acc);
+      const T cd = T(a.cdiag);
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc.v[sp][c] = scale(cd, acc.v[sp][c]);
+    }
+    if (h == 0) {
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        Nbr n = neighbour(g, si, mu, +1);
+        SU3<T> U;
+        LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+        Spinor<T> nb;
+        SI::load(nin, Vh, n.s, nb);
+        hop_fwd(mu, U, nb, ch * T(n.sign), acc);
+      }
+    } else {
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        Nbr n = neighbour(g, si, mu, -1);
+        SU3<T> U;
+        LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+        Spinor<T> nb;
+        SI::load(nin, Vh, n.s, nb);
+        hop_bwd(mu, U, nb, ch * T(n.sign), acc);
+      }
+    }
+  }
+  if (h == 1) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part[k][l] = acc.v[k / 3][k % 3];
+  }
+  __syncthreads();
+  if (h == 1 || !valid) return;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = acc.v[k / 3][k % 3] + part[k][l];
+  typename SO::unit* op = out + size_t(p) * SO::NC * Vh;
+  if (a.accumulate) {
+    Spinor<T> d;
+    SO::load(op, Vh, s, d);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.v[sp][c] = acc.v[sp][c] + d.v[sp][c];
+  }
+  SO::store(op, Vh, s, acc);
+}
+
+template <class SI, class SO, class LK, class T, int W>
+static void dslash_split_go(hipStream_t st, const DslashArgs& a, int nprop) {
+  int tiles = a.np * ((a.nb * a.g.Vbh + 127) / 128);
+  dim3 grid(tiles, a.nrhs, nprop);
+  hipLaunchKernelGGL((k_dslash_split<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
+}
+
+template <class SI, class SO, class LK, class T, int W>
+static void dslash_one_go(hipStream_t st, const DslashArgs& a, int nprop) {
+  int tiles = a.np * ((a.nb * a.g.Vbh + 255) / 256);
+  dim3 grid(tiles, a.nrhs, nprop);
+  hipLaunchKernelGGL((k_dslash<SI, SO, LK, T, HOP_ALL, 1, W>), grid, dim3(256), 0, st, a);
+}
+
+// Full-lattice stencil variants (form x register budget), chosen by the autotuner:
+//   0: one lane per site          1: two wave groups per site
+//   2: one lane, >= 4 waves/SIMD  3: split, >= 4 waves/SIMD
+//   4: one lane, >= 6 waves/SIMD  5: split, >= 6 waves/SIMD
+template <class SI, class SO, class LK, class T>
+static void dslash_variant(hipStream_t st, const DslashArgs& a, int nprop, int v) {
+  switch (v) {
+    case 1: dslash_split_go<SI, SO, LK, T, 1>(st, a, nprop); break;
+    case 2: dslash_one_go<SI, SO, LK, T, 4>(st, a, nprop); break;
+    case 3: dslash_split_go<SI, SO, LK, T, 4>(st, a, nprop); break;
+    case 4: dslash_one_go<SI, SO, LK, T, 6>(st, a, nprop); break;
+    case 5: dslash_split_go<SI, SO, LK, T, 6>(st, a, nprop); break;
+    default: dslash_one_go<SI, SO, LK, T, 1>(st, a, nprop); break;
+  }
+}
+
 template <class SI, class SO, class LK, class T, int SEL, int NR>
 static void dslash_go(hipStream_t st, const DslashArgs& a, int nprop) {
-  int n = a.np * a.nb * a.g.Vbh;
-  dim3 grid((n + 255) / 256, (a.nrhs + NR - 1) / NR, nprop);
+  int tiles = a.np * ((a.nb * a.g.Vbh + 255) / 256);
+  dim3 grid(tiles, (a.nrhs + NR - 1) / NR, nprop);
   hipLaunchKernelGGL((k_dslash<SI, SO, LK, T, SEL, NR>), grid, dim3(256), 0, st, a);
 }
 
@@ -149,6 +297,18 @@ void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int l
   a.cdiag = dp.cdiag;
   a.chop = dp.chop;
   a.accumulate = dp.accumulate;
+  a.xcd_map = dp.xcd_map;
+  if (dp.variant > 0 && dp.sel == HOP_ALL && nr_pref <= 1) {
+    if (in.prec == P_F64 && out.prec == P_F64 && linkfmt == LK_F64)
+      dslash_variant<StF64, StF64, LkF64, double>(st, a, in.nprop, dp.variant);
+    else if (in.prec == P_F32 && out.prec == P_F32 && linkfmt == LK_F32C12)
+      dslash_variant<StF32, StF32, LkF32C12, float>(st, a, in.nprop, dp.variant);
+    else if (in.prec == P_BF16 && out.prec == P_BF16 && linkfmt == LK_F32C12)
+      dslash_variant<StBF16, StBF16, LkF32C12, float>(st, a, in.nprop, dp.variant);
+    else
+      dslash_variant<StBF16, StF32, LkF32C12, float>(st, a, in.nprop, dp.variant);
+    return;
+  }
   if (in.prec == P_F64 && out.prec == P_F64 && linkfmt == LK_F64)
     dslash_sel<StF64, StF64, LkF64, double>(st, a, in.nprop, dp.sel, nr_pref);
   else if (in.prec == P_F32 && out.prec == P_F32 && linkfmt == LK_F32C12)

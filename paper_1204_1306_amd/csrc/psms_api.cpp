@@ -67,6 +67,7 @@ struct psms_ctx {
   int V = 0, Vh = 0;
   uint32_t* d_lcoord = nullptr;
   uint32_t* d_bcoord = nullptr;
+  int* d_border = nullptr;
   Slot slots[64];
   std::map<std::string, DevBuf> bufs;
   std::string err;
@@ -78,6 +79,11 @@ struct psms_ctx {
   double prof_ms[NFAM] = {0};
   long long prof_n[NFAM] = {0};
   double prof_bytes[NFAM] = {0};
+  // launch tuning (right-hand sides per stencil thread, by precision)
+  int nr_f64 = 1, nr_low = 2;
+  int variant[3] = {0, 0, 0};  // full-lattice stencil form per spinor storage (F64, F32, BF16)
+  int xcd_map = 1;             // per-XCD contiguous tile ranges for stencil launches
+  std::string tuned_from;      // "", "autotune" or "cache"
 };
 
 namespace {
@@ -241,6 +247,15 @@ void setup_geometry(psms_ctx* c, const psms_geom* gm) {
   HIPCHK(hipMemcpy(c->d_bcoord, bc.data(), bc.size() * 4, hipMemcpyHostToDevice));
   g.lcoord = c->d_lcoord;
   g.bcoord = c->d_bcoord;
+  // schedule of blocks for full-lattice launches: black block bi then white block
+  // bi (neighbours along direction 3), in lexicographic order of bi. (A Morton order
+  // of the block coordinates was measured slower: it scatters the per-block chunks
+  // of every component plane.)
+  std::vector<int> order(nblk);
+  for (int k = 0; k < nblk; ++k) order[k] = (k & 1) * g.nblk_c + (k >> 1);
+  c->d_border = (int*)dev_alloc(c, order.size() * 4);
+  HIPCHK(hipMemcpy(c->d_border, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+  g.border = c->d_border;
 }
 
 // ------------------------------------------------------------------ constants
@@ -299,11 +314,13 @@ void dslash(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch&
   dp.cdiag = cdiag;
   dp.chop = chop;
   dp.accumulate = accumulate;
+  dp.variant = c->variant[in.prec];
+  dp.xcd_map = c->xcd_map;
   bool full = sel == HOP_ALL && out_colour < 0 && !accumulate;
   // algorithmic bytes of a full application: every link once, input and output once per rhs
   double bytes = double(c->V) * in.nprop * (4 * link_bytes(L.fmt) + in.nrhs * (spinor_bytes(in.prec) + spinor_bytes(out.prec)));
   ProfScope ps(c, full ? FAM_DSLASH : FAM_DSLASH_PART, full ? bytes : 0.0);
-  launch_dslash(c->st, c->g, L.p, L.fmt, in, out, dp, 4);
+  launch_dslash(c->st, c->g, L.p, L.fmt, in, out, dp, in.prec == P_F64 ? c->nr_f64 : c->nr_low);
 }
 
 void apply_D(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch& out) {
@@ -328,6 +345,13 @@ struct SapCfg {
   Prec prec;
 };
 
+// Algorithmic bytes of one block-solver launch over the blocks of one colour: the
+// block's links once, rho and x read and written once, delta written once.
+double block_bytes(psms_ctx* c, const Links& L, const FieldBatch& rho) {
+  double sites = double(c->Vh);  // one colour = half the lattice
+  return sites * rho.nprop * (4 * link_bytes(L.fmt) + rho.nrhs * 5 * spinor_bytes(rho.prec));
+}
+
 // z = SAP(r): multiplicative Schwarz over black then white blocks, MR block solves.
 void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& r, const FieldBatch& z) {
   const int np = r.nprop, nr = r.nrhs;
@@ -344,7 +368,7 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
     for (int col = 0; col < 2; ++col) {
       BlockMRParams bp{col, sc.iters, 0.0, c->geom.kappa};
       {
-        ProfScope ps(c, FAM_BLOCK, 0);
+        ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho));
         launch_block_mr(c->st, c->g, L.p, L.fmt, rho, xs, dl, pb, bp, nullptr);
       }
       if (!(cy == sc.cycles - 1 && col == 1))  // rho on the other colour -= D_{other,col} delta
@@ -611,7 +635,7 @@ double solve_colour(psms_ctx* c, const Links& L, int col, const FieldBatch& b, c
   HIPCHK(hipMemcpyAsync(it, &zero_i, sizeof(int), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   {
-    ProfScope ps(c, FAM_BLOCK, 0);
+    ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho));
     BlockMRParams bp{col, maxit, tol, c->geom.kappa};
     launch_block_mr(c->st, c->g, L.p, L.fmt, rho, x, dl, pb, bp, it);
   }
@@ -772,6 +796,7 @@ void psms_destroy(psms_ctx* c) {
   }
   if (c->d_lcoord) (void)hipFree(c->d_lcoord);
   if (c->d_bcoord) (void)hipFree(c->d_bcoord);
+  if (c->d_border) (void)hipFree(c->d_border);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -1105,6 +1130,134 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
   if (!agg.converged) {
     c->err = "a solve inside the estimator did not reach tol";
     return PSMS_ENOTCONV;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+static int* tuning_slot(psms_ctx* c, const char* key) {
+  if (!std::strcmp(key, "dslash_variant_f64")) return &c->variant[P_F64];
+  if (!std::strcmp(key, "dslash_variant_f32")) return &c->variant[P_F32];
+  if (!std::strcmp(key, "dslash_variant_bf16")) return &c->variant[P_BF16];
+  if (!std::strcmp(key, "nr_f64")) return &c->nr_f64;
+  if (!std::strcmp(key, "nr_low")) return &c->nr_low;
+  if (!std::strcmp(key, "xcd_map")) return &c->xcd_map;
+  return nullptr;
+}
+static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
+                                    "xcd_map"};
+
+psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
+  API_BEGIN(c)
+  REQUIRE(key != nullptr, "null key");
+  int* t = tuning_slot(c, key);
+  REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
+  if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 5, "stencil variant must be in [0, 5]");
+  else if (!std::strcmp(key, "xcd_map")) REQUIRE(value == 0 || value == 1, "xcd_map must be 0 or 1");
+  else REQUIRE(value == 1 || value == 2 || value == 4, "right-hand sides per thread must be 1, 2 or 4");
+  *t = value;
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_get_tuning(psms_ctx* c, const char* key, int* value) {
+  API_BEGIN(c)
+  REQUIRE(key != nullptr && value != nullptr, "null argument");
+  int* t = tuning_slot(c, key);
+  REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
+  *value = *t;
+  API_END(c)
+  return PSMS_OK;
+}
+
+static std::string tuning_key(psms_ctx* c) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|L=%dx%dx%dx%d|b=%dx%dx%dx%d", arch.c_str(), c->g.L[0], c->g.L[1], c->g.L[2], c->g.L[3],
+                c->g.b[0], c->g.b[1], c->g.b[2], c->g.b[3]);
+  return buf;
+}
+
+// Mean time of `reps` full-lattice stencil launches with the current tuning.
+static double time_dslash(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch& out, int reps) {
+  for (int i = 0; i < 2; ++i) apply_D(c, L, in, out);
+  hipEvent_t a = get_event(c), b = get_event(c);
+  HIPCHK(hipEventRecord(a, c->st));
+  for (int i = 0; i < reps; ++i) apply_D(c, L, in, out);
+  HIPCHK(hipEventRecord(b, c->st));
+  HIPCHK(hipEventSynchronize(b));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  c->pool.push_back(a);
+  c->pool.push_back(b);
+  return ms / reps;
+}
+
+psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
+  API_BEGIN(c)
+  const std::string key = tuning_key(c);
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[1024];
+      while (std::fgets(line, sizeof line, f)) {
+        if (!std::strstr(line, (std::string("\"key\": \"") + key + "\"").c_str())) continue;
+        for (const char* k : tuning_keys) {
+          const char* q = std::strstr(line, (std::string("\"") + k + "\": ").c_str());
+          if (q) *tuning_slot(c, k) = std::atoi(q + std::strlen(k) + 4);
+        }
+        c->tuned_from = "cache";
+      }
+      std::fclose(f);
+      if (c->tuned_from == "cache") return PSMS_OK;
+    }
+  }
+  REQUIRE(slot >= 0 && slot < 64 && c->slots[slot].loaded, "autotune needs a loaded gauge slot");
+  const bool prof = c->prof;
+  c->prof = false;
+  const int reps = c->V >= (1 << 20) ? 10 : 30;
+  for (int pr = 0; pr < 3; ++pr) {
+    Prec P = Prec(pr);
+    if (P != P_F64 && !c->slots[slot].su3) continue;
+    Links L = links_of(c, &slot, 1, P == P_F64 ? LK_F64 : LK_F32C12);
+    FieldBatch in = field(c, "tune_in", P, 1, 1), out = field(c, "tune_out", P, 1, 1);
+    launch_zero(c->st, in, c->Vh);
+    int best = 0;
+    double tbest = 1e30;
+    for (int v = 0; v <= 5; ++v) {
+      c->variant[pr] = v;
+      double t = time_dslash(c, L, in, out, reps);
+      if (t < tbest) { tbest = t; best = v; }
+    }
+    c->variant[pr] = best;
+  }
+  // right-hand sides per thread for batched launches (8 right-hand sides)
+  for (int pr = 0; pr < 2; ++pr) {
+    Prec P = pr == 0 ? P_F64 : P_F32;
+    if (P != P_F64 && !c->slots[slot].su3) continue;
+    Links L = links_of(c, &slot, 1, P == P_F64 ? LK_F64 : LK_F32C12);
+    FieldBatch in = field(c, "tune_in", P, 1, 8), out = field(c, "tune_out", P, 1, 8);
+    launch_zero(c->st, in, c->Vh);
+    int* nr = pr == 0 ? &c->nr_f64 : &c->nr_low;
+    int best = 1;
+    double tbest = 1e30;
+    for (int cand : {1, 2, 4}) {
+      *nr = cand;
+      double t = time_dslash(c, L, in, out, std::max(3, reps / 4));
+      if (t < tbest) { tbest = t; best = cand; }
+    }
+    *nr = best;
+  }
+  c->prof = prof;
+  c->tuned_from = "autotune";
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "{\"key\": \"%s\"", key.c_str());
+      for (const char* k : tuning_keys) std::fprintf(f, ", \"%s\": %d", k, *tuning_slot(c, k));
+      std::fprintf(f, "}\n");
+      std::fclose(f);
+    }
   }
   API_END(c)
   return PSMS_OK;

@@ -74,6 +74,9 @@ _SIGS = {
                                        C.c_void_p]),
     "psms_logdet_ratio": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "psms_set_tuning": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int]),
+    "psms_get_tuning": (C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p]),
+    "psms_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
     "psms_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "psms_profile_read": (C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
@@ -257,6 +260,24 @@ class Context:
         if check:
             self._check(s)
         return delta, st.as_dict()
+
+    # ---------------------------------------------------------------- tuning
+    TUNING_KEYS = ("dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low", "xcd_map")
+
+    def set_tuning(self, key: str, value: int):
+        self._check(self._lib.psms_set_tuning(self._h, key.encode(), int(value)))
+
+    def get_tuning(self, key: str) -> int:
+        v = C.c_int()
+        self._check(self._lib.psms_get_tuning(self._h, key.encode(), C.byref(v)))
+        return v.value
+
+    def tuning(self) -> dict:
+        return {k: self.get_tuning(k) for k in self.TUNING_KEYS}
+
+    def autotune(self, slot: int = 0, cache_path: str | None = None) -> dict:
+        self._check(self._lib.psms_autotune(self._h, int(slot), cache_path.encode() if cache_path else None))
+        return self.tuning()
 
     # ---------------------------------------------------------------- profiling
     def profile(self, enable: bool):
