@@ -153,6 +153,56 @@ psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* 
                               int nnoise, int n_interp, const psms_solve_params* params, double* delta,
                               psms_solve_stats* stats);
 
+/* ---- Learned preconditioner (not from the paper; wraps its solves) ----------------
+ * A gauge-covariant linear network N with layers
+ *   Psi_c(x) = sum_{t=0..8} sum_c' W[t][c][c'] (T_t Phi_c')(x),
+ * T_0 = 1, T_{1+2mu} Phi(x) = U(x,mu) Phi(x+mu), T_{2+2mu} Phi(x) = U(x-mu,mu)^+ Phi(x-mu)
+ * (with the boundary sign of the Dirac operator), W[t][c][c'] a complex 4x4 spin
+ * matrix. Used as the right preconditioner of flexible GCR (params.pc = PSMS_PC_NET);
+ * the true FP64 residual still decides convergence, so the results stay exact.
+ * Weights: complex, layer by layer, each [9][c_out][c_in][4][4] (row-major spin
+ * matrix), as interleaved (re, im) doubles at the boundary; FP32 on the device.
+ * Links in the network are the 12-real FP32 copies, so the slot must hold SU(3) links. */
+typedef struct {
+  int npairs;            /* residual/correction pairs generated in total */
+  int batch;             /* pairs per optimisation step */
+  int epochs;            /* passes over each generated chunk */
+  int chunk;             /* pairs generated (and held on the GPU) at a time */
+  double lr;             /* Adam learning rate */
+  double solve_tol;      /* relative residual of the solves that produce e = D^-1 r */
+  unsigned long long seed;
+  const char* ckpt_path; /* checkpoint file (weights + Adam state), may be NULL */
+  int ckpt_every;        /* steps between checkpoints (0: only at the end) */
+} psms_train_params;
+
+typedef struct {
+  double first_loss, final_loss; /* mean relative loss |N(r) - e|^2 / |e|^2 of the first and last step */
+  int steps;
+  double seconds_data, seconds_train;
+} psms_train_stats;
+
+/* Creates a network with channels[0..nlayers] (channels[0] = channels[nlayers] = 1,
+ * every entry <= 8): weights N(0, scale^2 / (36 c_in)) plus the identity on the
+ * channel-0, t = 0 path, so that the untrained network is close to N(r) = r. */
+psms_status psms_net_init(psms_ctx* ctx, const int* channels, int nlayers, unsigned long long seed, double scale);
+long long psms_net_num_weights(const psms_ctx* ctx); /* complex weights, 0 without a network */
+psms_status psms_net_set_weights(psms_ctx* ctx, const double* w, long long n);
+psms_status psms_net_get_weights(psms_ctx* ctx, double* w, long long n);
+/* out = N(in) with the links of `slot`. */
+psms_status psms_net_apply(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs);
+/* loss = sum_b |N(r_b) - e_b|^2 / |e_b|^2 and grad = dloss / dconj(W) (Wirtinger
+ * convention, same layout as the weights); grad may be NULL. */
+psms_status psms_net_loss_grad(psms_ctx* ctx, int slot, const double* r, const double* e, int npairs, double* loss,
+                               double* grad);
+void psms_default_train_params(psms_train_params* p);
+/* Trains on pairs (r, e = D^-1 r): r Gaussian (counter-based generator), e from the
+ * mixed-precision Schwarz-GCR solver, cycling over the gauge slots; Adam on the mean
+ * relative loss; all on the GPU. */
+psms_status psms_net_train(psms_ctx* ctx, const int* slots, int nconf, const psms_train_params* params,
+                           psms_train_stats* stats);
+psms_status psms_net_save(psms_ctx* ctx, const char* path);
+psms_status psms_net_load(psms_ctx* ctx, const char* path);
+
 /* Launch tuning of the context. Keys: "dslash_variant_f64", "dslash_variant_f32",
  * "dslash_variant_bf16" (full-lattice stencil form, 0..5: one lane or two wave groups
  * per site, times three register budgets) and "nr_f64", "nr_low" (right-hand sides per

@@ -96,4 +96,23 @@ void defect_scales(hipStream_t st, const double* v, const int* active, int nrhs,
 void launch_axpy_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, int sgn);
 void reduce_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double2* out);
 
+// --- gauge-covariant network
+// one layer (forward, or adjoint with adj = 1) on F32 activations [batch][channel][field]
+void launch_net_layer(hipStream_t st, const Geo& g, const void* links, const void* in, void* out, const float2* W, int cin_f,
+                      int cout_f, int adj, int batch);
+// matrix-core form of the layer: weights packed into bf16 MFMA fragments first
+size_t net_pack_units(int cin_f, int cout_f, int adj);
+void launch_net_pack(hipStream_t st, const float2* W, int cin_f, int cout_f, int adj, uint2* Apack);
+void launch_net_layer_mfma(hipStream_t st, const Geo& g, const void* links, const void* in, void* out, const uint2* Apack,
+                           int cin_f, int cout_f, int adj, int batch);
+// number of float2 partial blocks (each 9*cout*cin*16) the gradient kernel writes
+int net_wgrad_partials(const Geo& g, int batch);
+// grad_out[t][co][ci][s1][s2] = sum_x G_co(x)[s1,.] conj((T_t Phi_ci)(x)[s2,.]), summed over the batch
+void launch_net_wgrad(hipStream_t st, const Geo& g, const void* links, const void* phi, const void* G, int cin, int cout,
+                      int batch, float2* partial, double2* grad_out);
+void launch_adam(hipStream_t st, float* w, const double* grad, float* m, float* v, int n, float lr, float b1, float b2,
+                 float eps, int step);
+// complex Gaussian boundary-layout fields (density exp(-|z|^2)), counter-based
+void launch_gaussian(hipStream_t st, double* out, size_t ncomplex, int nfield, uint64_t seed, uint32_t stream);
+
 }  // namespace psms

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -84,6 +85,21 @@ struct psms_ctx {
   int variant[3] = {0, 0, 0};  // full-lattice stencil form per spinor storage (F64, F32, BF16)
   int xcd_map = 1;             // per-XCD contiguous tile ranges for stencil launches
   std::string tuned_from;      // "", "autotune" or "cache"
+  // learned preconditioner: FP32 master weights, Adam moments, FP64 gradient
+  struct Net {
+    int nlayers = 0;
+    std::vector<int> ch;        // channels, nlayers + 1 entries
+    std::vector<size_t> woff;   // complex offset of each layer's weights
+    size_t nw = 0;              // complex weights in total
+    float* w = nullptr;         // [nw] complex as float pairs
+    float* m = nullptr;
+    float* v = nullptr;
+    double* grad = nullptr;     // [nw] complex as double pairs
+    int adam_step = 0;
+    std::vector<uint2*> pack_f, pack_a;  // bf16 MFMA fragments of each layer (forward, adjoint)
+    bool packed = false;                 // fragments match the FP32 weights
+  } net;
+  int net_mfma = 1;  // channel mixing on the matrix cores (bf16) or on the vector units (FP32)
 };
 
 namespace {
@@ -387,7 +403,11 @@ struct GcrCfg {
   int maxit, m;
   int pc;
   SapCfg sap;
+  const Links* net_links = nullptr;  // 12-real links for the network preconditioner
 };
+
+// z = N(r): the learned preconditioner (defined with the network code below)
+void net_precondition(psms_ctx* c, const Links& L12, const FieldBatch& r, const FieldBatch& z);
 
 struct GcrResult {
   int iters = 0;
@@ -452,6 +472,8 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
       FieldBatch Wk{(char*)W.p + k * vbytes, cf.wprec, np, nrb};
       if (cf.pc == PSMS_PC_SAP) {
         sap_apply(c, L, cf.sap, r, Zk);
+      } else if (cf.pc == PSMS_PC_NET) {
+        net_precondition(c, *cf.net_links, r, Zk);
       } else {
         ProfScope ps(c, FAM_BLAS, 0);
         launch_copy(st, g, r, Zk, nullptr);
@@ -515,7 +537,7 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
 // ------------------------------------------------------------------ full solve (FP64 in and out)
 struct FullSolveOut {
   int outer = 0, inner = 0;
-  bool converged = false, nan = false;
+  bool converged = false, nan = false, used_fallback = false;
   double max_rel = 0;
 };
 
@@ -526,20 +548,61 @@ FullSolveOut solve_full(psms_ctx* c, const int* slots, const psms_solve_params* 
   const hipStream_t st = c->st;
   Links L64 = links_of(c, slots, np, LK_F64);
   int restart = std::max(2, std::min(pp->restart, 64));
+  const bool use_net = pp->pc == PSMS_PC_NET;
+  if (use_net) REQUIRE(c->net.nlayers > 0, "PC_NET needs a network (psms_net_init or psms_net_load)");
+  Links L32{};
+  if (pp->prec != PSMS_F64 || use_net) L32 = links_of(c, slots, np, LK_F32C12);
   if (pp->prec == PSMS_F64) {
     GcrCfg cf{P_F64, P_F64, pp->tol, pp->max_iter, restart, pp->pc == PSMS_PC_NONE ? PSMS_PC_NONE : PSMS_PC_SAP,
               SapCfg{pp->sap_cycles, pp->block_iters, P_F64}};
+    if (use_net) {
+      cf.pc = PSMS_PC_NET;
+      cf.net_links = &L32;
+      if (pp->net_fallback) cf.maxit = std::min(pp->max_iter, 8 * restart);
+    }
     GcrResult gr = fgcr(c, L64, cf, b64, x64);
     o.inner = gr.iters;
     o.outer = 1;
     o.nan = gr.nan;
+    if (use_net && pp->net_fallback && !gr.converged && !gr.nan) {
+      // the network stalled: finish with Schwarz-preconditioned GCR on the residual
+      o.used_fallback = true;
+      FieldBatch r64 = field(c, "fb_r64", P_F64, np, nrb);
+      FieldBatch e64 = field(c, "fb_e64", P_F64, np, nrb);
+      apply_D(c, L64, x64, r64);
+      {
+        ProfScope ps(c, FAM_BLAS, 0);
+        launch_axpby(st, c->g, const_cx(c, "one", nr, 1, 0), b64, const_cx(c, "mone", nr, -1, 0), r64, +1);
+      }
+      // relative tolerance of the correction solve: tol |b| / |r|
+      double* n1 = dscratch<double>(c, "fb_n1", nr);
+      double* n2 = dscratch<double>(c, "fb_n2", nr);
+      norm2(c, r64, n1);
+      norm2(c, b64, n2);
+      std::vector<double> h1 = to_host(c, n1, nr), h2 = to_host(c, n2, nr);
+      double ratio = 1.0;
+      for (int i = 0; i < nr; ++i)
+        if (h1[i] > 0) ratio = std::min(ratio, std::sqrt(h2[i] / h1[i]));
+      GcrCfg cs = cf;
+      cs.pc = PSMS_PC_SAP;
+      cs.maxit = std::max(1, pp->max_iter - gr.iters);
+      cs.tol = pp->tol * ratio;
+      GcrResult g2 = fgcr(c, L64, cs, r64, e64);
+      o.inner += g2.iters;
+      o.nan |= g2.nan;
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_axpby(st, c->g, const_cx(c, "one", nr, 1, 0), e64, nullptr, x64, +1);
+    }
   } else {
-    Links L32 = links_of(c, slots, np, LK_F32C12);
     Prec wp = pp->inner_storage == PSMS_SPINOR_BF16 ? P_BF16 : P_F32;
     double itol = pp->inner_tol;
     if (wp == P_BF16) itol = std::max(itol, 5e-3);
     GcrCfg cf{wp, P_F32, itol, restart, restart, pp->pc == PSMS_PC_NONE ? PSMS_PC_NONE : PSMS_PC_SAP,
               SapCfg{pp->sap_cycles, pp->block_iters, P_F32}};
+    if (use_net) {
+      cf.pc = PSMS_PC_NET;
+      cf.net_links = &L32;
+    }
     FieldBatch r64 = field(c, "dc_r64", P_F64, np, nrb);
     FieldBatch rin = field(c, "dc_rin", P_F32, np, nrb);
     FieldBatch e = field(c, "dc_e", P_F32, np, nrb);
@@ -580,6 +643,17 @@ FullSolveOut solve_full(psms_ctx* c, const int* slots, const psms_solve_params* 
       }
       GcrResult gr = fgcr(c, L32, cf, rin, e, &act);
       o.inner += gr.iters;
+      if (cf.pc == PSMS_PC_NET && pp->net_fallback) {
+        // a network-preconditioned inner solve that does not halve the residual
+        // hands the remaining inner solves to the Schwarz preconditioner
+        double worst = 0;
+        for (int i = 0; i < nr; ++i)
+          if (act[i]) worst = std::max(worst, gr.rel[i]);
+        if (!(worst <= 0.5)) {
+          cf.pc = PSMS_PC_SAP;
+          o.used_fallback = true;
+        }
+      }
       ++o.outer;
       if (gr.nan) {
         o.nan = true;
@@ -733,6 +807,161 @@ void check_rhs(int nrhs) { REQUIRE(nrhs >= 1, "nrhs must be >= 1"); }
 
 }  // namespace
 
+// ====================================================================== network host code
+namespace {
+
+size_t net_layer_size(int cin, int cout) { return size_t(9) * cout * cin * 16; }  // complex entries
+
+void net_free(psms_ctx* c) {
+  auto& n = c->net;
+  for (void* p : {(void*)n.w, (void*)n.m, (void*)n.v, (void*)n.grad})
+    if (p) (void)hipFree(p);
+  for (auto* p : n.pack_f) (void)hipFree(p);
+  for (auto* p : n.pack_a) (void)hipFree(p);
+  n = psms_ctx::Net{};
+}
+
+void net_alloc(psms_ctx* c, const std::vector<int>& ch) {
+  REQUIRE(ch.size() >= 2, "a network needs at least one layer");
+  for (int v : ch) REQUIRE(v >= 1 && v <= 8, "channel counts must be in [1, 8]");
+  REQUIRE(ch.front() == 1 && ch.back() == 1, "the preconditioner maps one spinor field to one");
+  HIPCHK(hipStreamSynchronize(c->st));
+  net_free(c);
+  auto& n = c->net;
+  n.nlayers = int(ch.size()) - 1;
+  n.ch = ch;
+  n.nw = 0;
+  for (int l = 0; l < n.nlayers; ++l) {
+    n.woff.push_back(n.nw);
+    n.nw += net_layer_size(ch[l], ch[l + 1]);
+  }
+  n.w = (float*)dev_alloc(c, n.nw * 2 * sizeof(float));
+  n.m = (float*)dev_alloc(c, n.nw * 2 * sizeof(float));
+  n.v = (float*)dev_alloc(c, n.nw * 2 * sizeof(float));
+  n.grad = (double*)dev_alloc(c, n.nw * 2 * sizeof(double));
+  std::vector<float> z(n.nw * 2, 0.f);
+  HIPCHK(hipMemcpy(n.m, z.data(), z.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(n.v, z.data(), z.size() * sizeof(float), hipMemcpyHostToDevice));
+  n.adam_step = 0;
+  for (int l = 0; l < n.nlayers; ++l) {
+    n.pack_f.push_back((uint2*)dev_alloc(c, net_pack_units(ch[l], ch[l + 1], 0) * sizeof(uint2)));
+    n.pack_a.push_back((uint2*)dev_alloc(c, net_pack_units(ch[l], ch[l + 1], 1) * sizeof(uint2)));
+  }
+  n.packed = false;
+}
+
+const float2* net_W(psms_ctx* c, int l) { return reinterpret_cast<const float2*>(c->net.w) + c->net.woff[l]; }
+
+// (re)pack the bf16 MFMA fragments after the FP32 weights changed
+void net_ensure_packed(psms_ctx* c) {
+  auto& n = c->net;
+  if (n.packed || !c->net_mfma) return;
+  for (int l = 0; l < n.nlayers; ++l) {
+    launch_net_pack(c->st, net_W(c, l), n.ch[l], n.ch[l + 1], 0, n.pack_f[l]);
+    launch_net_pack(c->st, net_W(c, l), n.ch[l], n.ch[l + 1], 1, n.pack_a[l]);
+  }
+  n.packed = true;
+}
+
+void net_layer(psms_ctx* c, const void* links12, const void* in, void* out, int l, int adj, int nb) {
+  auto& n = c->net;
+  ProfScope ps(c, FAM_NET, 0);
+  if (c->net_mfma) {
+    net_ensure_packed(c);
+    launch_net_layer_mfma(c->st, c->g, links12, in, out, adj ? n.pack_a[l] : n.pack_f[l], n.ch[l], n.ch[l + 1], adj, nb);
+  } else {
+    launch_net_layer(c->st, c->g, links12, in, out, net_W(c, l), n.ch[l], n.ch[l + 1], adj, nb);
+  }
+}
+
+// Forward pass of a batch of nb F32 fields (one gauge field). acts[l] receive the
+// activations when given (training); otherwise two ping-pong buffers are used.
+void net_forward(psms_ctx* c, const void* links12, const void* in, int nb, void* out, std::vector<void*>* acts) {
+  auto& n = c->net;
+  const size_t fb = bytes_per_field(P_F32, c->Vh);
+  int maxc = 1;
+  for (int v : n.ch) maxc = std::max(maxc, v);
+  const void* cur = in;
+  for (int l = 0; l < n.nlayers; ++l) {
+    void* dst;
+    if (l == n.nlayers - 1) dst = out;
+    else if (acts) dst = (*acts)[l + 1];
+    else dst = buf(c, (l & 1) ? "net_pong" : "net_ping", fb * nb * maxc);
+    net_layer(c, links12, cur, dst, l, 0, nb);
+    cur = dst;
+  }
+}
+
+void net_precondition(psms_ctx* c, const Links& L12, const FieldBatch& r, const FieldBatch& z) {
+  const int nrb = r.nrhs;
+  FieldBatch in = field(c, "net_in", P_F32, 1, nrb), out = field(c, "net_out", P_F32, 1, nrb);
+  for (int p = 0; p < r.nprop; ++p) {
+    FieldBatch rp{(char*)r.p + size_t(p) * nrb * bytes_per_field(r.prec, c->Vh), r.prec, 1, nrb};
+    FieldBatch zp{(char*)z.p + size_t(p) * nrb * bytes_per_field(z.prec, c->Vh), z.prec, 1, nrb};
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_copy(c->st, c->g, rp, in, nullptr);
+    }
+    net_forward(c, L12.p[p], in.p, nrb, out.p, nullptr);
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(c->st, c->g, out, zp, nullptr);
+  }
+}
+
+// One optimisation step (or, with step == false, only loss and gradient) on nb pairs
+// (r, e) held as F32 fields. Loss sum_b |N(r_b) - e_b|^2 / |e_b|^2, divided by nb when
+// mean is set; the gradient dL/dconj(W) lands in c->net.grad.
+double net_loss_grad(psms_ctx* c, const void* links12, const FieldBatch& r, const FieldBatch& e, const double* en2_host,
+                     int nb, bool mean) {
+  auto& n = c->net;
+  const hipStream_t st = c->st;
+  const size_t fb = bytes_per_field(P_F32, c->Vh);
+  std::vector<void*> acts(n.nlayers + 1), grads(n.nlayers + 1);
+  acts[0] = r.p;
+  for (int l = 1; l <= n.nlayers; ++l) {
+    acts[l] = buf(c, "net_act" + std::to_string(l), fb * nb * n.ch[l]);
+    grads[l] = buf(c, "net_grad" + std::to_string(l), fb * nb * n.ch[l]);
+  }
+  net_forward(c, links12, r.p, nb, acts[n.nlayers], &acts);
+  // G_L = (out - e) / (|e|^2 [nb])
+  FieldBatch out{acts[n.nlayers], P_F32, 1, nb};
+  FieldBatch G{grads[n.nlayers], P_F32, 1, nb};
+  double2* s = dscratch<double2>(c, "net_scale", nb);
+  std::vector<double> hs(nb);
+  std::vector<double2> hs2(nb);
+  for (int b = 0; b < nb; ++b) {
+    hs[b] = 1.0 / (en2_host[b] * (mean ? nb : 1));
+    hs2[b] = make_double2(hs[b], 0.0);
+  }
+  HIPCHK(hipMemcpyAsync(s, hs2.data(), nb * sizeof(double2), hipMemcpyHostToDevice, st));
+  double* d2 = dscratch<double>(c, "net_d2", nb);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(st, c->g, out, G, nullptr);
+    launch_axpby(st, c->g, const_cx(c, "mone", nb, -1, 0), e, nullptr, G, +1);
+    reduce_norm2(st, c->g, G, reducer(c, nb, 1), d2);
+    launch_axpby(st, c->g, nullptr, G, s, G, +1);  // G *= s per pair
+  }
+  HIPCHK(hipStreamSynchronize(st));  // hs2 lives on the host stack
+  std::vector<double> hd = to_host(c, d2, nb);
+  double loss = 0;
+  for (int b = 0; b < nb; ++b) loss += hd[b] * hs[b];
+  // backward
+  const int nparts = net_wgrad_partials(c->g, nb);
+  size_t maxent = 0;
+  for (int l = 0; l < n.nlayers; ++l) maxent = std::max(maxent, net_layer_size(n.ch[l], n.ch[l + 1]));
+  float2* partial = dscratch<float2>(c, "net_partial", size_t(nparts) * maxent);
+  for (int l = n.nlayers - 1; l >= 0; --l) {
+    ProfScope ps(c, FAM_NET, 0);
+    launch_net_wgrad(st, c->g, links12, acts[l], grads[l + 1], n.ch[l], n.ch[l + 1], nb, partial,
+                     reinterpret_cast<double2*>(n.grad) + n.woff[l]);
+    if (l > 0) net_layer(c, links12, grads[l + 1], grads[l], l, 1, nb);
+  }
+  return loss;
+}
+
+}  // namespace
+
 // ====================================================================== C-ABI
 extern "C" {
 
@@ -802,6 +1031,7 @@ void psms_destroy(psms_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
+  net_free(c);
   delete c;
 }
 
@@ -937,7 +1167,7 @@ static void fill_stats(psms_solve_stats* s, const FullSolveOut& o, double secs) 
   s->converged = o.converged ? 1 : 0;
   s->outer_iters = o.outer;
   s->inner_iters = o.inner;
-  s->used_fallback = 0;
+  s->used_fallback = o.used_fallback ? 1 : 0;
   s->true_rel_residual = o.max_rel;
   s->seconds = secs;
 }
@@ -1112,6 +1342,7 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
       agg.max_rel = std::max(agg.max_rel, o.max_rel);
       agg.nan |= o.nan;
       agg.converged &= o.converged;
+      agg.used_fallback |= o.used_fallback;
       double* yn2 = dscratch<double>(c, "ld_yn2", size_t(npp) * nj);
       norm2(c, y, yn2);
       std::vector<double> hy = to_host(c, yn2, npp * nj);
@@ -1135,6 +1366,245 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
   return PSMS_OK;
 }
 
+psms_status psms_net_init(psms_ctx* c, const int* channels, int nlayers, unsigned long long seed, double scale) {
+  API_BEGIN(c)
+  REQUIRE(channels != nullptr && nlayers >= 1 && nlayers <= 16, "bad network shape");
+  std::vector<int> ch(channels, channels + nlayers + 1);
+  net_alloc(c, ch);
+  // small random weights plus the identity on the (t = 0, channel 0 -> 0) path, so
+  // that the untrained network starts close to N(r) = r
+  std::mt19937_64 rng(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::vector<float> w(c->net.nw * 2);
+  for (int l = 0; l < c->net.nlayers; ++l) {
+    const int cin = ch[l], cout = ch[l + 1];
+    const double sd = scale / std::sqrt(9.0 * 4.0 * cin);
+    const size_t o = c->net.woff[l];
+    for (size_t k = 0; k < net_layer_size(cin, cout); ++k) {
+      w[2 * (o + k)] = float(sd * nd(rng));
+      w[2 * (o + k) + 1] = float(sd * nd(rng));
+    }
+    for (int s = 0; s < 4; ++s) w[2 * (o + s * 4 + s)] += 1.0f;  // t = 0, co = 0, ci = 0
+  }
+  HIPCHK(hipMemcpy(c->net.w, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->net.packed = false;
+  API_END(c)
+  return PSMS_OK;
+}
+
+long long psms_net_num_weights(const psms_ctx* c) { return c ? (long long)c->net.nw : 0; }
+
+psms_status psms_net_set_weights(psms_ctx* c, const double* w, long long n) {
+  API_BEGIN(c)
+  REQUIRE(c->net.nlayers > 0, "no network");
+  REQUIRE(w != nullptr && n == (long long)c->net.nw, "weight count must equal psms_net_num_weights");
+  std::vector<float> f(2 * n);
+  for (long long i = 0; i < 2 * n; ++i) f[i] = float(w[i]);
+  HIPCHK(hipMemcpy(c->net.w, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->net.packed = false;
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_net_get_weights(psms_ctx* c, double* w, long long n) {
+  API_BEGIN(c)
+  REQUIRE(c->net.nlayers > 0, "no network");
+  REQUIRE(w != nullptr && n == (long long)c->net.nw, "weight count must equal psms_net_num_weights");
+  std::vector<float> f(2 * n);
+  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipMemcpy(f.data(), c->net.w, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+  for (long long i = 0; i < 2 * n; ++i) w[i] = f[i];
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_net_apply(psms_ctx* c, int slot, const double* in, double* out, int nrhs) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  REQUIRE(c->net.nlayers > 0, "no network");
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  Links L = links_of(c, &slot, 1, LK_F32C12);
+  FieldBatch a = field(c, "api_a32", P_F32, 1, nrhs), b = field(c, "api_b32", P_F32, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  net_forward(c, L.p[0], a.p, nrhs, b.p, nullptr);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_net_loss_grad(psms_ctx* c, int slot, const double* r, const double* e, int npairs, double* loss,
+                               double* grad) {
+  API_BEGIN(c)
+  check_rhs(npairs);
+  REQUIRE(c->net.nlayers > 0, "no network");
+  REQUIRE(loss != nullptr, "null loss");
+  size_t nd = size_t(npairs) * c->V * 24;
+  const double* dr = stage_in(c, r, nd, "stage_in");
+  const double* de = stage_in(c, e, nd, "stage_in2");
+  Links L = links_of(c, &slot, 1, LK_F32C12);
+  FieldBatch r32 = field(c, "api_a32", P_F32, 1, npairs), e32 = field(c, "api_b32", P_F32, 1, npairs);
+  FieldBatch e64 = field(c, "api_e64", P_F64, 1, npairs);
+  launch_pack(c->st, c->g, dr, r32);
+  launch_pack(c->st, c->g, de, e32);
+  launch_pack(c->st, c->g, de, e64);
+  double* en = dscratch<double>(c, "api_en", npairs);
+  norm2(c, e64, en);
+  std::vector<double> hen = to_host(c, en, npairs);
+  *loss = net_loss_grad(c, L.p[0], r32, e32, hen.data(), npairs, false);
+  if (grad) {
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(grad, c->net.grad, c->net.nw * 2 * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+void psms_default_train_params(psms_train_params* p) {
+  if (!p) return;
+  p->npairs = 256;
+  p->batch = 8;
+  p->epochs = 2;
+  p->chunk = 64;
+  p->lr = 2e-3;
+  p->solve_tol = 1e-6;
+  p->seed = 12345;
+  p->ckpt_path = nullptr;
+  p->ckpt_every = 0;
+}
+
+static void net_write(psms_ctx* c, const char* path) {
+  auto& n = c->net;
+  std::vector<float> w(2 * n.nw), m(2 * n.nw), v(2 * n.nw);
+  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipMemcpy(w.data(), n.w, w.size() * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(m.data(), n.m, m.size() * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(v.data(), n.v, v.size() * 4, hipMemcpyDeviceToHost));
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  REQUIRE(f != nullptr, std::string("cannot write ") + path);
+  int32_t hdr[2] = {n.nlayers, n.adam_step};
+  std::fwrite("PSMSNET1", 1, 8, f);
+  std::fwrite(hdr, 4, 2, f);
+  std::fwrite(n.ch.data(), 4, n.ch.size(), f);
+  std::fwrite(w.data(), 4, w.size(), f);
+  std::fwrite(m.data(), 4, m.size(), f);
+  std::fwrite(v.data(), 4, v.size(), f);
+  bool ok = std::fclose(f) == 0;
+  REQUIRE(ok && std::rename(tmp.c_str(), path) == 0, std::string("cannot write ") + path);
+}
+
+psms_status psms_net_save(psms_ctx* c, const char* path) {
+  API_BEGIN(c)
+  REQUIRE(c->net.nlayers > 0 && path != nullptr, "no network or null path");
+  net_write(c, path);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_net_load(psms_ctx* c, const char* path) {
+  API_BEGIN(c)
+  REQUIRE(path != nullptr, "null path");
+  FILE* f = std::fopen(path, "rb");
+  REQUIRE(f != nullptr, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t hdr[2];
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "PSMSNET1", 8) == 0 && std::fread(hdr, 4, 2, f) == 2 &&
+            hdr[0] >= 1 && hdr[0] <= 16;
+  std::vector<int32_t> ch(ok ? hdr[0] + 1 : 0);
+  ok = ok && std::fread(ch.data(), 4, ch.size(), f) == ch.size();
+  if (!ok) {
+    std::fclose(f);
+    throw Err{PSMS_EINVAL, std::string("not a network checkpoint: ") + path};
+  }
+  net_alloc(c, std::vector<int>(ch.begin(), ch.end()));
+  auto& n = c->net;
+  std::vector<float> w(2 * n.nw), m(2 * n.nw), v(2 * n.nw);
+  ok = std::fread(w.data(), 4, w.size(), f) == w.size() && std::fread(m.data(), 4, m.size(), f) == m.size() &&
+       std::fread(v.data(), 4, v.size(), f) == v.size();
+  std::fclose(f);
+  REQUIRE(ok, std::string("truncated network checkpoint: ") + path);
+  HIPCHK(hipMemcpy(n.w, w.data(), w.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(n.m, m.data(), m.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(n.v, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+  n.adam_step = hdr[1];
+  n.packed = false;
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_net_train(psms_ctx* c, const int* slots, int nconf, const psms_train_params* tp, psms_train_stats* ts) {
+  API_BEGIN(c)
+  REQUIRE(c->net.nlayers > 0, "no network (psms_net_init or psms_net_load first)");
+  REQUIRE(slots != nullptr && nconf >= 1 && tp != nullptr, "bad arguments");
+  REQUIRE(tp->npairs >= 1 && tp->batch >= 1 && tp->chunk >= tp->batch && tp->epochs >= 1 && tp->lr > 0 &&
+              tp->solve_tol > 0,
+          "bad training parameters");
+  auto t0 = std::chrono::steady_clock::now();
+  double t_data = 0, t_train = 0, first = -1, last = 0;
+  int steps = 0;
+  const size_t fd = size_t(c->V) * 24;
+  psms_solve_params sp;
+  psms_default_params(&sp);
+  sp.tol = tp->solve_tol;
+  sp.prec = PSMS_MIXED;
+  sp.pc = PSMS_PC_SAP;
+  for (int k = 0, p0 = 0; p0 < tp->npairs; ++k, p0 += tp->chunk) {
+    const int nc = std::min(tp->chunk, tp->npairs - p0);
+    const int conf = slots[k % nconf];
+    auto ta = std::chrono::steady_clock::now();
+    // residual / correction pairs: Gaussian r, e = D^-1 r from the plain solver
+    double* rb = dscratch<double>(c, "tr_rb", fd * nc);
+    launch_gaussian(c->st, rb, fd / 2, nc, tp->seed, uint32_t(k));
+    FieldBatch b64 = field(c, "tr_b64", P_F64, 1, nc), x64 = field(c, "tr_x64", P_F64, 1, nc);
+    launch_pack(c->st, c->g, rb, b64);
+    FullSolveOut so = solve_full(c, &conf, &sp, b64, x64);
+    REQUIRE(!so.nan, "NaN while generating training pairs");
+    FieldBatch r32 = field(c, "tr_r32", P_F32, 1, nc), e32 = field(c, "tr_e32", P_F32, 1, nc);
+    launch_copy(c->st, c->g, b64, r32, nullptr);
+    launch_copy(c->st, c->g, x64, e32, nullptr);
+    double* en = dscratch<double>(c, "tr_en", nc);
+    norm2(c, x64, en);
+    std::vector<double> hen = to_host(c, en, nc);
+    Links L = links_of(c, &conf, 1, LK_F32C12);
+    auto tb = std::chrono::steady_clock::now();
+    t_data += std::chrono::duration<double>(tb - ta).count();
+    const size_t fb = bytes_per_field(P_F32, c->Vh);
+    for (int ep = 0; ep < tp->epochs; ++ep) {
+      for (int b0 = 0; b0 < nc; b0 += tp->batch) {
+        const int nb = std::min(tp->batch, nc - b0);
+        FieldBatch rb32{(char*)r32.p + b0 * fb, P_F32, 1, nb}, eb32{(char*)e32.p + b0 * fb, P_F32, 1, nb};
+        double loss = net_loss_grad(c, L.p[0], rb32, eb32, hen.data() + b0, nb, true);
+        {
+          ProfScope ps(c, FAM_NET, 0);
+          launch_adam(c->st, c->net.w, c->net.grad, c->net.m, c->net.v, int(2 * c->net.nw), float(tp->lr), 0.9f, 0.999f,
+                      1e-8f, ++c->net.adam_step);
+          c->net.packed = false;
+        }
+        if (first < 0) first = loss;
+        last = loss;
+        ++steps;
+        if (tp->ckpt_path && tp->ckpt_every > 0 && steps % tp->ckpt_every == 0) net_write(c, tp->ckpt_path);
+      }
+    }
+    t_train += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
+  }
+  if (tp->ckpt_path) net_write(c, tp->ckpt_path);
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (ts) {
+    ts->first_loss = first;
+    ts->final_loss = last;
+    ts->steps = steps;
+    ts->seconds_data = t_data;
+    ts->seconds_train = t_train;
+  }
+  (void)t0;
+  API_END(c)
+  return PSMS_OK;
+}
+
 static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "dslash_variant_f64")) return &c->variant[P_F64];
   if (!std::strcmp(key, "dslash_variant_f32")) return &c->variant[P_F32];
@@ -1142,10 +1612,11 @@ static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "nr_f64")) return &c->nr_f64;
   if (!std::strcmp(key, "nr_low")) return &c->nr_low;
   if (!std::strcmp(key, "xcd_map")) return &c->xcd_map;
+  if (!std::strcmp(key, "net_mfma")) return &c->net_mfma;
   return nullptr;
 }
 static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
-                                    "xcd_map"};
+                                    "xcd_map", "net_mfma"};
 
 psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   API_BEGIN(c)
@@ -1153,7 +1624,7 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   int* t = tuning_slot(c, key);
   REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
   if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 5, "stencil variant must be in [0, 5]");
-  else if (!std::strcmp(key, "xcd_map")) REQUIRE(value == 0 || value == 1, "xcd_map must be 0 or 1");
+  else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma")) REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
   else REQUIRE(value == 1 || value == 2 || value == 4, "right-hand sides per thread must be 1, 2 or 4");
   *t = value;
   API_END(c)

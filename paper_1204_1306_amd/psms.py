@@ -51,6 +51,19 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("npairs", C.c_int), ("batch", C.c_int), ("epochs", C.c_int), ("chunk", C.c_int), ("lr", C.c_double),
+                ("solve_tol", C.c_double), ("seed", C.c_ulonglong), ("ckpt_path", C.c_char_p), ("ckpt_every", C.c_int)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("first_loss", C.c_double), ("final_loss", C.c_double), ("steps", C.c_int),
+                ("seconds_data", C.c_double), ("seconds_train", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 _SIGS = {
@@ -74,6 +87,16 @@ _SIGS = {
                                        C.c_void_p]),
     "psms_logdet_ratio": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "psms_net_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_ulonglong, C.c_double]),
+    "psms_net_num_weights": (C.c_longlong, [C.c_void_p]),
+    "psms_net_set_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_longlong]),
+    "psms_net_get_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_longlong]),
+    "psms_net_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    "psms_net_loss_grad": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "psms_default_train_params": (None, [C.c_void_p]),
+    "psms_net_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "psms_net_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "psms_net_load": (C.c_int, [C.c_void_p, C.c_char_p]),
     "psms_set_tuning": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int]),
     "psms_get_tuning": (C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p]),
     "psms_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
@@ -261,8 +284,59 @@ class Context:
             self._check(s)
         return delta, st.as_dict()
 
+    # ---------------------------------------------------------------- learned preconditioner
+    def net_init(self, channels=(1, 8, 8, 8, 1), seed: int = 1, scale: float = 0.1):
+        ch = (C.c_int * len(channels))(*channels)
+        self._check(self._lib.psms_net_init(self._h, ch, len(channels) - 1, int(seed), float(scale)))
+
+    def net_num_weights(self) -> int:
+        return int(self._lib.psms_net_num_weights(self._h))
+
+    def net_get_weights(self) -> np.ndarray:
+        n = self.net_num_weights()
+        w = np.empty(n, np.complex128)
+        self._check(self._lib.psms_net_get_weights(self._h, C.c_void_p(w.ctypes.data), n))
+        return w
+
+    def net_set_weights(self, w):
+        w = np.ascontiguousarray(np.asarray(w, np.complex128).ravel())
+        self._check(self._lib.psms_net_set_weights(self._h, C.c_void_p(w.ctypes.data), w.size))
+
+    def net_apply(self, slot: int, psi):
+        out = _empty_like(psi)
+        self._check(self._lib.psms_net_apply(self._h, slot, _ptr(psi), _ptr(out), self._nrhs(psi)))
+        return out
+
+    def net_loss_grad(self, slot: int, r, e):
+        loss = C.c_double()
+        g = np.empty(self.net_num_weights(), np.complex128)
+        self._check(self._lib.psms_net_loss_grad(self._h, slot, _ptr(r), _ptr(e), self._nrhs(r), C.byref(loss),
+                                                 C.c_void_p(g.ctypes.data)))
+        return loss.value, g
+
+    def net_train(self, slots, **kw):
+        tp = TrainParams()
+        self._lib.psms_default_train_params(C.byref(tp))
+        keep = None
+        for k, v in kw.items():
+            if k == "ckpt_path" and v is not None:
+                keep = v.encode()
+                v = keep
+            setattr(tp, k, v)
+        arr = (C.c_int * len(slots))(*slots)
+        ts = TrainStats()
+        self._check(self._lib.psms_net_train(self._h, arr, len(slots), C.byref(tp), C.byref(ts)))
+        return ts.as_dict()
+
+    def net_save(self, path: str):
+        self._check(self._lib.psms_net_save(self._h, path.encode()))
+
+    def net_load(self, path: str):
+        self._check(self._lib.psms_net_load(self._h, path.encode()))
+
     # ---------------------------------------------------------------- tuning
-    TUNING_KEYS = ("dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low", "xcd_map")
+    TUNING_KEYS = ("dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low", "xcd_map",
+                   "net_mfma")
 
     def set_tuning(self, key: str, value: int):
         self._check(self._lib.psms_set_tuning(self._h, key.encode(), int(value)))

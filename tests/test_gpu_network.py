@@ -1,0 +1,151 @@
+"""GPU parity of the learned preconditioner against the FP64 network oracle:
+forward, loss and Wirtinger gradients, the Wilson-weight layer against D, a short
+training run on the GPU, checkpoint round trip, and flexible GCR with the network
+as right preconditioner (exact to the FP64 residual)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dirac
+from oracle import network as net
+from paper_1204_1306_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def psms():
+    from paper_1204_1306_amd import psms as m
+
+    m.load_library()
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def flat(ws):
+    return np.concatenate([w.ravel() for w in ws])
+
+
+def unflat(v, chans):
+    out, o = [], 0
+    for cin, cout in zip(chans[:-1], chans[1:]):
+        n = 9 * cout * cin * 16
+        out.append(v[o:o + n].reshape(9, cout, cin, 4, 4))
+        o += n
+    return out
+
+
+def rand_weights(seed, chans, scale=0.15):
+    rng = np.random.default_rng(seed)
+    return [scale * (rng.standard_normal((9, co, ci, 4, 4)) + 1j * rng.standard_normal((9, co, ci, 4, 4)))
+            for ci, co in zip(chans[:-1], chans[1:])]
+
+
+# FP32 vector-unit mixing: FP32 weights, activations and links; matrix-core mixing:
+# bf16 inputs to the MFMA (8-bit mantissa) with FP32 accumulation
+TOL = {0: 2e-5, 1: 3e-2}
+
+
+@pytest.mark.parametrize("mfma", [0, 1])
+@pytest.mark.parametrize("chans", [(1, 1), (1, 3, 2, 1), (1, 8, 8, 8, 1)])
+def test_net_forward_parity(psms, chans, mfma):
+    say("case net forward", chans, "mfma", mfma)
+    L, b = (4, 4, 4, 8), (2, 2, 2, 2)
+    U = synth.gauge_field(L, 0.6, 101)
+    r = synth.gaussian_noise(L, 2, 102)
+    ctx = psms.Context(L, b, 0.13)
+    ctx.set_tuning("net_mfma", mfma)
+    ctx.gauge_load(0, U)
+    ctx.net_init(chans)
+    ws = rand_weights(103, chans)
+    ctx.net_set_weights(flat(ws))
+    out = ctx.net_apply(0, r)
+    for k in range(2):
+        ref, _ = net.forward(U, ws, r[k], L)
+        assert rel(out[k], ref) < TOL[mfma]
+
+
+@pytest.mark.parametrize("mfma", [0, 1])
+def test_net_wilson_layer_is_dirac(psms, mfma):
+    L, b = (8, 4, 4, 8), (4, 2, 2, 2)
+    U = synth.gauge_field(L, 0.6, 111)
+    r = synth.gaussian_noise(L, 1, 112)[0]
+    W = np.zeros((9, 1, 1, 4, 4), complex)
+    W[0, 0, 0] = np.eye(4)
+    for mu in range(4):
+        W[1 + 2 * mu, 0, 0] = -0.14 * (np.eye(4) - dirac.GAMMA[mu])
+        W[2 + 2 * mu, 0, 0] = -0.14 * (np.eye(4) + dirac.GAMMA[mu])
+    ctx = psms.Context(L, b, 0.14)
+    ctx.set_tuning("net_mfma", mfma)
+    ctx.gauge_load(0, U)
+    ctx.net_init((1, 1))
+    ctx.net_set_weights(W.ravel())
+    assert rel(ctx.net_apply(0, r), dirac.apply_D(U, r, 0.14, L)) < (2e-6 if mfma == 0 else 1e-2)
+
+
+@pytest.mark.parametrize("mfma", [0, 1])
+def test_net_loss_and_gradient_parity(psms, mfma):
+    chans = (1, 2, 3, 2, 1)
+    L, b = (4, 4, 4, 4), (2, 2, 2, 2)
+    U = synth.gauge_field(L, 0.6, 121)
+    rs = synth.gaussian_noise(L, 3, 122)
+    es = synth.gaussian_noise(L, 3, 123)
+    ws = rand_weights(124, chans, scale=0.3)
+    ctx = psms.Context(L, b, 0.13)
+    ctx.set_tuning("net_mfma", mfma)
+    ctx.gauge_load(0, U)
+    ctx.net_init(chans)
+    ctx.net_set_weights(flat(ws))
+    loss, g = ctx.net_loss_grad(0, rs, es)
+    ref_loss, ref_g = net.backward(U, ws, list(rs), list(es), L)
+    say(" loss", loss, ref_loss, "grad rel err", rel(g, flat(ref_g)))
+    assert loss == pytest.approx(ref_loss, rel=1e-5 if mfma == 0 else 3e-2)
+    assert rel(g, flat(ref_g)) < (1e-4 if mfma == 0 else 5e-2)
+
+
+def test_net_training_reduces_loss_and_checkpoints(psms, tmp_path):
+    L, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kappa = 0.15
+    ctx = psms.Context(L, b, kappa)
+    for s in range(2):
+        ctx.gauge_load(s, synth.gauge_field(L, 0.6, 4000 + s))
+    ctx.net_init((1, 4, 4, 1), seed=3, scale=0.05)
+    st = ctx.net_train([0, 1], npairs=64, batch=8, epochs=3, chunk=32, lr=3e-3, solve_tol=1e-6,
+                       ckpt_path=str(tmp_path / "net.bin"))
+    say(" train", st)
+    assert st["final_loss"] < 0.8 * st["first_loss"]
+    w = ctx.net_get_weights()
+    ctx2 = psms.Context(L, b, kappa)
+    ctx2.gauge_load(0, synth.gauge_field(L, 0.6, 4000))
+    ctx2.net_load(str(tmp_path / "net.bin"))
+    assert np.array_equal(ctx2.net_get_weights(), w)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_gcr_with_network_preconditioner_is_exact(psms, prec):
+    L, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kappa = 0.15
+    U = synth.gauge_field(L, 0.6, 2001)
+    bvec = synth.gaussian_noise(L, 2, 131)
+    ctx = psms.Context(L, b, kappa)
+    ctx.gauge_load(0, U)
+    ctx.net_init((1, 4, 4, 1), seed=5, scale=0.05)
+    kw = dict(tol=1e-10, pc=psms.PC_NET, restart=32, max_iter=3000)
+    if prec == "mixed":
+        kw["prec"] = psms.MIXED
+    x, st = ctx.solve(0, bvec, psms.default_params(**kw))
+    say(" stats", st)
+    assert st["converged"] == 1
+    for k in range(2):
+        res = bvec[k] - dirac.apply_D(U, x[k], kappa, L)
+        assert np.linalg.norm(res) / np.linalg.norm(bvec[k]) <= 1.01e-10
