@@ -1,16 +1,17 @@
 """Benchmark of the stochastic determinant-ratio estimator on one MI355X.
 
-A step is one pass of the whole hot path over one batch of synthetic input:
-for every proposal U'_p and Gaussian noise vector eta_j of the workload,
-Delta_pj = |M xi_j|^2 - |xi_j|^2 with M the Schur-complement ratio operator
-(projector, block solves with U, inter-block hops, one full-lattice solve with
-U' per pair, FP64 accumulation). Inputs (gauge fields, noise) are resident in
+A step is one pass of the whole hot path over one batch of synthetic input: for
+every proposal U'_p and Gaussian noise vector eta_j of the workload,
+Delta_pj = |M xi_j|^2 - |xi_j|^2 with M the Schur-complement ratio operator:
+projector, Dirichlet block solves with U, inter-block hops, one full-lattice solve
+with U' per pair (flexible GCR, Schwarz preconditioner, FP64 true residual to the
+workload's tolerance), FP64 accumulation. Gauge fields and noise are resident in
 HBM before the timed region.
 
-Prints one JSON line. ``value`` is seconds per det-ratio estimate of the fast
-configuration (mixed precision, batched); the plain FP64 Schwarz-GCR time per
-estimate on the same GPU, the D_w bandwidth, the roofline of the dominant
-kernel and the CPU oracle baseline are reported beside it.
+The default workload is the 8^4 lattice with 4^4 blocks, kappa 0.15, 16 noise
+vectors, tolerance 1e-10, timed once with FP32 inner solves and FP64 defect
+correction (the value) and once fully in FP64 (plain). Prints one JSON line;
+progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -38,10 +39,13 @@ def mode_params(psms, mode: str, tol: float):
         return psms.default_params(tol=tol, prec=psms.F64, pc=psms.PC_SAP)
     if mode == "mixed":
         return psms.default_params(tol=tol, prec=psms.MIXED, pc=psms.PC_SAP, inner_storage=psms.SPINOR_F32,
-                                   inner_tol=1e-3)
+                                   inner_tol=1e-6)
     if mode == "mixed_bf16":
         return psms.default_params(tol=tol, prec=psms.MIXED, pc=psms.PC_SAP, inner_storage=psms.SPINOR_BF16,
-                                   inner_tol=1e-2)
+                                   inner_tol=5e-3, restart=32)
+    if mode == "learned":
+        return psms.default_params(tol=tol, prec=psms.MIXED, pc=psms.PC_NET, inner_storage=psms.SPINOR_F32,
+                                   inner_tol=1e-4, restart=32, max_iter=4000)
     raise ValueError(mode)
 
 
@@ -52,7 +56,7 @@ def setup(workload: str, nprop=None, nnoise=None):
 
     w, U, Ups, eta = synth.workload_inputs(workload, nprop=nprop, nnoise=nnoise)
     stream = torch.cuda.current_stream().cuda_stream
-    ctx = psms.Context(w["L"], w["b"], w["kappa"], stream=stream)
+    ctx = psms.Context(w["L"], w["b"], w["kappa"], stream=stream, sap_b=w.get("sap_b"))
     dev = torch.device("cuda:0")
     ctx.gauge_load(0, torch.from_numpy(U).to(dev))
     for p, Up in enumerate(Ups):
@@ -63,7 +67,10 @@ def setup(workload: str, nprop=None, nnoise=None):
     return psms, ctx, w, noise, delta, len(Ups)
 
 
-def run_steps(psms, ctx, w, noise, delta, nprop, params, steps, warmup, profile=False):
+FAMILIES = ("dslash", "dslash_part", "block_mr", "blas", "net")
+
+
+def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=False):
     import torch
 
     slots = list(range(1, 1 + nprop))
@@ -82,15 +89,15 @@ def run_steps(psms, ctx, w, noise, delta, nprop, params, steps, warmup, profile=
     dt = time.perf_counter() - t0
     fam = {}
     if profile:
-        for f in ("dslash", "dslash_part", "block_mr", "blas"):
-            fam[f] = ctx.profile_read(f)
+        fam = {f: ctx.profile_read(f) for f in FAMILIES}
         ctx.profile(False)
-    return dt, stats, fam, delta.cpu().numpy()
+    return dt, stats, fam, delta.cpu().numpy().copy()
 
 
-def dw_bandwidth(psms, L, b, kappa, reps=20, nrhs=1):
-    """Standalone full-lattice D_w launches on device-resident fields (FP64 and mixed)
-    on an L lattice (32^4 by default: its working set exceeds the 256 MB Infinity Cache)."""
+def dw_bandwidth(psms, L, b, kappa, reps=20):
+    """Full-lattice D_w launches on device-resident fields (FP64 and mixed), HIP events on
+    the library's stream, on an L lattice (32^4 by default: its working set exceeds the
+    256 MB Infinity Cache)."""
     import torch
 
     from paper_1204_1306_amd import synth
@@ -98,8 +105,9 @@ def dw_bandwidth(psms, L, b, kappa, reps=20, nrhs=1):
     dev = torch.device("cuda:0")
     ctx = psms.Context(L, b, kappa, stream=torch.cuda.current_stream().cuda_stream)
     ctx.gauge_load(0, torch.from_numpy(synth.gauge_field(L, 0.6, 5001)).to(dev))
-    psi = torch.from_numpy(synth.gaussian_noise(L, nrhs, 7)).to(dev)
-    out = {"lattice": "x".join(map(str, L)), "nrhs": nrhs}
+    tune = ctx.autotune(0, None)
+    psi = torch.from_numpy(synth.gaussian_noise(L, 1, 7)).to(dev)
+    out = {"lattice": "x".join(map(str, L)), "tuning": tune}
     for name, prec in (("f64", psms.F64), ("mixed", psms.MIXED)):
         ctx.apply_dw(0, psi, prec)
         torch.cuda.synchronize()
@@ -111,18 +119,39 @@ def dw_bandwidth(psms, L, b, kappa, reps=20, nrhs=1):
         ctx.profile(False)
         out[name] = {"gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9, "us_per_launch": 1e3 * r["ms"] / r["launches"],
                      "bytes_per_launch": r["bytes"] / r["launches"]}
+    ctx.close()
     return out
 
 
+def learned_leg(psms, ctx, w, noise, delta, nprop, steps, npairs):
+    """Train the gauge-covariant network on seeded configurations of the workload's
+    geometry (outside the timed region), then time the estimator with it as the right
+    preconditioner of the mixed-precision solver."""
+    import torch
+
+    from paper_1204_1306_amd import synth
+
+    dev = torch.device("cuda:0")
+    train_slots = []
+    for k in range(4):
+        ctx.gauge_load(40 + k, torch.from_numpy(synth.gauge_field(w["L"], w["eps"], 9000 + k)).to(dev))
+        train_slots.append(40 + k)
+    ctx.net_init((1, 8, 8, 8, 1), seed=7, scale=0.05)
+    t0 = time.perf_counter()
+    tr = ctx.net_train(train_slots, npairs=npairs, batch=8, epochs=2, chunk=64, lr=2e-3, solve_tol=1e-6)
+    t_train = time.perf_counter() - t0
+    prm = mode_params(psms, "learned", w["tol"])
+    dt, st, fam, d = run_steps(psms, ctx, noise, delta, nprop, prm, steps, 1, profile=True)
+    return {"s_per_estimate": dt / steps / (nprop * noise.shape[0]), "train_seconds": t_train, "train": tr,
+            "solver": st[-1], "net_ms_per_step": fam["net"]["ms"] / steps}, d
+
+
 def cpu_baseline(workload: str, budget_s: float = 20.0):
-    """The CPU oracle on a bounded sample of the workload (one estimate, truncated).
-
-    Sample: the oracle's Schur estimator for one (proposal, noise) pair, with the
-    full solve by CG on the normal equations run for a bounded number of
-    iterations; the time is scaled to a full estimate by the number of CG
-    iterations the observed residual decay needs to reach the workload tolerance."""
-    import threading
-
+    """The CPU oracle on a bounded sample of the workload: one Schur estimate (one
+    proposal, one noise vector). The Dirichlet block solves are timed on two blocks per
+    colour (dense LU) and scaled to all blocks; the full solve is CG on the normal
+    equations, run until the workload tolerance or the time budget, and scaled to the
+    tolerance from the observed residual decay when the budget ends first."""
     from oracle import schur
     from oracle.solvers import norm2
     from paper_1204_1306_amd import synth
@@ -132,10 +161,9 @@ def cpu_baseline(workload: str, budget_s: float = 20.0):
     opU = schur.Operator(g, U, w["kappa"], direct=False)
     opP = schur.Operator(g, Ups[0], w["kappa"], direct=False)
     xi = g.project(eta[0])
-    # block part: dense LU factor + solve of a few blocks of each colour, scaled to all blocks
     nsample = min(2, g.V // int(np.prod(w["b"])) // 2)
     t0 = time.perf_counter()
-    for colour, mask in (("black", g.black), ("white", g.white)):
+    for mask in (g.black, g.white):
         for k in np.unique(g.block[mask])[:nsample]:
             m = g.block == k
             lu = schur.DenseLU(opU.sub_matrix(m, m).toarray())
@@ -143,17 +171,14 @@ def cpu_baseline(workload: str, budget_s: float = 20.0):
     t_blk = (time.perf_counter() - t0) / (2 * nsample)
     nblk = g.V // int(np.prod(w["b"]))
     t_schur = t_blk * nblk
-    phi = xi
-    v = opP.D_wb(phi)
-    # CG on the normal equations, bounded by the time budget
+    v = opP.D_wb(xi)
     bn = np.sqrt(norm2(v))
     x = np.zeros_like(v)
     r = v.copy()
     z = opP.Ddag(r)
     p = z.copy()
     zz = norm2(z)
-    it = 0
-    hist = []
+    it, hist = 0, []
     t1 = time.perf_counter()
     while time.perf_counter() - t1 < budget_s and it < 5000 and (not hist or hist[-1] > w["tol"]):
         q = opP.D(p)
@@ -168,38 +193,37 @@ def cpu_baseline(workload: str, budget_s: float = 20.0):
         zz = zn
     t_cg = time.perf_counter() - t1
     per_it = t_cg / max(it, 1)
-    # iterations to reach tol from the average log-decay over the second half of the run
     h = np.array(hist)
     k0 = len(h) // 2
     rate = (np.log(h[-1]) - np.log(h[k0])) / max(len(h) - 1 - k0, 1)
     need = it if h[-1] <= w["tol"] else it + (np.log(w["tol"]) - np.log(h[-1])) / min(rate, -1e-12)
-    est = t_schur + per_it * need
-    import os as _os
-
     try:
-        cores = len(_os.sched_getaffinity(0))
+        cores = len(os.sched_getaffinity(0))
     except Exception:
-        cores = _os.cpu_count()
-    blas_threads = _os.environ.get("OMP_NUM_THREADS", str(cores))
-    return {"value": float(est), "unit": "s/estimate", "cores": int(blas_threads) if blas_threads.isdigit() else cores,
-            "kind": "oracle",
-            "sample": (f"one {workload} Schur estimate: block solves by dense LU per block "
-                       f"({nsample} blocks per colour timed, {t_blk:.2f} s each, x {nblk} blocks = {t_schur:.1f} s), then {it} CG-on-normal-equations iterations of the full solve "
-                       f"({t_cg:.1f} s, residual {h[-1]:.2e}); scaled to {need:.0f} iterations for tol {w['tol']:g} "
-                       f"from the observed residual decay")}
+        cores = os.cpu_count()
+    threads = os.environ.get("OMP_NUM_THREADS")
+    return {"value": float(t_schur + per_it * need), "unit": "s/estimate",
+            "cores": int(threads) if threads and threads.isdigit() else cores, "kind": "oracle",
+            "sample": (f"one {workload} Schur estimate (1 proposal x 1 noise): block solves by dense LU timed on "
+                       f"{nsample} blocks per colour ({t_blk:.3f} s each) x {nblk} blocks = {t_schur:.2f} s; full solve "
+                       f"by CG on the normal equations, {it} iterations in {t_cg:.1f} s reaching {h[-1]:.1e}"
+                       + ("" if h[-1] <= w["tol"] else f", scaled to {need:.0f} iterations for {w['tol']:g}"))}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
     ap.add_argument("--mode", default="mixed")
-    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--nprop", type=int, default=None)
     ap.add_argument("--nnoise", type=int, default=None)
+    ap.add_argument("--rhs-chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-pairs", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--dw-lattice", default="32,32,32,32")
     args = ap.parse_args()
@@ -215,29 +239,48 @@ def main():
     psms, ctx, w, noise, delta, nprop = setup(args.workload, args.nprop, args.nnoise)
     nnoise = noise.shape[0]
     nest = nprop * nnoise
-    log(f"workload {args.workload}: L={w['L']} b={w['b']} kappa={w['kappa']} {nprop} proposals x {nnoise} noise")
+    tune = ctx.autotune(0, None)
+    log(f"workload {args.workload}: L={w['L']} b={w['b']} kappa={w['kappa']} {nprop} proposals x {nnoise} noise; "
+        f"tuning {tune}")
 
     fast = mode_params(psms, args.mode, w["tol"])
-    dt, stats, fam, d_fast = run_steps(psms, ctx, w, noise, delta, nprop, fast, args.steps, args.warmup, profile=True)
+    fast.rhs_chunk = args.rhs_chunk
+    dt, stats, fam, d_fast = run_steps(psms, ctx, noise, delta, nprop, fast, args.steps, args.warmup, profile=True)
     ms_per_step = 1e3 * dt / args.steps
-    log(f"{args.mode}: {ms_per_step:.1f} ms/step, stats {stats[-1]}")
+    log(f"{args.mode}: {ms_per_step:.2f} ms/step, solver {stats[-1]}")
+    log("  kernel families (ms over the timed steps):", {f: round(v["ms"], 2) for f, v in fam.items()})
 
     plain = mode_params(psms, "plain", w["tol"])
-    dtp, stp, _, d_plain = run_steps(psms, ctx, w, noise, delta, nprop, plain, args.plain_steps, 0)
+    plain.rhs_chunk = args.rhs_chunk
+    dtp, stp, _, d_plain = run_steps(psms, ctx, noise, delta, nprop, plain, args.plain_steps, 1)
     s_plain = dtp / args.plain_steps / nest
-    log(f"plain f64: {1e3 * dtp / args.plain_steps:.1f} ms/step, stats {stp[-1]}")
+    log(f"plain f64: {1e3 * dtp / args.plain_steps:.2f} ms/step, solver {stp[-1]}")
+
+    learned = None
+    if not args.no_learned:
+        try:
+            learned, d_learned = learned_leg(psms, ctx, w, noise, delta, nprop, max(1, args.plain_steps // 2),
+                                             args.learned_pairs)
+            learned["max_abs_delta_diff_vs_plain"] = float(np.abs(d_learned - d_plain).max())
+            log(f"learned: {learned}")
+        except Exception as e:  # reported, not hidden
+            learned = {"error": repr(e)}
 
     dwL = tuple(int(v) for v in args.dw_lattice.split(","))
     dw = dw_bandwidth(psms, dwL, tuple(max(2, v // 4) for v in dwL), w["kappa"])
     log(f"D_w: {dw}")
 
-    # roofline of the dominant kernel family over the timed region
-    dom = max((f for f in fam if fam[f]["launches"] > 0 and fam[f]["bytes"] > 0), key=lambda f: fam[f]["ms"])
+    # roofline of the dominant kernel family (by time) among those with a bytes model
+    cand = [f for f in fam if fam[f]["launches"] > 0 and fam[f]["bytes"] > 0]
+    dom = max(cand, key=lambda f: fam[f]["ms"])
     ach = fam[dom]["bytes"] / (fam[dom]["ms"] * 1e-3) / 1e9
+    total_ms = sum(v["ms"] for v in fam.values())
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
             "us_per_launch": round(1e3 * fam[dom]["ms"] / fam[dom]["launches"], 2),
-            "time_share": round(fam[dom]["ms"] / max(sum(f["ms"] for f in fam.values()), 1e-9), 3)}
+            "bytes_per_launch": fam[dom]["bytes"] / fam[dom]["launches"],
+            "time_share": round(fam[dom]["ms"] / max(total_ms, 1e-9), 3),
+            "family_ms": {f: round(v["ms"], 2) for f, v in fam.items()}}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -247,22 +290,26 @@ def main():
             cpu = {"value": None, "error": repr(e)}
 
     value = dt / args.steps / nest
+    dtype = {"mixed": "f32+f64", "mixed_bf16": "bf16+f32+f64", "plain": "f64", "learned": "f32+f64"}[args.mode]
     line = {
         "metric": METRIC, "value": value, "unit": "s/estimate", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if args.mode == "mixed" else ("bf16+f32+f64" if "bf16" in args.mode else "f64"),
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {'x'.join(map(str, w['L']))} lattice, {'x'.join(map(str, w['b']))} blocks, "
-                               f"kappa {w['kappa']}, {nprop} proposals x {nnoise} noise, Schur ratio, tol {w['tol']:g}",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": (f"{args.workload}: {'x'.join(map(str, w['L']))} lattice, {'x'.join(map(str, w['b']))} "
+                                f"blocks, kappa {w['kappa']}, links exp(i {w['eps']} H), {nprop} proposal(s) x {nnoise} "
+                                f"noise, Schur-complement ratio, relative residual {w['tol']:g}"),
                    "mode": args.mode, "estimates_per_step": nest},
         "plain_f64_s_per_estimate": s_plain,
         "speedup_vs_plain_f64": s_plain / value,
         "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
+        "learned": learned,
         "dw_lattice": dw["lattice"],
-        "dw_gbs": {k: round(v["gbs"], 1) for k, v in dw.items() if isinstance(v, dict)},
-        "dw_us_per_launch": {k: round(v["us_per_launch"], 2) for k, v in dw.items() if isinstance(v, dict)},
-        "dw_frac_of_hbm_peak": {k: round(v["gbs"] / HBM_PEAK_GBS, 4) for k, v in dw.items() if isinstance(v, dict)},
+        "dw_gbs": {k: round(v["gbs"], 1) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
+        "dw_us_per_launch": {k: round(v["us_per_launch"], 2) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
+        "dw_frac_of_hbm_peak": {k: round(v["gbs"] / HBM_PEAK_GBS, 4) for k, v in dw.items()
+                                if isinstance(v, dict) and "gbs" in v},
         "solver": {"fast": stats[-1], "plain": stp[-1]},
+        "tuning": tune,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

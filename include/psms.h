@@ -50,9 +50,13 @@ typedef enum { PSMS_SPINOR_F32 = 0, PSMS_SPINOR_BF16 = 1 } psms_inner_storage;
 
 typedef struct {
   int L[4];            /* lattice extent, mu = 0 is time */
-  int b[4];            /* block extent */
+  int b[4];            /* block extent of the domain decomposition (Schur complement) */
   int antiperiodic_t;  /* 1: fermions antiperiodic in time */
   double kappa;        /* hopping parameter */
+  int sap_b[4];        /* block extent of the Schwarz preconditioner of the full-lattice
+                          solves; all zero: the same as b. Must divide b, be even, with
+                          L[mu]/sap_b[mu] even. The solver then works in a second block
+                          layout (fields permuted in and out, links held twice). */
 } psms_geom;
 
 typedef struct {
@@ -81,7 +85,7 @@ typedef struct {
 typedef struct psms_ctx psms_ctx;
 
 /* Fills params with defaults: tol 1e-10, max_iter 2000, restart 16, F64, SAP,
- * 4 cycles, 4 block iterations, inner_tol 1e-2 (BF16 inner storage clamps it to
+ * 4 cycles, 6 block iterations, inner_tol 1e-2 (BF16 inner storage clamps it to
  * >= 5e-3), F32 inner storage, fallback on, rhs_chunk 0. */
 void psms_default_params(psms_solve_params* params);
 
@@ -205,9 +209,12 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
 
 /* Launch tuning of the context. Keys: "dslash_variant_f64", "dslash_variant_f32",
  * "dslash_variant_bf16" (full-lattice stencil form, 0..5: one lane or two wave groups
- * per site, times three register budgets) and "nr_f64", "nr_low" (right-hand sides per
- * stencil thread: 1, 2 or 4). Unknown keys or values give PSMS_EINVAL. Results do not
- * depend on the tuning; only speed does. */
+ * per site, times three register budgets), "nr_f64", "nr_low" (right-hand sides per
+ * stencil thread: 1, 2 or 4), "xcd_map" (1: each XCD sweeps a contiguous range of
+ * tiles), "net_mfma" (1: network channel mixing on the matrix cores in bf16, 0: FP32 on
+ * the vector units) and "block_solver" (block inverses to tolerance: 0 minimal residual
+ * per block, 1 flexible GCR on the block-diagonal operator). Unknown keys or values give
+ * PSMS_EINVAL. Results do not depend on the tuning beyond rounding; only speed does. */
 psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);
 psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);
 

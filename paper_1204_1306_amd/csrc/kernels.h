@@ -37,6 +37,9 @@ struct DslashParams {
 void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& in,
                    const FieldBatch& out, const DslashParams& dp, int nr_pref);
 
+// the same fields in another block layout (a lattice with two block sizes)
+void launch_permute(hipStream_t st, const Geo& from, const Geo& to, const FieldBatch& in, const FieldBatch& out);
+
 // boundary layout [rhs][V][4][3] complex double  <->  internal batch
 void launch_pack(hipStream_t st, const Geo& g, const double* src, const FieldBatch& dst);
 void launch_unpack(hipStream_t st, const Geo& g, const FieldBatch& src, double* dst);

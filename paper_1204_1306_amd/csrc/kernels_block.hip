@@ -69,6 +69,28 @@ __device__ __forceinline__ double wg_sum(double v, double* sm) {
   return t;
 }
 
+// Three workgroup sums with one barrier pair (fixed order, deterministic).
+__device__ __forceinline__ void wg_sum3(double& a, double& b, double& c, double (*sm)[16]) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sm[0][w] = a;
+    sm[1][w] = b;
+    sm[2][w] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) {
+    a += sm[0][k];
+    b += sm[1][k];
+    c += sm[2][k];
+  }
+}
+
 template <class S, class LK, class T>
 __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   __shared__ double sm[16];
@@ -283,9 +305,7 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
           pri += ar * bi - ai * br;
           pp += ar * ar + ai * ai;
         }
-      prr = wg_sum(prr, sm[0]);
-      pri = wg_sum(pri, sm[1]);
-      pp = wg_sum(pp, sm[2]);
+      wg_sum3(prr, pri, pp, sm);
       if (!(pp > 0.0)) break;
       const cx<T> alpha = {T(prr / pp), T(pri / pp)};
       double rr = 0.0;

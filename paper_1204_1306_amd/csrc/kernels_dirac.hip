@@ -322,13 +322,8 @@ void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int l
 }
 
 // ----------------------------------------------------------------- layout conversion
-// Internal (parity, s) of a lexicographic site.
-__device__ __forceinline__ void lex_to_internal(const Geo& g, int lex, int& p, int& s) {
-  int x[4];
-  int r = lex;
-  x[3] = r % g.L[3]; r /= g.L[3];
-  x[2] = r % g.L[2]; r /= g.L[2];
-  x[1] = r % g.L[1]; x[0] = r / g.L[1];
+// Internal (parity, s) of the site with coordinates x.
+__device__ __forceinline__ void coords_to_internal(const Geo& g, const int (&x)[4], int& p, int& s) {
   int B[4], l[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -340,6 +335,42 @@ __device__ __forceinline__ void lex_to_internal(const Geo& g, int lex, int& p, i
   int ll = ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * g.b[3] + l[3];
   p = (x[0] + x[1] + x[2] + x[3]) & 1;
   s = (col * g.nblk_c + (lexB >> 1)) * g.Vbh + (ll >> 1);
+}
+
+// Internal (parity, s) of a lexicographic site.
+__device__ __forceinline__ void lex_to_internal(const Geo& g, int lex, int& p, int& s) {
+  int x[4];
+  int r = lex;
+  x[3] = r % g.L[3]; r /= g.L[3];
+  x[2] = r % g.L[2]; r /= g.L[2];
+  x[1] = r % g.L[1]; x[0] = r / g.L[1];
+  coords_to_internal(g, x, p, s);
+}
+
+// out (layout `to`) = in (layout `from`): the same fields in another block order.
+// Parity is a property of the site, so only the index within the parity changes.
+template <class S>
+__global__ void k_permute(Geo from, Geo to, const typename S::unit* __restrict__ in, typename S::unit* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * to.Vh) return;
+  const int p = t / to.Vh, s = t - p * to.Vh;
+  SiteInfo si;
+  site_info(to, p, s, si);
+  int x[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) x[m] = si.B[m] * to.b[m] + si.l[m];
+  int pf, sf;
+  coords_to_internal(from, x, pf, sf);
+  const size_t Vh = to.Vh, off = size_t(blockIdx.y) * 2 * S::NC * Vh;
+#pragma unroll
+  for (int k = 0; k < S::NC; ++k) out[off + (size_t(p) * S::NC + k) * Vh + s] = in[off + (size_t(pf) * S::NC + k) * Vh + sf];
+}
+
+void launch_permute(hipStream_t st, const Geo& from, const Geo& to, const FieldBatch& in, const FieldBatch& out) {
+  dim3 grid((2 * to.Vh + 255) / 256, in.nprop * in.nrhs);
+  if (in.prec == P_F64) hipLaunchKernelGGL(k_permute<StF64>, grid, dim3(256), 0, st, from, to, (const double2*)in.p, (double2*)out.p);
+  else if (in.prec == P_F32) hipLaunchKernelGGL(k_permute<StF32>, grid, dim3(256), 0, st, from, to, (const float4*)in.p, (float4*)out.p);
+  else hipLaunchKernelGGL(k_permute<StBF16>, grid, dim3(256), 0, st, from, to, (const uint4*)in.p, (uint4*)out.p);
 }
 
 template <class S, class T>

@@ -47,6 +47,8 @@ struct Slot {
   bool su3 = false;
   void* f64 = nullptr;
   void* c12 = nullptr;
+  void* f64_s = nullptr;  // the same links in the solver layout (when the layouts differ)
+  void* c12_s = nullptr;
 };
 
 struct ProfRec {
@@ -66,9 +68,16 @@ struct psms_ctx {
   int device = 0;
   hipStream_t st = nullptr;
   int V = 0, Vh = 0;
-  uint32_t* d_lcoord = nullptr;
-  uint32_t* d_bcoord = nullptr;
-  int* d_border = nullptr;
+  std::vector<void*> geo_mem;  // device tables of the layouts
+  bool split = false;          // the solver works in a second layout with Schwarz blocks sap_b
+  Geo gs;                      // that layout
+  bool solver_view = false;    // links_of hands out the solver-layout links
+  int op_colour = -1;          // >= 0: the solver's operator is D_cc of that colour
+  int block_solver = 0;        // block inverses to tolerance: 0 minimal residual, 1 flexible GCR
+  // pinned host slots for the lagged convergence check of the GCR iteration
+  double* pinned[2] = {nullptr, nullptr};
+  size_t pinned_n = 0;
+  hipEvent_t rn_ev[2] = {nullptr, nullptr};
   Slot slots[64];
   std::map<std::string, DevBuf> bufs;
   std::string err;
@@ -214,31 +223,28 @@ void prof_collect(psms_ctx* c) {
 }
 
 // ------------------------------------------------------------------ geometry
-void setup_geometry(psms_ctx* c, const psms_geom* gm) {
-  Geo& g = c->g;
+// Builds the block-major layout of a lattice L with blocks b (device tables owned by c).
+void build_geo(psms_ctx* c, const int* L, const int* b, int apbc, Geo& g) {
   int V = 1, nblk = 1, Vb = 1;
   for (int m = 0; m < 4; ++m) {
-    REQUIRE(gm->L[m] > 0 && gm->L[m] <= 255, "L[mu] must be in [1, 255]");
-    REQUIRE(gm->b[m] > 0 && gm->L[m] % gm->b[m] == 0, "L[mu] must be a multiple of b[mu]");
-    REQUIRE(gm->b[m] % 2 == 0, "b[mu] must be even (even-odd order inside blocks)");
-    REQUIRE((gm->L[m] / gm->b[m]) % 2 == 0, "L[mu]/b[mu] must be even (consistent block colouring)");
-    g.L[m] = gm->L[m];
-    g.b[m] = gm->b[m];
-    g.NB[m] = gm->L[m] / gm->b[m];
+    REQUIRE(L[m] > 0 && L[m] <= 255, "L[mu] must be in [1, 255]");
+    REQUIRE(b[m] > 0 && L[m] % b[m] == 0, "L[mu] must be a multiple of b[mu]");
+    REQUIRE(b[m] % 2 == 0, "b[mu] must be even (even-odd order inside blocks)");
+    REQUIRE((L[m] / b[m]) % 2 == 0, "L[mu]/b[mu] must be even (consistent block colouring)");
+    g.L[m] = L[m];
+    g.b[m] = b[m];
+    g.NB[m] = L[m] / b[m];
     V *= g.L[m];
     nblk *= g.NB[m];
     Vb *= g.b[m];
   }
-  REQUIRE(gm->kappa > 0 && std::isfinite(gm->kappa), "kappa must be positive");
   g.sB[3] = 1; g.sB[2] = g.NB[3]; g.sB[1] = g.NB[3] * g.NB[2]; g.sB[0] = g.sB[1] * g.NB[1];
   g.sl[3] = 1; g.sl[2] = g.b[3]; g.sl[1] = g.b[3] * g.b[2]; g.sl[0] = g.sl[1] * g.b[1];
   g.Vh = V / 2;
   g.Vbh = Vb / 2;
   g.nblk = nblk;
   g.nblk_c = nblk / 2;
-  g.apbc = gm->antiperiodic_t ? 1 : 0;
-  c->V = V;
-  c->Vh = V / 2;
+  g.apbc = apbc;
   // local coordinates of (parity, i) and block coordinates of blk
   std::vector<uint32_t> lc(2 * g.Vbh), bc(nblk);
   for (int l0 = 0; l0 < g.b[0]; ++l0)
@@ -257,21 +263,38 @@ void setup_geometry(psms_ctx* c, const psms_geom* gm) {
           int col = (B0 + B1 + B2 + B3) & 1;
           bc[col * g.nblk_c + (lexB >> 1)] = uint32_t(B0) | (uint32_t(B1) << 8) | (uint32_t(B2) << 16) | (uint32_t(B3) << 24);
         }
-  c->d_lcoord = (uint32_t*)dev_alloc(c, lc.size() * 4);
-  c->d_bcoord = (uint32_t*)dev_alloc(c, bc.size() * 4);
-  HIPCHK(hipMemcpy(c->d_lcoord, lc.data(), lc.size() * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_bcoord, bc.data(), bc.size() * 4, hipMemcpyHostToDevice));
-  g.lcoord = c->d_lcoord;
-  g.bcoord = c->d_bcoord;
   // schedule of blocks for full-lattice launches: black block bi then white block
   // bi (neighbours along direction 3), in lexicographic order of bi. (A Morton order
   // of the block coordinates was measured slower: it scatters the per-block chunks
   // of every component plane.)
   std::vector<int> order(nblk);
   for (int k = 0; k < nblk; ++k) order[k] = (k & 1) * g.nblk_c + (k >> 1);
-  c->d_border = (int*)dev_alloc(c, order.size() * 4);
-  HIPCHK(hipMemcpy(c->d_border, order.data(), order.size() * 4, hipMemcpyHostToDevice));
-  g.border = c->d_border;
+  uint32_t* dl = (uint32_t*)dev_alloc(c, lc.size() * 4);
+  uint32_t* db = (uint32_t*)dev_alloc(c, bc.size() * 4);
+  int* dord = (int*)dev_alloc(c, order.size() * 4);
+  c->geo_mem.insert(c->geo_mem.end(), {(void*)dl, (void*)db, (void*)dord});
+  HIPCHK(hipMemcpy(dl, lc.data(), lc.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(db, bc.data(), bc.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dord, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+  g.lcoord = dl;
+  g.bcoord = db;
+  g.border = dord;
+}
+
+void setup_geometry(psms_ctx* c, const psms_geom* gm) {
+  REQUIRE(gm->kappa > 0 && std::isfinite(gm->kappa), "kappa must be positive");
+  build_geo(c, gm->L, gm->b, gm->antiperiodic_t ? 1 : 0, c->g);
+  c->V = 2 * c->g.Vh;
+  c->Vh = c->g.Vh;
+  const bool any = gm->sap_b[0] || gm->sap_b[1] || gm->sap_b[2] || gm->sap_b[3];
+  c->split = false;
+  if (any) {
+    for (int m = 0; m < 4; ++m) {
+      REQUIRE(gm->sap_b[m] > 0 && gm->b[m] % gm->sap_b[m] == 0, "sap_b[mu] must divide b[mu]");
+      c->split |= gm->sap_b[m] != gm->b[m];
+    }
+    if (c->split) build_geo(c, gm->L, gm->sap_b, gm->antiperiodic_t ? 1 : 0, c->gs);
+  }
 }
 
 // ------------------------------------------------------------------ constants
@@ -305,11 +328,12 @@ Links links_of(psms_ctx* c, const int* slots, int nprop, int fmt) {
   L.fmt = fmt;
   for (int i = 0; i < nprop; ++i) {
     REQUIRE(slots[i] >= 0 && slots[i] < 64 && c->slots[slots[i]].loaded, "gauge slot not loaded");
+    const Slot& sl = c->slots[slots[i]];
     if (fmt == LK_F32C12) {
-      if (!c->slots[slots[i]].su3) throw Err{PSMS_ENOTSU3, "mixed precision needs SU(3) links (12-real compression)"};
-      L.p[i] = c->slots[slots[i]].c12;
+      if (!sl.su3) throw Err{PSMS_ENOTSU3, "mixed precision needs SU(3) links (12-real compression)"};
+      L.p[i] = c->solver_view ? sl.c12_s : sl.c12;
     } else {
-      L.p[i] = c->slots[slots[i]].f64;
+      L.p[i] = c->solver_view ? sl.f64_s : sl.f64;
     }
   }
   return L;
@@ -339,13 +363,39 @@ void dslash(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch&
   launch_dslash(c->st, c->g, L.p, L.fmt, in, out, dp, in.prec == P_F64 ? c->nr_f64 : c->nr_low);
 }
 
+// The solver's operator: D on the full lattice, or D_cc (blocks of one colour, the
+// other colour kept at zero) while a block-diagonal system is being solved.
 void apply_D(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch& out) {
+  if (c->op_colour >= 0) {
+    dslash(c, L, in, out, HOP_INTRA, c->op_colour, 1.0, -c->geom.kappa, 0);
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_keep_colour(c->st, c->g, out, c->op_colour);
+    return;
+  }
   dslash(c, L, in, out, HOP_ALL, -1, 1.0, -c->geom.kappa, 0);
 }
 
 void norm2(psms_ctx* c, const FieldBatch& x, double* d_out) {
   ProfScope ps(c, FAM_BLAS, 0);
   reduce_norm2(c->st, c->g, x, reducer(c, x.nprop * x.nrhs, 1), d_out);
+}
+
+// Pinned host slot (page-locked, allocated by hipHostMalloc) for n doubles.
+double* pinned_slot(psms_ctx* c, int slot, int n) {
+  if (c->pinned_n < size_t(n)) {
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (auto& p : c->pinned) {
+      if (p) HIPCHK(hipHostFree(p));
+      p = nullptr;
+    }
+    for (auto& p : c->pinned) HIPCHK(hipHostMalloc((void**)&p, size_t(n) * sizeof(double), hipHostMallocDefault));
+    c->pinned_n = n;
+  }
+  if (!c->rn_ev[0]) {
+    HIPCHK(hipEventCreateWithFlags(&c->rn_ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->rn_ev[1], hipEventDisableTiming));
+  }
+  return c->pinned[slot];
 }
 
 std::vector<double> to_host(psms_ctx* c, const double* d, int n) {
@@ -495,15 +545,28 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
         else launch_axpy_mixed(st, g, NEGA, Wk, r, +1);
         reduce_norm2(st, g, r, R, rn2);
       }
-      std::vector<double> hr = to_host(c, rn2, nr);
+      // Residual norms go to pinned host memory behind an event; the check of
+      // iteration k - 1 happens after iteration k is enqueued, so the host never idles
+      // the GPU. Convergence seen one iteration late costs one extra (harmless) step.
+      double* hslot = pinned_slot(c, k & 1, nr);
+      HIPCHK(hipMemcpyAsync(hslot, rn2, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipEventRecord(c->rn_ev[k & 1], st));
       ++res.iters;
       used = k + 1;
-      conv = true;
-      for (int i = 0; i < nr; ++i) {
-        if (!std::isfinite(hr[i])) res.nan = true;
-        res.rel[i] = hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0;
-        if (act[i] && hr[i] > tol2 * hb[i]) conv = false;
-      }
+      const bool last = k == m - 1 || res.iters >= cf.maxit;
+      auto check = [&](int slot) {
+        HIPCHK(hipEventSynchronize(c->rn_ev[slot]));
+        const double* hr = pinned_slot(c, slot, nr);
+        bool cv = true;
+        for (int i = 0; i < nr; ++i) {
+          if (!std::isfinite(hr[i])) res.nan = true;
+          res.rel[i] = hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0;
+          if (act[i] && hr[i] > tol2 * hb[i]) cv = false;
+        }
+        return cv;
+      };
+      if (k > 0) conv = check((k - 1) & 1);
+      if (!conv && !res.nan && last) conv = check(k & 1);
       if (res.nan || conv || res.iters >= cf.maxit) break;
     }
     {
@@ -541,8 +604,34 @@ struct FullSolveOut {
   double max_rel = 0;
 };
 
+FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& b64,
+                             const FieldBatch& x64);
+
+// Full-lattice solve D x = b. With a separate Schwarz block size the right-hand sides
+// are permuted into the solver layout, solved there and the solutions permuted back.
 FullSolveOut solve_full(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& b64,
                         const FieldBatch& x64) {
+  if (!c->split || c->solver_view) return solve_full_impl(c, slots, pp, b64, x64);
+  FieldBatch bs = field(c, "sv_b", P_F64, b64.nprop, b64.nrhs), xs = field(c, "sv_x", P_F64, b64.nprop, b64.nrhs);
+  launch_permute(c->st, c->g, c->gs, b64, bs);
+  std::swap(c->g, c->gs);
+  c->solver_view = true;
+  FullSolveOut o;
+  try {
+    o = solve_full_impl(c, slots, pp, bs, xs);
+  } catch (...) {
+    std::swap(c->g, c->gs);
+    c->solver_view = false;
+    throw;
+  }
+  std::swap(c->g, c->gs);
+  c->solver_view = false;
+  launch_permute(c->st, c->gs, c->g, xs, x64);
+  return o;
+}
+
+FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& b64,
+                             const FieldBatch& x64) {
   FullSolveOut o;
   const int np = b64.nprop, nrb = b64.nrhs, nr = np * nrb;
   const hipStream_t st = c->st;
@@ -691,10 +780,44 @@ FullSolveOut solve_full(psms_ctx* c, const int* slots, const psms_solve_params* 
 }
 
 // ------------------------------------------------------------------ block solves to tolerance
+// While alive, the solver's operator is D_cc (the blocks of one colour, Dirichlet).
+struct ColourOperator {
+  psms_ctx* c;
+  ColourOperator(psms_ctx* c_, int col) : c(c_) { c->op_colour = col; }
+  ~ColourOperator() { c->op_colour = -1; }
+};
+
 // x = D_cc^-1 b on the blocks of colour col; b is left unchanged. Returns max relative residual.
-double solve_colour(psms_ctx* c, const Links& L, int col, const FieldBatch& b, const FieldBatch& x, double tol, int maxit,
+// By default every block is solved by the minimal-residual kernel, one workgroup per
+// block (LDS-resident for blocks of 256 sites). block_solver = 1 instead runs flexible
+// GCR on the block-diagonal operator (mixed precision with FP64 defect correction);
+// measured slower for 8^4 blocks at 32^4 (its Krylov basis costs more than it saves).
+double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b, const FieldBatch& x, double tol, int maxit,
                     int* iters_host) {
   const int np = b.nprop, nrb = b.nrhs, nr = np * nrb;
+  Links L = links_of(c, slots, np, LK_F64);
+  if (c->block_solver == 1) {
+    FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_copy(c->st, c->g, b, bc, nullptr);
+      launch_keep_colour(c->st, c->g, bc, col);
+    }
+    bool su3 = true;
+    for (int i = 0; i < np; ++i) su3 &= c->slots[slots[i]].su3;
+    psms_solve_params p;
+    psms_default_params(&p);
+    p.tol = tol;
+    p.max_iter = maxit;
+    p.restart = 32;
+    p.pc = PSMS_PC_NONE;
+    p.prec = su3 ? PSMS_MIXED : PSMS_F64;
+    p.inner_tol = 1e-4;
+    ColourOperator guard(c, col);
+    FullSolveOut o = solve_full_impl(c, slots, &p, bc, x);
+    if (iters_host) *iters_host = o.inner;
+    return o.nan ? std::nan("") : o.max_rel;
+  }
   FieldBatch rho = field(c, "bs_rho", P_F64, np, nrb);
   FieldBatch dl = field(c, "bs_delta", P_F64, np, nrb);
   FieldBatch pb = field(c, "bs_p", P_F64, np, nrb);
@@ -739,8 +862,9 @@ double solve_colour(psms_ctx* c, const Links& L, int col, const FieldBatch& b, c
 }
 
 // out = (1 - P Q) xi, Q = D_bb^-1 D_bw D_ww^-1 D_wb. Returns worst block-solve residual.
-double schur_apply(psms_ctx* c, const Links& L, const FieldBatch& xi, const FieldBatch& out, double tol, int maxit) {
+double schur_apply(psms_ctx* c, const int* slots, const FieldBatch& xi, const FieldBatch& out, double tol, int maxit) {
   const int np = xi.nprop, nrb = xi.nrhs;
+  Links L = links_of(c, slots, np, LK_F64);
   FieldBatch t1 = field(c, "sc_t1", P_F64, np, nrb);
   FieldBatch t2 = field(c, "sc_t2", P_F64, np, nrb);
   {
@@ -748,13 +872,13 @@ double schur_apply(psms_ctx* c, const Links& L, const FieldBatch& xi, const Fiel
     launch_zero(c->st, t1, c->Vh);
   }
   dslash(c, L, xi, t1, HOP_CROSS, 1, 0.0, -c->geom.kappa, 0);  // D_wb xi (white sites)
-  double r1 = solve_colour(c, L, 1, t1, t2, tol, maxit, nullptr);  // D_ww^-1
+  double r1 = solve_colour(c, slots, 1, t1, t2, tol, maxit, nullptr);  // D_ww^-1
   {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_zero(c->st, t1, c->Vh);
   }
   dslash(c, L, t2, t1, HOP_CROSS, 0, 0.0, -c->geom.kappa, 0);  // D_bw (black sites)
-  double r2 = solve_colour(c, L, 0, t1, t2, tol, maxit, nullptr);  // D_bb^-1
+  double r2 = solve_colour(c, slots, 0, t1, t2, tol, maxit, nullptr);  // D_bb^-1
   {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_project(c->st, c->g, t2, t1);
@@ -973,7 +1097,7 @@ void psms_default_params(psms_solve_params* p) {
   p->prec = PSMS_F64;
   p->pc = PSMS_PC_SAP;
   p->sap_cycles = 4;
-  p->block_iters = 4;
+  p->block_iters = 6;
   p->inner_tol = 1e-2;
   p->inner_storage = PSMS_SPINOR_F32;
   p->net_fallback = 1;
@@ -1019,18 +1143,19 @@ void psms_destroy(psms_ctx* c) {
   (void)hipStreamSynchronize(c->st);
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
-  for (auto& s : c->slots) {
-    if (s.f64) (void)hipFree(s.f64);
-    if (s.c12) (void)hipFree(s.c12);
-  }
-  if (c->d_lcoord) (void)hipFree(c->d_lcoord);
-  if (c->d_bcoord) (void)hipFree(c->d_bcoord);
-  if (c->d_border) (void)hipFree(c->d_border);
+  for (auto& s : c->slots)
+    for (void* p : {s.f64, s.c12, s.f64_s, s.c12_s})
+      if (p) (void)hipFree(p);
+  for (void* p : c->geo_mem) (void)hipFree(p);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
+  for (auto p : c->pinned)
+    if (p) (void)hipHostFree(p);
+  for (auto e : c->rn_ev)
+    if (e) (void)hipEventDestroy(e);
   net_free(c);
   delete c;
 }
@@ -1050,6 +1175,12 @@ psms_status psms_gauge_load(psms_ctx* c, int slot, const double* U) {
   if (!s.c12) s.c12 = dev_alloc(c, size_t(c->V) * 4 * 3 * 16);
   launch_pack_links(c->st, c->g, dU, s.f64, LK_F64);
   launch_pack_links(c->st, c->g, dU, s.c12, LK_F32C12);
+  if (c->split) {
+    if (!s.f64_s) s.f64_s = dev_alloc(c, size_t(c->V) * 4 * 9 * 16);
+    if (!s.c12_s) s.c12_s = dev_alloc(c, size_t(c->V) * 4 * 3 * 16);
+    launch_pack_links(c->st, c->gs, dU, s.f64_s, LK_F64);
+    launch_pack_links(c->st, c->gs, dU, s.c12_s, LK_F32C12);
+  }
   const int nwg = 256;
   double* part = dscratch<double>(c, "unit_partial", nwg);
   launch_unitarity(c->st, c->g, dU, part, nwg);
@@ -1220,7 +1351,7 @@ psms_status psms_solve_block(psms_ctx* c, int slot, int colour, const double* b,
   FieldBatch b64 = field(c, "api_b64", P_F64, 1, nrhs), x64 = field(c, "api_x64", P_F64, 1, nrhs);
   launch_pack(c->st, c->g, db, b64);
   int iters = 0;
-  double rel = solve_colour(c, L, colour, b64, x64, pp->tol, pp->max_iter, &iters);
+  double rel = solve_colour(c, &slot, colour, b64, x64, pp->tol, pp->max_iter, &iters);
   launch_unpack(c->st, c->g, x64, dx);
   finish_out(c, x, dx, nd);
   FullSolveOut o;
@@ -1250,7 +1381,7 @@ psms_status psms_apply_schur(psms_ctx* c, int slot, const double* in, double* ou
   Links L = links_of(c, &slot, 1, LK_F64);
   FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
   launch_pack(c->st, c->g, din, a);
-  double rel = schur_apply(c, L, a, b, pp->tol, pp->max_iter);
+  double rel = schur_apply(c, &slot, a, b, pp->tol, pp->max_iter);
   launch_unpack(c->st, c->g, b, dout);
   finish_out(c, out, dout, nd);
   FullSolveOut o;
@@ -1316,7 +1447,7 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
     double* xin2 = dscratch<double>(c, "ld_xin2", nj);
     if (op == PSMS_OP_SCHUR) {
       launch_project(c->st, c->g, eta, xi);
-      double rel = schur_apply(c, LU, xi, phi, pp->tol, pp->max_iter);
+      double rel = schur_apply(c, &slot_U, xi, phi, pp->tol, pp->max_iter);
       if (!(rel <= pp->tol * 1.0001)) agg.converged = false;
     } else {
       launch_copy(c->st, c->g, eta, xi, nullptr);
@@ -1613,10 +1744,11 @@ static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "nr_low")) return &c->nr_low;
   if (!std::strcmp(key, "xcd_map")) return &c->xcd_map;
   if (!std::strcmp(key, "net_mfma")) return &c->net_mfma;
+  if (!std::strcmp(key, "block_solver")) return &c->block_solver;
   return nullptr;
 }
 static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
-                                    "xcd_map", "net_mfma"};
+                                    "xcd_map", "net_mfma", "block_solver"};
 
 psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   API_BEGIN(c)
@@ -1624,7 +1756,8 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   int* t = tuning_slot(c, key);
   REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
   if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 5, "stencil variant must be in [0, 5]");
-  else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma")) REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
+  else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
+    REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
   else REQUIRE(value == 1 || value == 2 || value == 4, "right-hand sides per thread must be 1, 2 or 4");
   *t = value;
   API_END(c)

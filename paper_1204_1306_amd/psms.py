@@ -34,7 +34,8 @@ class PsmsError(RuntimeError):
 
 
 class Geom(C.Structure):
-    _fields_ = [("L", C.c_int * 4), ("b", C.c_int * 4), ("antiperiodic_t", C.c_int), ("kappa", C.c_double)]
+    _fields_ = [("L", C.c_int * 4), ("b", C.c_int * 4), ("antiperiodic_t", C.c_int), ("kappa", C.c_double),
+                ("sap_b", C.c_int * 4)]
 
 
 class SolveParams(C.Structure):
@@ -155,13 +156,14 @@ def _empty_like(a):
 class Context:
     """One libpsms context (geometry, device, stream)."""
 
-    def __init__(self, L, b, kappa: float, antiperiodic: bool = True, device: int = 0, stream=None):
+    def __init__(self, L, b, kappa: float, antiperiodic: bool = True, device: int = 0, stream=None, sap_b=None):
         lib = load_library()
         g = Geom()
         g.L[:] = list(L)
         g.b[:] = list(b)
         g.antiperiodic_t = 1 if antiperiodic else 0
         g.kappa = float(kappa)
+        g.sap_b[:] = list(sap_b) if sap_b is not None else [0, 0, 0, 0]
         self.L, self.b, self.kappa = tuple(L), tuple(b), float(kappa)
         self.V = int(np.prod(L))
         h = C.c_void_p()
@@ -336,7 +338,7 @@ class Context:
 
     # ---------------------------------------------------------------- tuning
     TUNING_KEYS = ("dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low", "xcd_map",
-                   "net_mfma")
+                   "net_mfma", "block_solver")
 
     def set_tuning(self, key: str, value: int):
         self._check(self._lib.psms_set_tuning(self._h, key.encode(), int(value)))

@@ -176,7 +176,8 @@ WORKLOADS = {
     "c4": dict(L=(16, 16, 16, 16), b=(4, 4, 4, 4), kappa=0.157, eps=0.6, eps_prime=(0.02, 0.1),
                nprop=1, nnoise=8, seed_U=4999, seed_Up=4899, seed_noise=4501, tol=1e-10),
     "c5": dict(L=(32, 32, 32, 32), b=(8, 8, 8, 8), kappa=0.1575, eps=0.6, eps_prime=(0.02, 0.1),
-               nprop=4, nnoise=32, seed_U=5001, seed_Up=5101, seed_noise=5501, tol=1e-10),
+               nprop=4, nnoise=32, seed_U=5001, seed_Up=5101, seed_noise=5501, tol=1e-10,
+               sap_b=(4, 4, 4, 4)),
 }
 
 
