@@ -67,18 +67,42 @@ def setup(workload: str, nprop=None, nnoise=None):
     return psms, ctx, w, noise, delta, len(Ups)
 
 
-FAMILIES = ("dslash", "dslash_part", "block_mr", "blas", "net")
+FAMILIES = ("dslash", "dslash_part", "block_mr", "block_solve", "blas", "net")
+
+# HBM bytes per launch of a kernel family, from two rocprofv3 counter passes over this
+# benchmark (FETCH_SIZE, then WRITE_SIZE; the summaries are in profiles/), each scaled
+# by the factor that makes the counter read the known byte count of the plain copy
+# kernel of the same run (copy_ceiling). Keyed by (family, workload, mode). A figure
+# holds only for the kernel source it was taken on: `sha256` is that of the file
+# holding the kernel, and a changed file turns the figure into null.
+TRAFFIC = {}
+
+
+def traffic_for(family: str, workload: str, mode: str):
+    import hashlib
+
+    t = TRAFFIC.get((family, workload, mode))
+    if not t:
+        return None
+    path = os.path.join(ROOT, "paper_1204_1306_amd", "csrc", t["source"])
+    try:
+        with open(path, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+                return None
+    except OSError:
+        return None
+    return t["bytes_per_launch"]
 
 
 def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=False):
+    """Times `steps` unprofiled steps; with `profile`, then runs the same number of steps
+    again with per-family kernel timing (the event bookkeeping is kept out of the timed
+    region, where it would add to every launch of a latency-bound step)."""
     import torch
 
     slots = list(range(1, 1 + nprop))
     for _ in range(warmup):
         ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise, params, delta=delta)
-    torch.cuda.synchronize()
-    if profile:
-        ctx.profile(True)
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -87,11 +111,16 @@ def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=Fal
         stats.append(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    d = delta.cpu().numpy().copy()
     fam = {}
     if profile:
+        ctx.profile(True)
+        for _ in range(steps):
+            ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise, params, delta=delta)
+        torch.cuda.synchronize()
         fam = {f: ctx.profile_read(f) for f in FAMILIES}
         ctx.profile(False)
-    return dt, stats, fam, delta.cpu().numpy().copy()
+    return dt, stats, fam, d
 
 
 def dw_bandwidth(psms, L, b, kappa, reps=20):
@@ -123,6 +152,29 @@ def dw_bandwidth(psms, L, b, kappa, reps=20):
     return out
 
 
+def copy_ceiling(mib=512, reps=10):
+    """A plain device copy of known size (an elementwise kernel reading and writing
+    `mib` MiB each way): the achievable HBM rate on this GPU, and the kernel against
+    which the HBM byte counters of a profiled run are calibrated."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * n * 4
+    del src, dst
+    return {"bytes_per_launch": nbytes, "us_per_launch": round(1e3 * ms, 2), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def learned_leg(psms, ctx, w, noise, delta, nprop, steps, npairs):
     """Train the gauge-covariant network on seeded configurations of the workload's
     geometry (outside the timed region), then time the estimator with it as the right
@@ -144,6 +196,30 @@ def learned_leg(psms, ctx, w, noise, delta, nprop, steps, npairs):
     dt, st, fam, d = run_steps(psms, ctx, noise, delta, nprop, prm, steps, 1, profile=True)
     return {"s_per_estimate": dt / steps / (nprop * noise.shape[0]), "train_seconds": t_train, "train": tr,
             "solver": st[-1], "net_ms_per_step": fam["net"]["ms"] / steps}, d
+
+
+def batched_leg(psms, workload: str, steps: int, rhs_chunk: int):
+    """The batched workload (all proposals x noise vectors of it in one call), with
+    BF16 Krylov storage and FP32 inner solves against plain FP64, same tolerance."""
+    import torch
+
+    _, ctx, w, noise, delta, nprop = setup(workload)
+    ctx.autotune(0, None)
+    nest = nprop * noise.shape[0]
+    out = {"workload": workload, "estimates_per_step": nest, "rhs_chunk": rhs_chunk}
+    d = {}
+    for mode in ("mixed_bf16", "plain"):
+        prm = mode_params(psms, mode, w["tol"])
+        prm.rhs_chunk = rhs_chunk
+        dt, st, _, d[mode] = run_steps(psms, ctx, noise, delta, nprop, prm, steps, 1)
+        out[mode] = {"s_per_estimate": dt / steps / nest, "ms_per_step": 1e3 * dt / steps, "solver": st[-1]}
+        log(f"batched {workload} {mode}: {1e3 * dt / steps:.1f} ms/step")
+    out["speedup_vs_plain_f64"] = out["plain"]["s_per_estimate"] / out["mixed_bf16"]["s_per_estimate"]
+    out["max_abs_delta_diff"] = float(np.abs(d["mixed_bf16"] - d["plain"]).max())
+    ctx.close()
+    del noise, delta
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(workload: str, budget_s: float = 20.0):
@@ -226,6 +302,9 @@ def main():
     ap.add_argument("--learned-pairs", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--dw-lattice", default="32,32,32,32")
+    ap.add_argument("--batched-workload", default="c3", help="'none' skips the batched leg")
+    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--batched-rhs-chunk", type=int, default=128)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -266,6 +345,15 @@ def main():
         except Exception as e:  # reported, not hidden
             learned = {"error": repr(e)}
 
+    batched = None
+    if args.batched_workload != "none":
+        try:
+            batched = batched_leg(psms, args.batched_workload, args.batched_steps, args.batched_rhs_chunk)
+        except Exception as e:  # reported, not hidden
+            batched = {"error": repr(e)}
+
+    copy = copy_ceiling()
+    log(f"copy: {copy}")
     dwL = tuple(int(v) for v in args.dw_lattice.split(","))
     dw = dw_bandwidth(psms, dwL, tuple(max(2, v // 4) for v in dwL), w["kappa"])
     log(f"D_w: {dw}")
@@ -276,7 +364,7 @@ def main():
     ach = fam[dom]["bytes"] / (fam[dom]["ms"] * 1e-3) / 1e9
     total_ms = sum(v["ms"] for v in fam.values())
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, args.workload, args.mode), "kernel": dom,
             "us_per_launch": round(1e3 * fam[dom]["ms"] / fam[dom]["launches"], 2),
             "bytes_per_launch": fam[dom]["bytes"] / fam[dom]["launches"],
             "time_share": round(fam[dom]["ms"] / max(total_ms, 1e-9), 3),
@@ -303,11 +391,13 @@ def main():
         "speedup_vs_plain_f64": s_plain / value,
         "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
         "learned": learned,
+        "batched": batched,
         "dw_lattice": dw["lattice"],
         "dw_gbs": {k: round(v["gbs"], 1) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
         "dw_us_per_launch": {k: round(v["us_per_launch"], 2) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
         "dw_frac_of_hbm_peak": {k: round(v["gbs"] / HBM_PEAK_GBS, 4) for k, v in dw.items()
                                 if isinstance(v, dict) and "gbs" in v},
+        "copy_ceiling": copy,
         "solver": {"fast": stats[-1], "plain": stp[-1]},
         "tuning": tune,
         "roofline": roof,

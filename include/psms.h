@@ -212,8 +212,10 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
  * per site, times three register budgets), "nr_f64", "nr_low" (right-hand sides per
  * stencil thread: 1, 2 or 4), "xcd_map" (1: each XCD sweeps a contiguous range of
  * tiles), "net_mfma" (1: network channel mixing on the matrix cores in bf16, 0: FP32 on
- * the vector units) and "block_solver" (block inverses to tolerance: 0 minimal residual
- * per block, 1 flexible GCR on the block-diagonal operator). Unknown keys or values give
+ * the vector units), "block_solver" (block inverses to tolerance: 0 minimal residual
+ * per block, 1 flexible GCR on the block-diagonal operator) and "block_lanes" (block
+ * solver for 256-site blocks with 12-real links: 1 or 2 lanes per site, 0 = two lanes
+ * when the launch has fewer than two workgroups per compute unit). Unknown keys or values give
  * PSMS_EINVAL. Results do not depend on the tuning beyond rounding; only speed does. */
 psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);
 psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);
@@ -226,7 +228,8 @@ psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);
 psms_status psms_autotune(psms_ctx* ctx, int slot, const char* cache_path);
 
 /* Kernel timing with HIP events on the context's stream. enable=1 starts recording
- * the launches of the named kernel families ("dslash", "block_mr", "blas", "net"),
+ * the launches of the named kernel families ("dslash", "dslash_part", "block_mr" (Schwarz sweeps),
+ * "block_solve" (block inverses to a tolerance), "blas", "net"),
  * 0 stops. psms_profile_read gives the total milliseconds, launch count and
  * algorithmic bytes moved since the last enable. */
 psms_status psms_profile(psms_ctx* ctx, int enable);

@@ -175,7 +175,7 @@ struct Geo {
   int apbc;
   const uint32_t* lcoord;  // [2][Vbh] local coords of (parity, i), 8 bits each
   const uint32_t* bcoord;  // [nblk] block coords of blk, 8 bits each
-  const int* border;       // [nblk] blocks in Morton order of their block coordinates
+  const int* border;       // [nblk] the order in which the stencil visits blocks (black, then its white neighbour)
 };
 
 // Everything the stencil needs about one site.
@@ -310,5 +310,32 @@ template <class T> __device__ __forceinline__ T wave_sum(T v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+// The same sum through the data-parallel-primitive (DPP) lane network, for waves
+// whose 64 lanes are all active: xor-1 and xor-2 swaps inside quads, then the
+// half-row and row mirrors give every lane of a 16-lane row the row's sum (each step
+// pairs lanes holding equal partial sums, so the mirrors act as xor-4 and xor-8);
+// the four row sums are then added in a fixed order from lanes 0, 16, 32 and 48.
+// No LDS round trips, deterministic, and the result is wave-uniform.
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]: xor 1
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]: xor 2
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+// Every FP64 wave sum of the library runs on full waves (all call sites reduce after
+// workgroup-uniform loops), so the overload for double takes the DPP form.
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 }  // namespace psms

@@ -1,5 +1,6 @@
 // Host-side launchers of the HIP kernels (internal to libpsms; not the C-ABI).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -9,6 +10,27 @@
 namespace psms {
 
 constexpr int MAXPROP = 16;  // proposals (gauge fields) addressed by one launch
+
+// Kernel-bracketing timer. While armed (t_kernel_timer set), launches made through
+// launch_timed take `start` at the first kernel's start and `stop` at the end of
+// the latest kernel (hipExtLaunchKernelGGL), so the measured span is the kernels'
+// own duration without the dispatch gaps that separate event records add.
+struct KernelTimer {
+  hipEvent_t start, stop;
+  bool used;
+};
+extern thread_local KernelTimer* t_kernel_timer;
+
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st, Args... args) {
+  KernelTimer* t = t_kernel_timer;
+  if (!t) {
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, shm, st, t->used ? nullptr : t->start, t->stop, 0u, args...);
+  t->used = true;
+}
 
 enum HopSel : int { HOP_ALL = 0, HOP_INTRA = 1, HOP_CROSS = 2 };
 enum LinkFmt : int { LK_F64 = 0, LK_F32C12 = 1 };
@@ -82,8 +104,11 @@ struct BlockMRParams {
   int niter;
   double tol;     // >0: stop a block when |r_b| <= tol |rho_b(initial)|
   double kappa;
+  int face = 0;   // 1: first rho_b -= D_{b,other} delta_other across the block faces
+  int lanes = 0;  // LDS-resident 256-site blocks: lanes per site (1, 2; 0 = by grid size)
 };
-// For every block of the colour: delta = MR approximation of D_b^-1 rho_b, x += delta,
+// For every block of the colour: (optionally) the face update of rho_b from the
+// other colour's delta, then delta = MR approximation of D_b^-1 rho_b, x += delta,
 // rho_b <- rho_b - D_b delta. pbuf is scratch of the same shape.
 void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& rho,
                      const FieldBatch& x, const FieldBatch& delta, const FieldBatch& pbuf, const BlockMRParams& bp,

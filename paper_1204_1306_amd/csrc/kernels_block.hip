@@ -19,8 +19,42 @@ struct BlockArgs {
   size_t rhs_stride;  // units
   int nrhs, colour, niter;
   double tol, kappa;
+  int face;  // 1: first apply the residual update across the block faces (see face_update)
+  int lanes;  // LDS-resident form: 1 or 2 lanes per site (0: by grid size)
   int* iters;
 };
+
+// Schwarz residual update across the faces of a block of colour c:
+// rho_c -= D_{c,c'} delta_c', i.e. acc += kappa * (the hops of site (p, s) that
+// leave its block, applied to delta of the neighbouring blocks, which all have the
+// other colour c' and hold the deltas of that colour's last sweep). Only sites of
+// the other colour are read, so the blocks of colour c can update in parallel.
+template <class S, class LK, class T>
+__device__ __forceinline__ void face_update(const Geo& g, const typename LK::unit* __restrict__ lk,
+                                            const typename S::unit* __restrict__ dl, int p, int s, T kp, Spinor<T>& acc) {
+  const size_t Vh = g.Vh;
+  SiteInfo si;
+  site_info(g, p, s, si);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    Nbr n = neighbour(g, si, mu, +1);
+    if (n.cross) {
+      SU3<T> U;
+      LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+      Spinor<T> nb;
+      S::load(dl + size_t(1 - p) * S::NC * Vh, Vh, n.s, nb);
+      hop_fwd(mu, U, nb, kp * T(n.sign), acc);
+    }
+    n = neighbour(g, si, mu, -1);
+    if (n.cross) {
+      SU3<T> U;
+      LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+      Spinor<T> nb;
+      S::load(dl + size_t(1 - p) * S::NC * Vh, Vh, n.s, nb);
+      hop_bwd(mu, U, nb, kp * T(n.sign), acc);
+    }
+  }
+}
 
 // (D_b r)(x) for one site: r(x) - kappa * sum of the intra-block hops.
 template <class S, class LK, class T>
@@ -108,12 +142,16 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   const int nsite = 2 * g.Vbh;
   const T mk = T(-a.kappa);
 
-  // delta = 0, |rho_b|^2
+  // rho_b += face update (optional), delta = 0, |rho_b|^2
   double b2 = 0.0;
   for (int j = threadIdx.x; j < nsite; j += blockDim.x) {
     int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
     Spinor<T> v, z;
     S::load(rho + size_t(p) * S::NC * Vh, Vh, s, v);
+    if (a.face) {
+      face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), v);
+      S::store(rho + size_t(p) * S::NC * Vh, Vh, s, v);
+    }
     zero(z);
     S::store(dl + size_t(p) * S::NC * Vh, Vh, s, z);
 #pragma unroll
@@ -245,6 +283,7 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
   }
   Spinor<T> r, d;
   S::load(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+  if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), r);
   zero(d);
   double b2 = 0.0;
 #pragma unroll
@@ -338,15 +377,178 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
   if (a.iters && t == 0) atomicMax(a.iters, it);
 }
 
+
+// Two lanes per site (512 threads, LDS-resident links for 12-real link storage):
+// waves 0-3 take the forward hops, the MR update and the residual of their site;
+// waves 4-7 take the backward hops and hand their partial sum over through LDS.
+// Twice the waves per block hide the LDS and barrier latency of a block solve
+// whose grid is too small to give every SIMD more than one wave.
+template <class S, class LK, class T>
+__global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
+  constexpr int VB = 256;
+  static_assert(LdsLinks<LK>::on, "two-lane form stages 12-real links in LDS");
+  __shared__ cx<T> r_lds[12][VB];
+  __shared__ cx<T> q_lds[12][VB];
+  __shared__ float4 lk_lds[4 * 3][VB];
+  __shared__ double sm[3][16];
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int blk = a.colour * g.nblk_c + blockIdx.x;
+  const int prop = blockIdx.z;
+  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  using unit = typename S::unit;
+  unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  unit* x = reinterpret_cast<unit*>(a.x) + roff;
+  unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const T mk = T(-a.kappa);
+  const int t = threadIdx.x & (VB - 1);
+  const int h = threadIdx.x >> 8;  // wave-uniform: 0 forward hops, 1 backward hops
+  const int Vbh = VB / 2;
+  const int p = t < Vbh ? 0 : 1;
+  const int s = blk * Vbh + (t - p * Vbh);
+
+  int nbt[4];  // neighbour thread of this lane's four hops (-1: leaves the block)
+  {
+    SiteInfo si;
+    site_info(g, p, s, si);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      Nbr n = neighbour(g, si, mu, h == 0 ? +1 : -1);
+      nbt[mu] = n.cross ? -1 : (1 - p) * Vbh + (n.s - blk * Vbh);
+    }
+  }
+  // each half stages the link planes of two directions
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int mu = 2 * h + k / 3, kk = k % 3;
+    lk_lds[mu * 3 + kk][t] = reinterpret_cast<const float4*>(lk)[(size_t(p * 4 + mu) * 3 + kk) * Vh + s];
+  }
+  Spinor<T> r, d;
+  zero(r);
+  zero(d);
+  double b2 = 0.0;
+  if (h == 0) {
+    S::load(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+    if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), r);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) b2 += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+  }
+  b2 = wg_sum(b2, sm[0]);
+  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
+
+  int it = 0;
+  if (b2 > 0.0) {
+    for (; it < a.niter; ++it) {
+      if (h == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) r_lds[k][t] = r.v[k / 3][k % 3];
+      }
+      __syncthreads();
+      Spinor<T> acc;
+      if (h == 0) acc = r;
+      else zero(acc);
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        const int tn = nbt[mu];
+        if (tn >= 0) {
+          SU3<T> U;
+          const int lt = h == 0 ? t : tn;  // forward hop: own link; backward: the neighbour's
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            float4 v = lk_lds[mu * 3 + k][lt];
+            U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
+            U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
+          }
+          cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
+          cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
+          cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
+          U.m[2][0] = {c0.re, -c0.im};
+          U.m[2][1] = {c1.re, -c1.im};
+          U.m[2][2] = {c2.re, -c2.im};
+          Spinor<T> nb;
+#pragma unroll
+          for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = r_lds[k][tn];
+          if (h == 0) hop_fwd(mu, U, nb, mk, acc);
+          else hop_bwd(mu, U, nb, mk, acc);
+        }
+      }
+      if (h == 1) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q_lds[k][t] = acc.v[k / 3][k % 3];
+      }
+      __syncthreads();
+      double prr = 0.0, pri = 0.0, pp = 0.0;
+      if (h == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = acc.v[k / 3][k % 3] + q_lds[k][t];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double ar = acc.v[q][c].re, ai = acc.v[q][c].im, br = r.v[q][c].re, bi = r.v[q][c].im;
+            prr += ar * br + ai * bi;
+            pri += ar * bi - ai * br;
+            pp += ar * ar + ai * ai;
+          }
+      }
+      wg_sum3(prr, pri, pp, sm);
+      if (!(pp > 0.0)) break;
+      const cx<T> alpha = {T(prr / pp), T(pri / pp)};
+      double rr = 0.0;
+      if (h == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            d.v[q][c] = d.v[q][c] + cmul(alpha, r.v[q][c]);
+            r.v[q][c] = r.v[q][c] - cmul(alpha, acc.v[q][c]);
+            rr += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+          }
+      }
+      if (stop2 > 0) {
+        rr = wg_sum(rr, sm[0]);
+        if (rr <= stop2) {
+          ++it;
+          break;
+        }
+      }
+    }
+  }
+  if (h == 0) {
+    S::store(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+    S::store(dl + size_t(p) * S::NC * Vh, Vh, s, d);
+    Spinor<T> xv;
+    S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
+    S::store(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+    if (a.iters && t == 0) atomicMax(a.iters, it);
+  }
+}
+
 template <class S, class LK, class T>
 static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
   if (2 * a.g.Vbh == 256) {
-    hipLaunchKernelGGL((k_block_mr_lds<S, LK, T, 256>), dim3(a.g.nblk_c, a.nrhs, nprop), dim3(256), 0, st, a);
+    const dim3 grid(a.g.nblk_c, a.nrhs, nprop);
+    if constexpr (LdsLinks<LK>::on) {
+      // two lanes per site when the grid gives fewer than two workgroups per CU
+      const int lanes = a.lanes > 0 ? a.lanes : (grid.x * grid.y * grid.z < 512 ? 2 : 1);
+      if (lanes == 2) {
+        launch_timed((k_block_mr_lds2<S, LK, T>), grid, dim3(512), 0, st, a);
+        return;
+      }
+    }
+    launch_timed((k_block_mr_lds<S, LK, T, 256>), grid, dim3(256), 0, st, a);
     return;
   }
   dim3 grid(a.g.nblk_c, a.nrhs, nprop);
   int threads = 2 * a.g.Vbh < 256 ? ((2 * a.g.Vbh + 63) / 64) * 64 : 256;
-  hipLaunchKernelGGL((k_block_mr<S, LK, T>), grid, dim3(threads), 0, st, a);
+  launch_timed((k_block_mr<S, LK, T>), grid, dim3(threads), 0, st, a);
 }
 
 void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& rho,
@@ -365,6 +567,8 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
   a.niter = bp.niter;
   a.tol = bp.tol;
   a.kappa = bp.kappa;
+  a.face = bp.face;
+  a.lanes = bp.lanes;
   a.iters = iters_out;
   if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);
   else if (rho.prec == P_F32 && linkfmt == LK_F32C12) block_go<StF32, LkF32C12, float>(st, a, rho.nprop);

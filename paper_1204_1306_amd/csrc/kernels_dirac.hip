@@ -233,14 +233,14 @@ template <class SI, class SO, class LK, class T, int W>
 static void dslash_split_go(hipStream_t st, const DslashArgs& a, int nprop) {
   int tiles = a.np * ((a.nb * a.g.Vbh + 127) / 128);
   dim3 grid(tiles, a.nrhs, nprop);
-  hipLaunchKernelGGL((k_dslash_split<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
+  launch_timed((k_dslash_split<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
 }
 
 template <class SI, class SO, class LK, class T, int W>
 static void dslash_one_go(hipStream_t st, const DslashArgs& a, int nprop) {
   int tiles = a.np * ((a.nb * a.g.Vbh + 255) / 256);
   dim3 grid(tiles, a.nrhs, nprop);
-  hipLaunchKernelGGL((k_dslash<SI, SO, LK, T, HOP_ALL, 1, W>), grid, dim3(256), 0, st, a);
+  launch_timed((k_dslash<SI, SO, LK, T, HOP_ALL, 1, W>), grid, dim3(256), 0, st, a);
 }
 
 // Full-lattice stencil variants (form x register budget), chosen by the autotuner:
@@ -263,7 +263,7 @@ template <class SI, class SO, class LK, class T, int SEL, int NR>
 static void dslash_go(hipStream_t st, const DslashArgs& a, int nprop) {
   int tiles = a.np * ((a.nb * a.g.Vbh + 255) / 256);
   dim3 grid(tiles, (a.nrhs + NR - 1) / NR, nprop);
-  hipLaunchKernelGGL((k_dslash<SI, SO, LK, T, SEL, NR>), grid, dim3(256), 0, st, a);
+  launch_timed((k_dslash<SI, SO, LK, T, SEL, NR>), grid, dim3(256), 0, st, a);
 }
 
 template <class SI, class SO, class LK, class T, int SEL>

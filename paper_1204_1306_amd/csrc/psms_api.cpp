@@ -57,8 +57,9 @@ struct ProfRec {
   double bytes;
 };
 
-enum Fam { FAM_DSLASH = 0, FAM_DSLASH_PART, FAM_BLOCK, FAM_BLAS, FAM_NET, NFAM };
-const char* fam_names[NFAM] = {"dslash", "dslash_part", "block_mr", "blas", "net"};
+enum Fam { FAM_DSLASH = 0, FAM_DSLASH_PART, FAM_BLOCK, FAM_BLOCK_SOLVE, FAM_BLAS, FAM_NET, NFAM };
+// block_mr: Schwarz sweeps (fixed iterations); block_solve: block inverses to a tolerance
+const char* fam_names[NFAM] = {"dslash", "dslash_part", "block_mr", "block_solve", "blas", "net"};
 
 }  // namespace
 
@@ -74,6 +75,7 @@ struct psms_ctx {
   bool solver_view = false;    // links_of hands out the solver-layout links
   int op_colour = -1;          // >= 0: the solver's operator is D_cc of that colour
   int block_solver = 0;        // block inverses to tolerance: 0 minimal residual, 1 flexible GCR
+  int block_lanes = 0;         // LDS-resident block solver: lanes per site (1, 2; 0 = by grid size)
   // pinned host slots for the lagged convergence check of the GCR iteration
   double* pinned[2] = {nullptr, nullptr};
   size_t pinned_n = 0;
@@ -187,21 +189,45 @@ hipEvent_t get_event(psms_ctx* c) {
   return e;
 }
 
+}  // namespace
+thread_local psms::KernelTimer* psms::t_kernel_timer = nullptr;
+namespace {
+
+// Times one family's work on the library's stream. The stencil and block-solver
+// families launch through launch_timed, so their span runs from the first kernel's
+// start to the last kernel's end (what a kernel trace reports); the other families
+// are bracketed by event records.
 struct ProfScope {
   psms_ctx* c;
   int fam;
   double bytes;
   hipEvent_t a{}, b{};
+  KernelTimer kt{};
+  bool kernel_timed = false;
   ProfScope(psms_ctx* c_, int fam_, double bytes_) : c(c_), fam(fam_), bytes(bytes_) {
     if (c->prof) {
       a = get_event(c);
       b = get_event(c);
-      HIPCHK(hipEventRecord(a, c->st));
+      kernel_timed = fam == FAM_DSLASH || fam == FAM_DSLASH_PART || fam == FAM_BLOCK || fam == FAM_BLOCK_SOLVE;
+      if (kernel_timed) {
+        kt = KernelTimer{a, b, false};
+        t_kernel_timer = &kt;
+      } else {
+        HIPCHK(hipEventRecord(a, c->st));
+      }
     }
   }
   ~ProfScope() {
     if (c->prof) {
-      (void)hipEventRecord(b, c->st);
+      if (kernel_timed) {
+        t_kernel_timer = nullptr;
+        if (!kt.used) {  // nothing was launched: an empty span
+          (void)hipEventRecord(a, c->st);
+          (void)hipEventRecord(b, c->st);
+        }
+      } else {
+        (void)hipEventRecord(b, c->st);
+      }
       c->recs.push_back(ProfRec{fam, a, b, bytes});
     }
   }
@@ -412,10 +438,17 @@ struct SapCfg {
 };
 
 // Algorithmic bytes of one block-solver launch over the blocks of one colour: the
-// block's links once, rho and x read and written once, delta written once.
-double block_bytes(psms_ctx* c, const Links& L, const FieldBatch& rho) {
+// block's links once, rho and x read and written once, delta written once; with the
+// face update, also the link and the neighbour's delta of every hop leaving a block.
+double block_bytes(psms_ctx* c, const Links& L, const FieldBatch& rho, int face = 0) {
   double sites = double(c->Vh);  // one colour = half the lattice
-  return sites * rho.nprop * (4 * link_bytes(L.fmt) + rho.nrhs * 5 * spinor_bytes(rho.prec));
+  double b = sites * rho.nprop * (4 * link_bytes(L.fmt) + rho.nrhs * 5 * spinor_bytes(rho.prec));
+  if (face) {
+    double hops = 0;  // hops leaving a block, over the sites of one colour
+    for (int m = 0; m < 4; ++m) hops += 2.0 * sites / c->g.b[m];
+    b += hops * rho.nprop * (link_bytes(L.fmt) + rho.nrhs * spinor_bytes(rho.prec));
+  }
+  return b;
 }
 
 // z = SAP(r): multiplicative Schwarz over black then white blocks, MR block solves.
@@ -430,15 +463,15 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
     launch_copy(c->st, c->g, r, rho, nullptr);
     launch_zero(c->st, xs, c->Vh);
   }
+  // Each sweep first applies rho_col -= D_{col,other} delta_other across its block
+  // faces (fused into the block kernel), except the very first, where no delta exists.
   for (int cy = 0; cy < sc.cycles; ++cy) {
     for (int col = 0; col < 2; ++col) {
       BlockMRParams bp{col, sc.iters, 0.0, c->geom.kappa};
-      {
-        ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho));
-        launch_block_mr(c->st, c->g, L.p, L.fmt, rho, xs, dl, pb, bp, nullptr);
-      }
-      if (!(cy == sc.cycles - 1 && col == 1))  // rho on the other colour -= D_{other,col} delta
-        dslash(c, L, dl, rho, HOP_CROSS, 1 - col, 0.0, c->geom.kappa, 1);
+      bp.face = (cy > 0 || col > 0) ? 1 : 0;
+      bp.lanes = c->block_lanes;
+      ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho, bp.face));
+      launch_block_mr(c->st, c->g, L.p, L.fmt, rho, xs, dl, pb, bp, nullptr);
     }
   }
   ProfScope ps(c, FAM_BLAS, 0);
@@ -828,12 +861,11 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
     launch_keep_colour(c->st, c->g, rho, col);
     launch_zero(c->st, x, c->Vh);
   }
-  const int zero_i = 0;
-  HIPCHK(hipMemcpyAsync(it, &zero_i, sizeof(int), hipMemcpyHostToDevice, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipMemsetAsync(it, 0, sizeof(int), c->st));
   {
-    ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho));
+    ProfScope ps(c, FAM_BLOCK_SOLVE, block_bytes(c, L, rho));
     BlockMRParams bp{col, maxit, tol, c->geom.kappa};
+    bp.lanes = c->block_lanes;
     launch_block_mr(c->st, c->g, L.p, L.fmt, rho, x, dl, pb, bp, it);
   }
   if (iters_host) HIPCHK(hipMemcpyAsync(iters_host, it, sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -1745,10 +1777,11 @@ static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "xcd_map")) return &c->xcd_map;
   if (!std::strcmp(key, "net_mfma")) return &c->net_mfma;
   if (!std::strcmp(key, "block_solver")) return &c->block_solver;
+  if (!std::strcmp(key, "block_lanes")) return &c->block_lanes;
   return nullptr;
 }
 static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
-                                    "xcd_map", "net_mfma", "block_solver"};
+                                    "xcd_map", "net_mfma", "block_solver", "block_lanes"};
 
 psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   API_BEGIN(c)
@@ -1758,6 +1791,8 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 5, "stencil variant must be in [0, 5]");
   else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
+  else if (!std::strcmp(key, "block_lanes"))
+    REQUIRE(value >= 0 && value <= 2, "lanes per site must be 0 (by grid size), 1 or 2");
   else REQUIRE(value == 1 || value == 2 || value == 4, "right-hand sides per thread must be 1, 2 or 4");
   *t = value;
   API_END(c)
