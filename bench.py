@@ -75,7 +75,14 @@ FAMILIES = ("dslash", "dslash_part", "block_mr", "block_solve", "blas", "net")
 # kernel of the same run (copy_ceiling). Keyed by (family, workload, mode). A figure
 # holds only for the kernel source it was taken on: `sha256` is that of the file
 # holding the kernel, and a changed file turns the figure into null.
-TRAFFIC = {}
+TRAFFIC = {
+    # two-lane FP32 block kernel, 8 blocks x 16 right-hand sides, Schwarz sweeps
+    ("block_mr", "c2", "mixed"): {"bytes_per_launch": 25023063, "source": "kernels_block.hip",
+                                  "sha256": "093d544378785e40b68923c0feca0a945ef4658b9db6858340542dc065e1d79c"},
+    # full-lattice FP64 stencil at 32^4 in the split form with one wave per SIMD (variant 1)
+    ("dslash_f64_v1", "32x32x32x32", "dw"): {"bytes_per_launch": 1728300000, "source": "kernels_dirac.hip",
+                                             "sha256": "3a69a6f4250a19cc69a284b81a94cb5953b966e1a36925eb0093c5a6b50315b9"},
+}
 
 
 def traffic_for(family: str, workload: str, mode: str):
@@ -397,6 +404,8 @@ def main():
         "dw_us_per_launch": {k: round(v["us_per_launch"], 2) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
         "dw_frac_of_hbm_peak": {k: round(v["gbs"] / HBM_PEAK_GBS, 4) for k, v in dw.items()
                                 if isinstance(v, dict) and "gbs" in v},
+        "dw_traffic_bytes_per_launch": {"f64": traffic_for(f"dslash_f64_v{dw['tuning']['dslash_variant_f64']}",
+                                                          dw["lattice"], "dw")},
         "copy_ceiling": copy,
         "solver": {"fast": stats[-1], "plain": stp[-1]},
         "tuning": tune,
