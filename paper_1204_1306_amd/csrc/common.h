@@ -59,6 +59,16 @@ __host__ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 }
 __host__ __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
 
+// Non-temporal 16-byte accesses (streamed data that is not read again soon: the
+// output of a full-lattice stencil), so the L2 keeps the neighbour spinors.
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
+template <class V> __device__ __forceinline__ void nt_st(V* p, V v) {
+  static_assert(sizeof(V) == 16, "16-byte storage units");
+  nt_u4 n;
+  __builtin_memcpy(&n, &v, 16);
+  __builtin_nontemporal_store(n, reinterpret_cast<nt_u4*>(p));
+}
+
 // ----------------------------------------------------------------- storage formats
 // Spinor storage: F64 = 12 double2 planes, F32 = 6 float4 planes, BF16 = 3 uint4 planes.
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
@@ -77,6 +87,10 @@ struct StF64 {
   template <class T> __device__ __forceinline__ static void store(unit* __restrict__ p, size_t Vh, int s, const Spinor<T>& o) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) p[k * Vh + s] = make_double2(double(o.v[k / 3][k % 3].re), double(o.v[k / 3][k % 3].im));
+  }
+  template <class T> __device__ __forceinline__ static void store_nt(unit* __restrict__ p, size_t Vh, int s, const Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) nt_st(p + k * Vh + s, make_double2(double(o.v[k / 3][k % 3].re), double(o.v[k / 3][k % 3].im)));
   }
 };
 
@@ -97,6 +111,13 @@ struct StF32 {
     for (int k = 0; k < 6; ++k) {
       cx<T> a = o.v[(2 * k) / 3][(2 * k) % 3], b = o.v[(2 * k + 1) / 3][(2 * k + 1) % 3];
       p[k * Vh + s] = make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
+    }
+  }
+  template <class T> __device__ __forceinline__ static void store_nt(unit* __restrict__ p, size_t Vh, int s, const Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      cx<T> a = o.v[(2 * k) / 3][(2 * k) % 3], b = o.v[(2 * k + 1) / 3][(2 * k + 1) % 3];
+      nt_st(p + k * Vh + s, make_float4(float(a.re), float(a.im), float(b.re), float(b.im)));
     }
   }
 };
@@ -127,6 +148,18 @@ struct StBF16 {
         w[j] = uint32_t(f32_to_bf16(float(o.v[e / 3][e % 3].re))) | (uint32_t(f32_to_bf16(float(o.v[e / 3][e % 3].im))) << 16);
       }
       p[k * Vh + s] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+  template <class T> __device__ __forceinline__ static void store_nt(unit* __restrict__ p, size_t Vh, int s, const Spinor<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int e = 4 * k + j;
+        w[j] = uint32_t(f32_to_bf16(float(o.v[e / 3][e % 3].re))) | (uint32_t(f32_to_bf16(float(o.v[e / 3][e % 3].im))) << 16);
+      }
+      nt_st(p + k * Vh + s, make_uint4(w[0], w[1], w[2], w[3]));
     }
   }
 };

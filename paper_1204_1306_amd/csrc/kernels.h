@@ -106,6 +106,7 @@ struct BlockMRParams {
   double kappa;
   int face = 0;   // 1: first rho_b -= D_{b,other} delta_other across the block faces
   int lanes = 0;  // LDS-resident 256-site blocks: lanes per site (1, 2; 0 = by grid size)
+  int eo = 0;     // LDS-resident 256-site blocks: even-odd preconditioned minimal residual
 };
 // For every block of the colour: (optionally) the face update of rho_b from the
 // other colour's delta, then delta = MR approximation of D_b^-1 rho_b, x += delta,

@@ -21,6 +21,7 @@ struct BlockArgs {
   double tol, kappa;
   int face;  // 1: first apply the residual update across the block faces (see face_update)
   int lanes;  // LDS-resident form: 1 or 2 lanes per site (0: by grid size)
+  int eo;     // LDS-resident form: 1 = even-odd preconditioned minimal residual
   int* iters;
 };
 
@@ -531,10 +532,242 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
   }
 }
 
+
+// Even-odd preconditioned block solver for 256-site blocks (256 threads). With e/o
+// the two parities of the block, D_b = [[1, -k H_eo], [-k H_oe, 1]] and
+//   D_b x = rho  <=>  (1 - k^2 H_eo H_oe) x_e = rho_e + k H_eo rho_o,  x_o = rho_o + k H_oe x_e.
+// Minimal residual runs on the even Schur complement, whose spectral radius around 1
+// is about the square of that of D_b, so an iteration reduces the residual about as
+// much as two iterations on D_b. Afterwards the block residual rho - D_b delta is the
+// minimal-residual residual on the even sites and exactly zero on the odd sites.
+// Thread (j, h): site j of each parity; every hop phase gives each site two lanes
+// (h = 0 forward hops, h = 1 backward hops, wave-uniform), so no SIMD idles while
+// only one parity computes. The even-site state lives in lane 0, the odd in lane 1.
+template <class S, class LK, class T>
+__global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
+  constexpr int H = 128;  // sites per parity
+  constexpr bool LL = LdsLinks<LK>::on;
+  __shared__ cx<T> ev[12][H];     // an even-site field
+  __shared__ cx<T> od[2][12][H];  // odd-site partial sums of the two lanes
+  __shared__ cx<T> eb[12][H];     // even-site partial sum of lane 1
+  __shared__ float4 lk_lds[LL ? 12 : 1][LL ? 2 * H : 1];
+  __shared__ double sm[3][16];
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int blk = a.colour * g.nblk_c + blockIdx.x;
+  const int prop = blockIdx.z;
+  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  using unit = typename S::unit;
+  unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  unit* x = reinterpret_cast<unit*>(a.x) + roff;
+  unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const T kp = T(a.kappa), mk = T(-a.kappa);
+  const int j = threadIdx.x & (H - 1);
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
+  const int s = blk * H + j;  // index of site j in either parity array
+
+  // in-block neighbours of this lane's four hops: nA for the odd site j (even
+  // neighbours), nB for the even site j (odd neighbours); -1 when the hop leaves the block
+  int nA[4], nB[4], gA[4], gB[4];
+  {
+    SiteInfo so, se;
+    site_info(g, 1, s, so);
+    site_info(g, 0, s, se);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      Nbr n = neighbour(g, so, mu, h == 0 ? +1 : -1);
+      nA[mu] = n.cross ? -1 : n.s - blk * H;
+      gA[mu] = n.s;
+      Nbr m = neighbour(g, se, mu, h == 0 ? +1 : -1);
+      nB[mu] = m.cross ? -1 : m.s - blk * H;
+      gB[mu] = m.s;
+    }
+  }
+  if constexpr (LL) {  // lane h stages the forward links of site j of parity h
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      lk_lds[k][h * H + j] = reinterpret_cast<const float4*>(lk)[(size_t(h * 4 + k / 3) * 3 + k % 3) * Vh + s];
+  }
+  // forward link of site (parity gp, in-block index q) in direction mu
+  auto link = [&](int mu, int gp, int q, int gs, SU3<T>& U) {
+    if constexpr (LL) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float4 v = lk_lds[mu * 3 + k][gp * H + q];
+        U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
+        U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
+      }
+      cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
+      cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
+      cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
+      U.m[2][0] = {c0.re, -c0.im};
+      U.m[2][1] = {c1.re, -c1.im};
+      U.m[2][2] = {c2.re, -c2.im};
+    } else {
+      LK::load(lk + size_t(gp * 4 + mu) * LK::NC * Vh, Vh, gs, U);
+    }
+  };
+  // this lane's hops of the odd site j, applied to the even field ev
+  auto phase_odd = [&](T c, Spinor<T>& acc) {
+    zero(acc);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const int q = nA[mu];
+      if (q >= 0) {
+        SU3<T> U;
+        if (h == 0) link(mu, 1, j, s, U);  // U(x, mu) of the odd site
+        else link(mu, 0, q, gA[mu], U);    // U(x - mu, mu) of its even neighbour
+        Spinor<T> nb;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = ev[k][q];
+        if (h == 0) hop_fwd(mu, U, nb, c, acc);
+        else hop_bwd(mu, U, nb, c, acc);
+      }
+    }
+  };
+  // this lane's hops of the even site j, applied to od[0] (+ od[1])
+  auto phase_even = [&](T c, bool both, Spinor<T>& acc) {
+    zero(acc);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const int q = nB[mu];
+      if (q >= 0) {
+        SU3<T> U;
+        if (h == 0) link(mu, 0, j, s, U);
+        else link(mu, 1, q, gB[mu], U);
+        Spinor<T> nb;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = both ? od[0][k][q] + od[1][k][q] : od[0][k][q];
+        if (h == 0) hop_fwd(mu, U, nb, c, acc);
+        else hop_bwd(mu, U, nb, c, acc);
+      }
+    }
+  };
+
+  // own site (parity h): rho (+ the face update), |rho|^2 over the block
+  Spinor<T> r, d, acc;
+  S::load(rho + size_t(h) * S::NC * Vh, Vh, s, r);
+  if (a.face) face_update<S, LK, T>(g, lk, dl, h, s, kp, r);
+  double b2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b2 += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+  b2 = wg_sum(b2, sm[0]);
+  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
+  zero(d);
+
+  // even right-hand side rho_e + k H_eo rho_o (lane 0); lane 1 keeps rho_o
+  if (h == 1) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) od[0][k][j] = r.v[k / 3][k % 3];
+  }
+  __syncthreads();
+  phase_even(kp, false, acc);
+  if (h == 1) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) eb[k][j] = acc.v[k / 3][k % 3];
+  }
+  __syncthreads();
+  if (h == 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + eb[k][j];
+  }
+
+  int it = 0;
+  if (b2 > 0.0) {
+    for (; it < a.niter; ++it) {
+      // p = (1 - k^2 H_eo H_oe) r on the even sites
+      if (h == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ev[k][j] = r.v[k / 3][k % 3];
+      }
+      __syncthreads();
+      phase_odd(kp, acc);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) od[h][k][j] = acc.v[k / 3][k % 3];
+      __syncthreads();
+      phase_even(mk, true, acc);
+      if (h == 1) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) eb[k][j] = acc.v[k / 3][k % 3];
+      }
+      __syncthreads();
+      double prr = 0.0, pri = 0.0, pp = 0.0;
+      if (h == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + eb[k][j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double ar = acc.v[q][c].re, ai = acc.v[q][c].im, br = r.v[q][c].re, bi = r.v[q][c].im;
+            prr += ar * br + ai * bi;
+            pri += ar * bi - ai * br;
+            pp += ar * ar + ai * ai;
+          }
+      }
+      wg_sum3(prr, pri, pp, sm);
+      if (!(pp > 0.0)) break;
+      const cx<T> alpha = {T(prr / pp), T(pri / pp)};
+      double rr = 0.0;
+      if (h == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            d.v[q][c] = d.v[q][c] + cmul(alpha, r.v[q][c]);
+            r.v[q][c] = r.v[q][c] - cmul(alpha, acc.v[q][c]);
+            rr += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+          }
+      }
+      if (stop2 > 0) {
+        rr = wg_sum(rr, sm[0]);
+        if (rr <= stop2) {
+          ++it;
+          break;
+        }
+      }
+    }
+  }
+  // x_o = rho_o + k H_oe x_e; the odd residual is then zero
+  if (h == 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ev[k][j] = d.v[k / 3][k % 3];
+  }
+  __syncthreads();
+  phase_odd(kp, acc);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) od[h][k][j] = acc.v[k / 3][k % 3];
+  __syncthreads();
+  if (h == 1) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      d.v[k / 3][k % 3] = r.v[k / 3][k % 3] + od[0][k][j] + od[1][k][j];
+      r.v[k / 3][k % 3] = {T(0), T(0)};
+    }
+  }
+  S::store(rho + size_t(h) * S::NC * Vh, Vh, s, r);
+  S::store(dl + size_t(h) * S::NC * Vh, Vh, s, d);
+  Spinor<T> xv;
+  S::load(x + size_t(h) * S::NC * Vh, Vh, s, xv);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
+  S::store(x + size_t(h) * S::NC * Vh, Vh, s, xv);
+  if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
+}
+
 template <class S, class LK, class T>
 static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
   if (2 * a.g.Vbh == 256) {
     const dim3 grid(a.g.nblk_c, a.nrhs, nprop);
+    if (a.eo) {
+      launch_timed((k_block_mr_eo<S, LK, T>), grid, dim3(256), 0, st, a);
+      return;
+    }
     if constexpr (LdsLinks<LK>::on) {
       // two lanes per site when the grid gives fewer than two workgroups per CU
       const int lanes = a.lanes > 0 ? a.lanes : (grid.x * grid.y * grid.z < 512 ? 2 : 1);
@@ -569,6 +802,7 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
   a.kappa = bp.kappa;
   a.face = bp.face;
   a.lanes = bp.lanes;
+  a.eo = bp.eo;
   a.iters = iters_out;
   if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);
   else if (rho.prec == P_F32 && linkfmt == LK_F32C12) block_go<StF32, LkF32C12, float>(st, a, rho.nprop);

@@ -22,6 +22,7 @@ struct DslashArgs {
   double cdiag, chop;
   int accumulate;
   int xcd_map;  // 1: remap workgroups to per-XCD contiguous tile ranges
+  int nt_out;   // 1: non-temporal output stores (output larger than the chip's L2)
 };
 
 // Workgroup -> site tile. Workgroups are dispatched round-robin over the 8 XCDs,
@@ -136,7 +137,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
 #pragma unroll
           for (int c = 0; c < 3; ++c) acc[r].v[sp][c] = acc[r].v[sp][c] + d.v[sp][c];
       }
-      SO::store(o, Vh, s, acc[r]);
+      if (a.nt_out) SO::store_nt(o, Vh, s, acc[r]);
+      else SO::store(o, Vh, s, acc[r]);
     }
   }
 }
@@ -226,7 +228,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc.v[sp][c] = acc.v[sp][c] + d.v[sp][c];
   }
-  SO::store(op, Vh, s, acc);
+  if (a.nt_out) SO::store_nt(op, Vh, s, acc);
+  else SO::store(op, Vh, s, acc);
 }
 
 template <class SI, class SO, class LK, class T, int W>
@@ -298,6 +301,9 @@ void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int l
   a.chop = dp.chop;
   a.accumulate = dp.accumulate;
   a.xcd_map = dp.xcd_map;
+  // an output larger than the 8 XCD L2 caches (8 x 4 MB) cannot be re-read from L2 by
+  // the next kernel anyway: stream it past the cache
+  a.nt_out = double(bytes_per_field(out.prec, g.Vh)) * out.nrhs * out.nprop > 32.0 * (1 << 20) ? 1 : 0;
   if (dp.variant > 0 && dp.sel == HOP_ALL && nr_pref <= 1) {
     if (in.prec == P_F64 && out.prec == P_F64 && linkfmt == LK_F64)
       dslash_variant<StF64, StF64, LkF64, double>(st, a, in.nprop, dp.variant);

@@ -76,6 +76,7 @@ struct psms_ctx {
   int op_colour = -1;          // >= 0: the solver's operator is D_cc of that colour
   int block_solver = 0;        // block inverses to tolerance: 0 minimal residual, 1 flexible GCR
   int block_lanes = 0;         // LDS-resident block solver: lanes per site (1, 2; 0 = by grid size)
+  int block_eo = 2;            // LDS-resident block solver: 1 even-odd, 0 plain, 2 by launch shape
   // pinned host slots for the lagged convergence check of the GCR iteration
   double* pinned[2] = {nullptr, nullptr};
   size_t pinned_n = 0;
@@ -463,13 +464,21 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
     launch_copy(c->st, c->g, r, rho, nullptr);
     launch_zero(c->st, xs, c->Vh);
   }
+  // Block solver form: even-odd minimal residual (block_eo 1), plain (0), or by launch
+  // shape (2): even-odd when the grid has fewer than two workgroups per CU or the
+  // solver runs in FP64 (both forms then hold one workgroup per CU), with half the
+  // iterations, one even-odd iteration reducing the residual about as much as two plain.
+  const int wgs = c->g.nblk_c * r.nrhs * r.nprop;
+  const bool eo = c->block_eo == 1 || (c->block_eo == 2 && (wgs < 512 || sc.prec == P_F64));
+  const int iters = (eo && c->block_eo == 2) ? (sc.iters + 1) / 2 : sc.iters;
   // Each sweep first applies rho_col -= D_{col,other} delta_other across its block
   // faces (fused into the block kernel), except the very first, where no delta exists.
   for (int cy = 0; cy < sc.cycles; ++cy) {
     for (int col = 0; col < 2; ++col) {
-      BlockMRParams bp{col, sc.iters, 0.0, c->geom.kappa};
+      BlockMRParams bp{col, iters, 0.0, c->geom.kappa};
       bp.face = (cy > 0 || col > 0) ? 1 : 0;
       bp.lanes = c->block_lanes;
+      bp.eo = eo ? 1 : 0;
       ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho, bp.face));
       launch_block_mr(c->st, c->g, L.p, L.fmt, rho, xs, dl, pb, bp, nullptr);
     }
@@ -866,6 +875,7 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
     ProfScope ps(c, FAM_BLOCK_SOLVE, block_bytes(c, L, rho));
     BlockMRParams bp{col, maxit, tol, c->geom.kappa};
     bp.lanes = c->block_lanes;
+    bp.eo = c->block_eo != 0 ? 1 : 0;  // to a tolerance the even-odd form always pays
     launch_block_mr(c->st, c->g, L.p, L.fmt, rho, x, dl, pb, bp, it);
   }
   if (iters_host) HIPCHK(hipMemcpyAsync(iters_host, it, sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -1778,10 +1788,11 @@ static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "net_mfma")) return &c->net_mfma;
   if (!std::strcmp(key, "block_solver")) return &c->block_solver;
   if (!std::strcmp(key, "block_lanes")) return &c->block_lanes;
+  if (!std::strcmp(key, "block_eo")) return &c->block_eo;
   return nullptr;
 }
 static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
-                                    "xcd_map", "net_mfma", "block_solver", "block_lanes"};
+                                    "xcd_map", "net_mfma", "block_solver", "block_lanes", "block_eo"};
 
 psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   API_BEGIN(c)
@@ -1789,6 +1800,8 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   int* t = tuning_slot(c, key);
   REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
   if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 5, "stencil variant must be in [0, 5]");
+  else if (!std::strcmp(key, "block_eo"))
+    REQUIRE(value >= 0 && value <= 2, "block_eo must be 0 (plain), 1 (even-odd) or 2 (by launch shape)");
   else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
   else if (!std::strcmp(key, "block_lanes"))
