@@ -205,6 +205,46 @@ def learned_leg(psms, ctx, w, noise, delta, nprop, steps, npairs):
             "solver": st[-1], "net_ms_per_step": fam["net"]["ms"] / steps}, d
 
 
+def net_leg(psms, L=(16, 16, 16, 16), nrhs=8, reps=10):
+    """Applications of the gauge-covariant network (1-8-8-8-1 channels, the learned
+    preconditioner's shape) to nrhs fields on an L lattice (the near-critical 16^4
+    workload's size), timed on the library's stream. Algorithmic flops count the
+    complex spin mixing (9 transports x C_in x C_out complex 4x4 spin matrices on 3
+    colours, 8 flops per complex multiply-add) and the parallel transports (8
+    directions x C_in fields x 4 spins x a 3x3 complex matrix-vector product); the
+    matrix cores execute the mixing as a real GEMM of twice the mixing flops."""
+    import torch
+
+    from paper_1204_1306_amd import synth
+
+    dev = torch.device("cuda:0")
+    ctx = psms.Context(L, tuple(max(2, v // 4) for v in L), 0.157, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.gauge_load(0, torch.from_numpy(synth.gauge_field(L, 0.6, 4999)).to(dev))
+    chans = (1, 8, 8, 8, 1)
+    ctx.net_init(chans, seed=7, scale=0.05)
+    psi = torch.from_numpy(synth.gaussian_noise(L, nrhs, 11)).to(dev)
+    out = {"lattice": "x".join(map(str, L)), "nrhs": nrhs, "channels": list(chans)}
+    V = int(np.prod(L))
+    mix = sum(9 * ci * co * 48 * 8 for ci, co in zip(chans[:-1], chans[1:]))
+    transport = sum(8 * ci * 4 * 9 * 8 for ci in chans[:-1])
+    for name, flag in (("mfma_bf16", 1), ("valu_fp32", 0)):
+        ctx.set_tuning("net_mfma", flag)
+        ctx.net_apply(0, psi)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.net_apply(0, psi)
+        torch.cuda.synchronize()
+        r = ctx.profile_read("net")
+        ctx.profile(False)
+        ms = r["ms"] / reps
+        out[name] = {"ms_per_apply": round(ms, 3),
+                     "algorithmic_tflops": round(nrhs * V * (mix + transport) / (ms * 1e-3) / 1e12, 2),
+                     "mixing_gemm_tflops": round(nrhs * V * 2 * mix / (ms * 1e-3) / 1e12, 2)}
+    ctx.close()
+    return out
+
+
 def batched_leg(psms, workload: str, steps: int, rhs_chunk: int):
     """The batched workload (all proposals x noise vectors of it in one call), with
     BF16 Krylov storage and FP32 inner solves against plain FP64, same tolerance."""
@@ -310,6 +350,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--dw-lattice", default="32,32,32,32")
     ap.add_argument("--batched-workload", default="c3", help="'none' skips the batched leg")
+    ap.add_argument("--no-net-leg", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--batched-rhs-chunk", type=int, default=128)
     args = ap.parse_args()
@@ -359,6 +400,14 @@ def main():
         except Exception as e:  # reported, not hidden
             batched = {"error": repr(e)}
 
+    net = None
+    if not args.no_net_leg:
+        try:
+            net = net_leg(psms)
+            log(f"network: {net}")
+        except Exception as e:  # reported, not hidden
+            net = {"error": repr(e)}
+
     copy = copy_ceiling()
     log(f"copy: {copy}")
     dwL = tuple(int(v) for v in args.dw_lattice.split(","))
@@ -399,6 +448,7 @@ def main():
         "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
         "learned": learned,
         "batched": batched,
+        "network": net,
         "dw_lattice": dw["lattice"],
         "dw_tuning": dw["tuning"],
         "dw_gbs": {k: round(v["gbs"], 1) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
