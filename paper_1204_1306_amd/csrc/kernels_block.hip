@@ -21,7 +21,7 @@ struct BlockArgs {
   double tol, kappa;
   int face;  // 1: first apply the residual update across the block faces (see face_update)
   int lanes;  // LDS-resident form: 1 or 2 lanes per site (0: by grid size)
-  int eo;     // LDS-resident form: 1 = even-odd preconditioned minimal residual
+  int eo;     // 1: even-odd preconditioned minimal residual (k_block_mr_eo, k_block_mr_eo_g)
   int* iters;
 };
 
@@ -128,7 +128,8 @@ __device__ __forceinline__ void wg_sum3(double& a, double& b, double& c, double 
 
 template <class S, class LK, class T>
 __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
-  __shared__ double sm[16];
+  __shared__ double sm3[3][16];
+  double* sm = sm3[0];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
   const int blk = a.colour * g.nblk_c + blockIdx.x;
@@ -184,9 +185,7 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
             pp += ar * ar + ai * ai;
           }
       }
-      prr = wg_sum(prr, sm);
-      pri = wg_sum(pri, sm);
-      pp = wg_sum(pp, sm);
+      wg_sum3(prr, pri, pp, sm3);
       if (!(pp > 0.0)) break;
       const cx<T> alpha = {T(prr / pp), T(pri / pp)};
       double rr = 0.0;
@@ -222,6 +221,176 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
     S::store(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+  }
+  if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
+}
+
+// acc += c * (the intra-block hops of site (p, s), applied to src on the other parity)
+template <class S, class LK, class T>
+__device__ __forceinline__ void block_half_hops(const Geo& g, const typename LK::unit* __restrict__ lk,
+                                                const typename S::unit* __restrict__ src, int p, int s, T c,
+                                                Spinor<T>& acc) {
+  const size_t Vh = g.Vh;
+  SiteInfo si;
+  site_info(g, p, s, si);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    Nbr n = neighbour(g, si, mu, +1);
+    if (!n.cross) {
+      SU3<T> U;
+      LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+      Spinor<T> nb;
+      S::load(src + size_t(1 - p) * S::NC * Vh, Vh, n.s, nb);
+      hop_fwd(mu, U, nb, c, acc);
+    }
+    n = neighbour(g, si, mu, -1);
+    if (!n.cross) {
+      SU3<T> U;
+      LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+      Spinor<T> nb;
+      S::load(src + size_t(1 - p) * S::NC * Vh, Vh, n.s, nb);
+      hop_bwd(mu, U, nb, c, acc);
+    }
+  }
+}
+
+// Even-odd form of the global-memory block solver (any block size): minimal residual
+// on each block's even Schur complement 1 - k^2 H_eo H_oe (as in k_block_mr_eo), with
+// the fields in global memory. Per iteration the odd sites form t = k H_oe r (odd half
+// of pbuf), the even sites p = r - k H_eo t (even half) with the three inner products,
+// then the even sites update. rho's even half holds the residual, delta's even half
+// the iterate; at the end delta_o = rho_o + k H_oe delta_e and the odd residual is zero.
+// Per iteration this moves about the data of one plain iteration and reduces the
+// residual about as much as two.
+template <class S, class LK, class T>
+__global__ void __launch_bounds__(256) k_block_mr_eo_g(BlockArgs a) {
+  __shared__ double sm[3][16];
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int blk = a.colour * g.nblk_c + blockIdx.x;
+  const int prop = blockIdx.z;
+  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  using unit = typename S::unit;
+  unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  unit* x = reinterpret_cast<unit*>(a.x) + roff;
+  unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
+  unit* pb = reinterpret_cast<unit*>(a.pbuf) + roff;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const int H = g.Vbh;
+  const T kp = T(a.kappa), mk = T(-a.kappa);
+  const size_t odd = size_t(S::NC) * Vh;  // offset of the odd half of a field
+
+  // rho_b += face update (optional), |rho_b|^2
+  double b2 = 0.0;
+  for (int j = threadIdx.x; j < 2 * H; j += blockDim.x) {
+    const int p = j / H, s = blk * H + (j - p * H);
+    Spinor<T> v;
+    S::load(rho + p * odd, Vh, s, v);
+    if (a.face) {
+      face_update<S, LK, T>(g, lk, dl, p, s, kp, v);
+      S::store(rho + p * odd, Vh, s, v);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) b2 += double(v.v[q][c].re) * v.v[q][c].re + double(v.v[q][c].im) * v.v[q][c].im;
+  }
+  b2 = wg_sum(b2, sm[0]);  // also orders the rho stores before the next pass reads them
+  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
+  // even right-hand side rho_e + k H_eo rho_o (into rho_e), delta_e = 0
+  for (int j = threadIdx.x; j < H; j += blockDim.x) {
+    const int s = blk * H + j;
+    Spinor<T> v, z;
+    S::load(rho, Vh, s, v);
+    block_half_hops<S, LK, T>(g, lk, rho, 0, s, kp, v);
+    S::store(rho, Vh, s, v);
+    zero(z);
+    S::store(dl, Vh, s, z);
+  }
+  __syncthreads();
+
+  int it = 0;
+  if (b2 > 0.0) {
+    for (; it < a.niter; ++it) {
+      // t = k H_oe r on the odd sites
+      for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        const int s = blk * H + j;
+        Spinor<T> t;
+        zero(t);
+        block_half_hops<S, LK, T>(g, lk, rho, 1, s, kp, t);
+        S::store(pb + odd, Vh, s, t);
+      }
+      __syncthreads();
+      // p = r - k H_eo t on the even sites, (p, r) and |p|^2
+      double prr = 0.0, pri = 0.0, pp = 0.0;
+      for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        const int s = blk * H + j;
+        Spinor<T> r, pv;
+        S::load(rho, Vh, s, r);
+        pv = r;
+        block_half_hops<S, LK, T>(g, lk, pb, 0, s, mk, pv);
+        S::store(pb, Vh, s, pv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double ar = pv.v[q][c].re, ai = pv.v[q][c].im, br = r.v[q][c].re, bi = r.v[q][c].im;
+            prr += ar * br + ai * bi;
+            pri += ar * bi - ai * br;
+            pp += ar * ar + ai * ai;
+          }
+      }
+      wg_sum3(prr, pri, pp, sm);
+      if (!(pp > 0.0)) break;
+      const cx<T> alpha = {T(prr / pp), T(pri / pp)};
+      double rr = 0.0;
+      for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        const int s = blk * H + j;
+        Spinor<T> r, pv, d;
+        S::load(rho, Vh, s, r);
+        S::load(pb, Vh, s, pv);
+        S::load(dl, Vh, s, d);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            d.v[q][c] = d.v[q][c] + cmul(alpha, r.v[q][c]);
+            r.v[q][c] = r.v[q][c] - cmul(alpha, pv.v[q][c]);
+            rr += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
+          }
+        S::store(dl, Vh, s, d);
+        S::store(rho, Vh, s, r);
+      }
+      rr = wg_sum(rr, sm[0]);  // also orders the rho_e stores before the next pass reads them
+      if (rr <= stop2) {
+        ++it;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  // delta_o = rho_o + k H_oe delta_e, rho_o = 0; x += delta on both parities
+  for (int j = threadIdx.x; j < H; j += blockDim.x) {
+    const int s = blk * H + j;
+    Spinor<T> d, z, xv;
+    S::load(rho + odd, Vh, s, d);
+    block_half_hops<S, LK, T>(g, lk, dl, 1, s, kp, d);
+    S::store(dl + odd, Vh, s, d);
+    zero(z);
+    S::store(rho + odd, Vh, s, z);
+    S::load(x + odd, Vh, s, xv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
+    S::store(x + odd, Vh, s, xv);
+    S::load(dl, Vh, s, d);
+    S::load(x, Vh, s, xv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
+    S::store(x, Vh, s, xv);
   }
   if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
 }
@@ -780,6 +949,11 @@ static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
     return;
   }
   dim3 grid(a.g.nblk_c, a.nrhs, nprop);
+  if (a.eo) {
+    const int threads = a.g.Vbh < 256 ? ((a.g.Vbh + 63) / 64) * 64 : 256;
+    launch_timed((k_block_mr_eo_g<S, LK, T>), grid, dim3(threads), 0, st, a);
+    return;
+  }
   int threads = 2 * a.g.Vbh < 256 ? ((2 * a.g.Vbh + 63) / 64) * 64 : 256;
   launch_timed((k_block_mr<S, LK, T>), grid, dim3(threads), 0, st, a);
 }

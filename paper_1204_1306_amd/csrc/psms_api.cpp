@@ -829,15 +829,92 @@ struct ColourOperator {
   ~ColourOperator() { c->op_colour = -1; }
 };
 
+// Mixed-precision block inverse x = D_cc^-1 b (SU(3) links): FP64 defect correction
+// around the FP32 block solver (12-real links, FP32 fields). Each pass solves
+// D_cc e = r to 1e-5 relative per block in FP32, adds e to x in FP64 and recomputes
+// the FP64 residual r = b_c - D_cc x, until |r| <= tol |b_c| for every right-hand side
+// or maxit block iterations are spent. Returns the max relative FP64 residual.
+double solve_colour_mixed(psms_ctx* c, const int* slots, int col, const FieldBatch& b, const FieldBatch& x, double tol,
+                          int maxit, int* iters_host) {
+  const int np = b.nprop, nrb = b.nrhs, nr = np * nrb;
+  Links L64 = links_of(c, slots, np, LK_F64);
+  Links L32 = links_of(c, slots, np, LK_F32C12);
+  FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
+  FieldBatch rt = field(c, "bs_rt", P_F64, np, nrb);
+  FieldBatch rho = field(c, "bs_rho32", P_F32, np, nrb);
+  FieldBatch e = field(c, "bs_e32", P_F32, np, nrb);
+  FieldBatch dl = field(c, "bs_delta32", P_F32, np, nrb);
+  FieldBatch pb = field(c, "bs_p32", P_F32, np, nrb);
+  int* it = dscratch<int>(c, "bs_iters", 1);
+  double* n1 = dscratch<double>(c, "bs_n1", nr);
+  double* n2 = dscratch<double>(c, "bs_n2", nr);
+  const double2* ONE = const_cx(c, "one", nr, 1, 0);
+  const double2* MONE = const_cx(c, "mone", nr, -1, 0);
+  {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(c->st, c->g, b, bc, nullptr);
+    launch_keep_colour(c->st, c->g, bc, col);
+    launch_copy(c->st, c->g, bc, rt, nullptr);  // r = b_c for x = 0
+    launch_zero(c->st, x, c->Vh);
+  }
+  norm2(c, bc, n2);
+  const std::vector<double> h2 = to_host(c, n2, nr);
+  int total = 0;
+  double mx = 1.0;
+  for (int pass = 0; pass < 8 && total < maxit; ++pass) {
+    HIPCHK(hipMemsetAsync(it, 0, sizeof(int), c->st));
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_copy(c->st, c->g, rt, rho, nullptr);  // FP64 -> FP32
+      launch_zero(c->st, e, c->Vh);
+    }
+    {
+      ProfScope ps(c, FAM_BLOCK_SOLVE, block_bytes(c, L32, rho));
+      BlockMRParams bp{col, maxit - total, 1e-5, c->geom.kappa};
+      bp.lanes = c->block_lanes;
+      bp.eo = c->block_eo != 0 ? 1 : 0;
+      launch_block_mr(c->st, c->g, L32.p, L32.fmt, rho, e, dl, pb, bp, it);
+    }
+    int hit = 0;
+    HIPCHK(hipMemcpyAsync(&hit, it, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_axpy_mixed(c->st, c->g, ONE, e, x, +1);  // x += e in FP64
+    }
+    dslash(c, L64, x, rt, HOP_INTRA, col, 1.0, -c->geom.kappa, 0);
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_keep_colour(c->st, c->g, rt, col);
+      launch_axpby(c->st, c->g, ONE, bc, MONE, rt, +1);  // r = b_c - D_cc x
+    }
+    norm2(c, rt, n1);
+    const std::vector<double> h1 = to_host(c, n1, nr);  // synchronises: `hit` is valid
+    total += hit;
+    mx = 0;
+    for (int i = 0; i < nr; ++i) mx = std::max(mx, h2[i] > 0 ? std::sqrt(h1[i] / h2[i]) : std::sqrt(h1[i]));
+    if (mx <= tol || hit == 0) break;
+  }
+  if (iters_host) *iters_host = total;
+  return mx;
+}
+
 // x = D_cc^-1 b on the blocks of colour col; b is left unchanged. Returns max relative residual.
 // By default every block is solved by the minimal-residual kernel, one workgroup per
-// block (LDS-resident for blocks of 256 sites). block_solver = 1 instead runs flexible
-// GCR on the block-diagonal operator (mixed precision with FP64 defect correction);
-// measured slower for 8^4 blocks at 32^4 (its Krylov basis costs more than it saves).
+// block (LDS-resident for blocks of 256 sites). With `mixed` (SU(3) links) and blocks
+// that are not LDS-resident, whose solver is bound by memory traffic, the FP64 defect
+// correction of solve_colour_mixed runs the block solver in FP32. block_solver = 1
+// instead runs flexible GCR on the block-diagonal operator (mixed precision with FP64
+// defect correction); measured slower for 8^4 blocks at 32^4 (its Krylov basis costs
+// more than it saves).
 double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b, const FieldBatch& x, double tol, int maxit,
-                    int* iters_host) {
+                    int* iters_host, bool mixed = false) {
   const int np = b.nprop, nrb = b.nrhs, nr = np * nrb;
   Links L = links_of(c, slots, np, LK_F64);
+  if (mixed && c->block_solver == 0 && 2 * c->g.Vbh != 256) {
+    bool su3 = true;
+    for (int i = 0; i < np; ++i) su3 &= c->slots[slots[i]].su3;
+    if (su3) return solve_colour_mixed(c, slots, col, b, x, tol, maxit, iters_host);
+  }
   if (c->block_solver == 1) {
     FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
     {
@@ -904,7 +981,8 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
 }
 
 // out = (1 - P Q) xi, Q = D_bb^-1 D_bw D_ww^-1 D_wb. Returns worst block-solve residual.
-double schur_apply(psms_ctx* c, const int* slots, const FieldBatch& xi, const FieldBatch& out, double tol, int maxit) {
+double schur_apply(psms_ctx* c, const int* slots, const FieldBatch& xi, const FieldBatch& out, double tol, int maxit,
+                   bool mixed = false) {
   const int np = xi.nprop, nrb = xi.nrhs;
   Links L = links_of(c, slots, np, LK_F64);
   FieldBatch t1 = field(c, "sc_t1", P_F64, np, nrb);
@@ -914,13 +992,13 @@ double schur_apply(psms_ctx* c, const int* slots, const FieldBatch& xi, const Fi
     launch_zero(c->st, t1, c->Vh);
   }
   dslash(c, L, xi, t1, HOP_CROSS, 1, 0.0, -c->geom.kappa, 0);  // D_wb xi (white sites)
-  double r1 = solve_colour(c, slots, 1, t1, t2, tol, maxit, nullptr);  // D_ww^-1
+  double r1 = solve_colour(c, slots, 1, t1, t2, tol, maxit, nullptr, mixed);  // D_ww^-1
   {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_zero(c->st, t1, c->Vh);
   }
   dslash(c, L, t2, t1, HOP_CROSS, 0, 0.0, -c->geom.kappa, 0);  // D_bw (black sites)
-  double r2 = solve_colour(c, slots, 0, t1, t2, tol, maxit, nullptr);  // D_bb^-1
+  double r2 = solve_colour(c, slots, 0, t1, t2, tol, maxit, nullptr, mixed);  // D_bb^-1
   {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_project(c->st, c->g, t2, t1);
@@ -1393,7 +1471,7 @@ psms_status psms_solve_block(psms_ctx* c, int slot, int colour, const double* b,
   FieldBatch b64 = field(c, "api_b64", P_F64, 1, nrhs), x64 = field(c, "api_x64", P_F64, 1, nrhs);
   launch_pack(c->st, c->g, db, b64);
   int iters = 0;
-  double rel = solve_colour(c, &slot, colour, b64, x64, pp->tol, pp->max_iter, &iters);
+  double rel = solve_colour(c, &slot, colour, b64, x64, pp->tol, pp->max_iter, &iters, pp->prec == PSMS_MIXED);
   launch_unpack(c->st, c->g, x64, dx);
   finish_out(c, x, dx, nd);
   FullSolveOut o;
@@ -1423,7 +1501,7 @@ psms_status psms_apply_schur(psms_ctx* c, int slot, const double* in, double* ou
   Links L = links_of(c, &slot, 1, LK_F64);
   FieldBatch a = field(c, "api_a", P_F64, 1, nrhs), b = field(c, "api_b", P_F64, 1, nrhs);
   launch_pack(c->st, c->g, din, a);
-  double rel = schur_apply(c, &slot, a, b, pp->tol, pp->max_iter);
+  double rel = schur_apply(c, &slot, a, b, pp->tol, pp->max_iter, pp->prec == PSMS_MIXED);
   launch_unpack(c->st, c->g, b, dout);
   finish_out(c, out, dout, nd);
   FullSolveOut o;
@@ -1489,7 +1567,7 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
     double* xin2 = dscratch<double>(c, "ld_xin2", nj);
     if (op == PSMS_OP_SCHUR) {
       launch_project(c->st, c->g, eta, xi);
-      double rel = schur_apply(c, &slot_U, xi, phi, pp->tol, pp->max_iter);
+      double rel = schur_apply(c, &slot_U, xi, phi, pp->tol, pp->max_iter, pp->prec == PSMS_MIXED);
       if (!(rel <= pp->tol * 1.0001)) agg.converged = false;
     } else {
       launch_copy(c->st, c->g, eta, xi, nullptr);
