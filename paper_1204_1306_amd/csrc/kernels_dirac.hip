@@ -246,10 +246,109 @@ static void dslash_one_go(hipStream_t st, const DslashArgs& a, int nprop) {
   launch_timed((k_dslash<SI, SO, LK, T, HOP_ALL, 1, W>), grid, dim3(256), 0, st, a);
 }
 
+// Four lanes per site: 64 sites per workgroup; wave q takes two of the eight hops
+// (q = 0: forward mu 0,1; 1: forward mu 2,3; 2: backward mu 0,1; 3: backward mu 2,3),
+// wave 0 also the diagonal term; the partial sums meet in LDS. A lane holds the loads
+// of only two hops, so two waves fit on a SIMD and interleave their memory latency.
+template <class SI, class SO, class LK, class T, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k_dslash_quad(DslashArgs a) {
+  __shared__ cx<T> part[3][12][64];
+  const Geo& g = a.g;
+  const int nwg = gridDim.x;
+  const int w = blockIdx.x;
+  const int qq = (a.xcd_map && (nwg & 7) == 0) ? (w & 7) * (nwg >> 3) + (w >> 3) : w;
+  const int tpp = (a.nb * g.Vbh + 63) >> 6;
+  const int tp = qq % a.np;
+  const int tq = qq / a.np;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int l = threadIdx.x & 63;
+  const int o = (tq << 6) + l;
+  const bool valid = tq < tpp && o < a.nb * g.Vbh;
+  const int p = a.p0 + tp;
+  int s = 0;
+  if (valid) {
+    if (a.nb == g.nblk) {
+      const int bp = o / g.Vbh;
+      s = g.border[bp] * g.Vbh + (o - bp * g.Vbh);
+    } else {
+      s = a.blk0 * g.Vbh + o;
+    }
+  }
+  const int prop = blockIdx.z;
+  const size_t Vh = g.Vh;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const typename SI::unit* in = reinterpret_cast<const typename SI::unit*>(a.in) + size_t(prop * a.nrhs + blockIdx.y) * a.in_rhs_stride;
+  typename SO::unit* out = reinterpret_cast<typename SO::unit*>(a.out) + size_t(prop * a.nrhs + blockIdx.y) * a.out_rhs_stride;
+  Spinor<T> acc;
+  zero(acc);
+  if (valid) {
+    SiteInfo si;
+    site_info(g, p, s, si);
+    const T ch = T(a.chop);
+    const typename SI::unit* nin = in + size_t(1 - p) * SI::NC * Vh;
+    if (q == 0 && a.cdiag != 0.0) {
+      SI::load(in + size_t(p) * SI::NC * Vh, Vh, s, acc);
+      const T cd = T(a.cdiag);
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc.v[sp][c] = scale(cd, acc.v[sp][c]);
+    }
+    // directions as compile-time constants, chosen by a wave-uniform test
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      if ((mu >> 1) != (q & 1)) continue;
+      if (q < 2) {
+        Nbr n = neighbour(g, si, mu, +1);
+        SU3<T> U;
+        LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+        Spinor<T> nb;
+        SI::load(nin, Vh, n.s, nb);
+        hop_fwd(mu, U, nb, ch * T(n.sign), acc);
+      } else {
+        Nbr n = neighbour(g, si, mu, -1);
+        SU3<T> U;
+        LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+        Spinor<T> nb;
+        SI::load(nin, Vh, n.s, nb);
+        hop_bwd(mu, U, nb, ch * T(n.sign), acc);
+      }
+    }
+  }
+  if (q > 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part[q - 1][k][l] = acc.v[k / 3][k % 3];
+  }
+  __syncthreads();
+  if (q > 0 || !valid) return;
+#pragma unroll
+  for (int k = 0; k < 12; ++k)
+    acc.v[k / 3][k % 3] = acc.v[k / 3][k % 3] + part[0][k][l] + part[1][k][l] + part[2][k][l];
+  typename SO::unit* op = out + size_t(p) * SO::NC * Vh;
+  if (a.accumulate) {
+    Spinor<T> d;
+    SO::load(op, Vh, s, d);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.v[sp][c] = acc.v[sp][c] + d.v[sp][c];
+  }
+  if (a.nt_out) SO::store_nt(op, Vh, s, acc);
+  else SO::store(op, Vh, s, acc);
+}
+
+template <class SI, class SO, class LK, class T, int W>
+static void dslash_quad_go(hipStream_t st, const DslashArgs& a, int nprop) {
+  int tiles = a.np * ((a.nb * a.g.Vbh + 63) / 64);
+  dim3 grid(tiles, a.nrhs, nprop);
+  launch_timed((k_dslash_quad<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
+}
+
 // Full-lattice stencil variants (form x register budget), chosen by the autotuner:
 //   0: one lane per site          1: two wave groups per site
 //   2: one lane, >= 4 waves/SIMD  3: split, >= 4 waves/SIMD
 //   4: one lane, >= 6 waves/SIMD  5: split, >= 6 waves/SIMD
+//   6: four lanes per site, >= 2 waves/SIMD
 template <class SI, class SO, class LK, class T>
 static void dslash_variant(hipStream_t st, const DslashArgs& a, int nprop, int v) {
   switch (v) {
@@ -258,6 +357,7 @@ static void dslash_variant(hipStream_t st, const DslashArgs& a, int nprop, int v
     case 3: dslash_split_go<SI, SO, LK, T, 4>(st, a, nprop); break;
     case 4: dslash_one_go<SI, SO, LK, T, 6>(st, a, nprop); break;
     case 5: dslash_split_go<SI, SO, LK, T, 6>(st, a, nprop); break;
+    case 6: dslash_quad_go<SI, SO, LK, T, 2>(st, a, nprop); break;
     default: dslash_one_go<SI, SO, LK, T, 1>(st, a, nprop); break;
   }
 }

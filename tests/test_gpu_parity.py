@@ -49,6 +49,30 @@ def test_dw_f64_matches_oracle(psms, L, b):
         assert rel(out[r], ref) < 1e-13
 
 
+@pytest.mark.parametrize("L,b", [((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (4, 2, 2, 2))])
+def test_dw_every_stencil_form(psms, L, b):
+    """Every full-lattice stencil form the autotuner can pick (variants 0..6, one right-hand
+    side per thread, three right-hand sides per launch), FP64 against the oracle to 1e-13
+    and FP32 links/spinors to 2e-6."""
+    kappa = 0.137
+    U = synth.gauge_field(L, 0.6, 13)
+    psi = synth.gaussian_noise(L, 3, 14)
+    ref = [dirac.apply_D(U, psi[r], kappa, L) for r in range(3)]
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    ctx.set_tuning("nr_f64", 1)
+    ctx.set_tuning("nr_low", 1)
+    for v in range(7):
+        say("case stencil form", v, L)
+        ctx.set_tuning("dslash_variant_f64", v)
+        ctx.set_tuning("dslash_variant_f32", v)
+        out = ctx.apply_dw(0, psi)
+        out32 = ctx.apply_dw(0, psi, prec=psms.MIXED)
+        for r in range(3):
+            assert rel(out[r], ref[r]) < 1e-13
+            assert rel(out32[r], ref[r]) < 2e-6
+
+
 def test_dw_periodic_time(psms):
     L, b = (4, 4, 4, 4), (2, 2, 2, 2)
     U = synth.gauge_field(L, 0.6, 13)
