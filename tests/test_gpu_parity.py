@@ -49,7 +49,8 @@ def test_dw_f64_matches_oracle(psms, L, b):
         assert rel(out[r], ref) < 1e-13
 
 
-@pytest.mark.parametrize("L,b", [((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (4, 2, 2, 2))])
+@pytest.mark.parametrize("L,b", [((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (4, 2, 2, 2)),
+                                 ((16, 16, 16, 16), (8, 8, 8, 8)), ((8, 16, 16, 16), (4, 8, 8, 8))])
 def test_dw_every_stencil_form(psms, L, b):
     """Every full-lattice stencil form the autotuner can pick (variants 0..6, one right-hand
     side per thread, three right-hand sides per launch), FP64 against the oracle to 1e-13
