@@ -106,7 +106,9 @@ struct BlockMRParams {
   double kappa;
   int face = 0;   // 1: first rho_b -= D_{b,other} delta_other across the block faces
   int lanes = 0;  // LDS-resident 256-site blocks: lanes per site (1, 2; 0 = by grid size)
-  int eo = 0;     // LDS-resident 256-site blocks: even-odd preconditioned minimal residual
+  int eo = 0;     // even-odd preconditioned minimal residual
+  const void* rho_in = nullptr;  // non-null: initial rho read from here (rho is still written)
+  int x_assign = 0;              // 1: x = delta instead of x += delta
 };
 // For every block of the colour: (optionally) the face update of rho_b from the
 // other colour's delta, then delta = MR approximation of D_b^-1 rho_b, x += delta,

@@ -22,6 +22,8 @@ struct BlockArgs {
   int face;  // 1: first apply the residual update across the block faces (see face_update)
   int lanes;  // LDS-resident form: 1 or 2 lanes per site (0: by grid size)
   int eo;     // 1: even-odd preconditioned minimal residual (k_block_mr_eo, k_block_mr_eo_g)
+  const void* rho_in;  // non-null: read the initial rho from here (same shape) instead of rho
+  int x_assign;        // 1: x = delta instead of x += delta (x need not be initialised)
   int* iters;
 };
 
@@ -137,6 +139,7 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   unit* pb = reinterpret_cast<unit*>(a.pbuf) + roff;
@@ -149,11 +152,9 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   for (int j = threadIdx.x; j < nsite; j += blockDim.x) {
     int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
     Spinor<T> v, z;
-    S::load(rho + size_t(p) * S::NC * Vh, Vh, s, v);
-    if (a.face) {
-      face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), v);
-      S::store(rho + size_t(p) * S::NC * Vh, Vh, s, v);
-    }
+    S::load(rin + size_t(p) * S::NC * Vh, Vh, s, v);
+    if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), v);
+    if (a.face || a.rho_in) S::store(rho + size_t(p) * S::NC * Vh, Vh, s, v);
     zero(z);
     S::store(dl + size_t(p) * S::NC * Vh, Vh, s, z);
 #pragma unroll
@@ -215,7 +216,8 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
     int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
     Spinor<T> d, xv;
     S::load(dl + size_t(p) * S::NC * Vh, Vh, s, d);
-    S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+    if (a.x_assign) zero(xv);
+    else S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -272,6 +274,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo_g(BlockArgs a) {
   const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   unit* pb = reinterpret_cast<unit*>(a.pbuf) + roff;
@@ -285,11 +288,9 @@ __global__ void __launch_bounds__(256) k_block_mr_eo_g(BlockArgs a) {
   for (int j = threadIdx.x; j < 2 * H; j += blockDim.x) {
     const int p = j / H, s = blk * H + (j - p * H);
     Spinor<T> v;
-    S::load(rho + p * odd, Vh, s, v);
-    if (a.face) {
-      face_update<S, LK, T>(g, lk, dl, p, s, kp, v);
-      S::store(rho + p * odd, Vh, s, v);
-    }
+    S::load(rin + p * odd, Vh, s, v);
+    if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, kp, v);
+    if (a.face || a.rho_in) S::store(rho + p * odd, Vh, s, v);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -378,14 +379,16 @@ __global__ void __launch_bounds__(256) k_block_mr_eo_g(BlockArgs a) {
     S::store(dl + odd, Vh, s, d);
     zero(z);
     S::store(rho + odd, Vh, s, z);
-    S::load(x + odd, Vh, s, xv);
+    if (a.x_assign) zero(xv);
+    else S::load(x + odd, Vh, s, xv);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
     S::store(x + odd, Vh, s, xv);
     S::load(dl, Vh, s, d);
-    S::load(x, Vh, s, xv);
+    if (a.x_assign) zero(xv);
+    else S::load(x, Vh, s, xv);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -420,6 +423,7 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
   const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
@@ -452,7 +456,7 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
       for (int k = 0; k < 3; ++k) lk_lds[mu * 3 + k][t] = reinterpret_cast<const float4*>(lk)[(size_t(p * 4 + mu) * 3 + k) * Vh + s];
   }
   Spinor<T> r, d;
-  S::load(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+  S::load(rin + size_t(p) * S::NC * Vh, Vh, s, r);
   if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), r);
   zero(d);
   double b2 = 0.0;
@@ -538,7 +542,8 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
   S::store(rho + size_t(p) * S::NC * Vh, Vh, s, r);
   S::store(dl + size_t(p) * S::NC * Vh, Vh, s, d);
   Spinor<T> xv;
-  S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+  if (a.x_assign) zero(xv);
+  else S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -568,6 +573,7 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
   const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
@@ -599,7 +605,7 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
   zero(d);
   double b2 = 0.0;
   if (h == 0) {
-    S::load(rho + size_t(p) * S::NC * Vh, Vh, s, r);
+    S::load(rin + size_t(p) * S::NC * Vh, Vh, s, r);
     if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), r);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -691,7 +697,8 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
     S::store(rho + size_t(p) * S::NC * Vh, Vh, s, r);
     S::store(dl + size_t(p) * S::NC * Vh, Vh, s, d);
     Spinor<T> xv;
-    S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+    if (a.x_assign) zero(xv);
+    else S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -728,6 +735,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
@@ -816,7 +824,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
 
   // own site (parity h): rho (+ the face update), |rho|^2 over the block
   Spinor<T> r, d, acc;
-  S::load(rho + size_t(h) * S::NC * Vh, Vh, s, r);
+  S::load(rin + size_t(h) * S::NC * Vh, Vh, s, r);
   if (a.face) face_update<S, LK, T>(g, lk, dl, h, s, kp, r);
   double b2 = 0.0;
 #pragma unroll
@@ -920,7 +928,8 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   S::store(rho + size_t(h) * S::NC * Vh, Vh, s, r);
   S::store(dl + size_t(h) * S::NC * Vh, Vh, s, d);
   Spinor<T> xv;
-  S::load(x + size_t(h) * S::NC * Vh, Vh, s, xv);
+  if (a.x_assign) zero(xv);
+  else S::load(x + size_t(h) * S::NC * Vh, Vh, s, xv);
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -977,6 +986,8 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
   a.face = bp.face;
   a.lanes = bp.lanes;
   a.eo = bp.eo;
+  a.rho_in = bp.rho_in;
+  a.x_assign = bp.x_assign;
   a.iters = iters_out;
   if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);
   else if (rho.prec == P_F32 && linkfmt == LK_F32C12) block_go<StF32, LkF32C12, float>(st, a, rho.nprop);

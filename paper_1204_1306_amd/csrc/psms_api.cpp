@@ -456,10 +456,14 @@ double block_bytes(psms_ctx* c, const Links& L, const FieldBatch& rho, int face 
 void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& r, const FieldBatch& z) {
   const int np = r.nprop, nr = r.nrhs;
   FieldBatch rho = field(c, "sap_rho", sc.prec, np, nr);
-  FieldBatch xs = field(c, "sap_x", sc.prec, np, nr);
   FieldBatch dl = field(c, "sap_delta", sc.prec, np, nr);
   FieldBatch pb = field(c, "sap_p", sc.prec, np, nr);
-  {
+  // The sweeps of the first cycle read their residual straight from r and assign the
+  // iterate (x = delta), so neither a copy of r nor a zeroed iterate is needed; the
+  // iterate is z itself when z has the solver's storage.
+  const bool direct = z.prec == sc.prec && r.prec == sc.prec;
+  FieldBatch xs = direct ? z : field(c, "sap_x", sc.prec, np, nr);
+  if (!direct || sc.cycles <= 0) {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_copy(c->st, c->g, r, rho, nullptr);
     launch_zero(c->st, xs, c->Vh);
@@ -479,12 +483,18 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
       bp.face = (cy > 0 || col > 0) ? 1 : 0;
       bp.lanes = c->block_lanes;
       bp.eo = eo ? 1 : 0;
+      if (direct && cy == 0) {
+        bp.rho_in = r.p;
+        bp.x_assign = 1;
+      }
       ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho, bp.face));
       launch_block_mr(c->st, c->g, L.p, L.fmt, rho, xs, dl, pb, bp, nullptr);
     }
   }
-  ProfScope ps(c, FAM_BLAS, 0);
-  launch_copy(c->st, c->g, xs, z, nullptr);
+  if (!direct) {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_copy(c->st, c->g, xs, z, nullptr);
+  }
 }
 
 // ------------------------------------------------------------------ flexible GCR
