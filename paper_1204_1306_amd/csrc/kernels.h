@@ -97,6 +97,11 @@ void reduce_norm2(hipStream_t st, const Geo& g, const FieldBatch& x, const Reduc
 // out[r*m + j] = (X_j, y)_r for j < m, X_j = basis + j*vstride
 void reduce_multidot(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m,
                      const FieldBatch& y, const Reducer& R, double2* out);
+// out3[r*3] = {|x|^2, Re (x, y), Im (x, y)} in one pass (x, y of one storage)
+void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double* out3);
+// y += a[r] x and out[r] = |y|^2 in one pass (x, y of one storage)
+void axpy_norm2(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
+                double* out);
 
 // --- block solver (Schwarz / Dirichlet block inverses, minimal residual)
 struct BlockMRParams {
@@ -121,6 +126,9 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
 void gcr_proj(hipStream_t st, const double2* c, const double* nw, int k, int m, int nrhs, double2* a, double2* T);
 void gcr_alpha(hipStream_t st, const double2* d, const double* nw, int k, int m, int nrhs, const int* active, double2* alpha,
                double2* neg_alpha);
+// the same from nd[r*3] = {|w_k|^2, (w_k, r)}, also storing nw[r*m + k] = |w_k|^2
+void gcr_alpha_nd(hipStream_t st, const double* nd, int k, int m, int nrhs, const int* active, double* nw, double2* alpha,
+                  double2* neg_alpha);
 void gcr_backsub(hipStream_t st, const double2* T, const double2* alpha, int n, int m, int nrhs, double2* beta);
 void scatter_col(hipStream_t st, const double* src, int k, int m, int nrhs, double* dst);
 void defect_scales(hipStream_t st, const double* v, const int* active, int nrhs, double* inv, double2* sq);

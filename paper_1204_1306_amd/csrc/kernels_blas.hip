@@ -300,8 +300,8 @@ __global__ void k_multidot_p1(const typename Unit<P>::unit* __restrict__ basis, 
 template <Prec P> static void multidot_go(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const FieldBatch& y,
                                           const Reducer& R, double2* out) {
   size_t n = units_per_field(P, g.Vh);
-  for (int j0 = 0; j0 < m; j0 += 4)
-    hipLaunchKernelGGL((k_multidot_p1<P, 4>), dim3(R.nwg, nrhs_of(y)), dim3(256), 0, st, (const typename Unit<P>::unit*)basis.p,
+  for (int j0 = 0; j0 < m; j0 += 16)
+    hipLaunchKernelGGL((k_multidot_p1<P, 16>), dim3(R.nwg, nrhs_of(y)), dim3(256), 0, st, (const typename Unit<P>::unit*)basis.p,
                        vstride, j0, m, (const typename Unit<P>::unit*)y.p, n, R.partial);
   hipLaunchKernelGGL(k_reduce_final, dim3(nrhs_of(y) * m), dim3(256), 0, st, R.partial, R.nwg, 2, (double*)out);
 }
@@ -309,6 +309,87 @@ void reduce_multidot(hipStream_t st, const Geo& g, const FieldBatch& basis, size
                      const Reducer& R, double2* out) {
   if (m <= 0) return;
   DISPATCH_PREC(y.prec, multidot_go, st, g, basis, vstride, m, y, R, out);
+}
+
+// |x|^2 and (x, y) (conj on x) in one pass; partial [(r * nwg + w) * 3 + {|x|^2, Re, Im}]
+template <Prec P>
+__global__ void k_norm_dot_p1(const typename Unit<P>::unit* __restrict__ x, const typename Unit<P>::unit* __restrict__ y,
+                              size_t n, double* __restrict__ partial) {
+  using U = Unit<P>;
+  using T = typename U::T;
+  __shared__ double sm[16];
+  const int r = blockIdx.y;
+  const size_t off = size_t(r) * n;
+  double xx = 0.0, re = 0.0, im = 0.0;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    cx<T> xv[U::N], yv[U::N];
+    U::ld(x[off + i], xv);
+    U::ld(y[off + i], yv);
+#pragma unroll
+    for (int e = 0; e < U::N; ++e) {
+      const double xr = xv[e].re, xi = xv[e].im, yr = yv[e].re, yi = yv[e].im;
+      xx += xr * xr + xi * xi;
+      re += xr * yr + xi * yi;
+      im += xr * yi - xi * yr;
+    }
+  }
+  const double t0 = block_sum(xx, sm), t1 = block_sum(re, sm), t2 = block_sum(im, sm);
+  if (threadIdx.x == 0) {
+    const size_t q = size_t(r) * gridDim.x + blockIdx.x;
+    partial[3 * q] = t0;
+    partial[3 * q + 1] = t1;
+    partial[3 * q + 2] = t2;
+  }
+}
+template <Prec P> static void norm_dot_go(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
+                                          double* out3) {
+  size_t n = units_per_field(P, g.Vh);
+  hipLaunchKernelGGL(k_norm_dot_p1<P>, dim3(R.nwg, nrhs_of(x)), dim3(256), 0, st, (const typename Unit<P>::unit*)x.p,
+                     (const typename Unit<P>::unit*)y.p, n, R.partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs_of(x)), dim3(256), 0, st, R.partial, R.nwg, 3, out3);
+}
+void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double* out3) {
+  DISPATCH_PREC(x.prec, norm_dot_go, st, g, x, y, R, out3);
+}
+
+// y += a[r] * x and the partial sums of |y|^2 (new y) in one pass
+template <Prec P>
+__global__ void k_axpy_norm_p1(const double2* __restrict__ a, const typename Unit<P>::unit* __restrict__ x,
+                               typename Unit<P>::unit* __restrict__ y, size_t n, double* __restrict__ partial) {
+  using U = Unit<P>;
+  using T = typename U::T;
+  __shared__ double sm[16];
+  const int r = blockIdx.y;
+  const cx<T> A = {T(a[r].x), T(a[r].y)};
+  const size_t off = size_t(r) * n;
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    cx<T> xv[U::N], yv[U::N];
+    U::ld(x[off + i], xv);
+    U::ld(y[off + i], yv);
+#pragma unroll
+    for (int e = 0; e < U::N; ++e) yv[e] = yv[e] + cmul(A, xv[e]);
+    typename U::unit u;
+    U::st(u, yv);
+    y[off + i] = u;
+    cx<T> zv[U::N];  // the stored (rounded) values enter the norm
+    U::ld(u, zv);
+#pragma unroll
+    for (int e = 0; e < U::N; ++e) acc += double(zv[e].re) * double(zv[e].re) + double(zv[e].im) * double(zv[e].im);
+  }
+  const double t = block_sum(acc, sm);
+  if (threadIdx.x == 0) partial[size_t(r) * gridDim.x + blockIdx.x] = t;
+}
+template <Prec P> static void axpy_norm_go(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y,
+                                           const Reducer& R, double* out) {
+  size_t n = units_per_field(P, g.Vh);
+  hipLaunchKernelGGL(k_axpy_norm_p1<P>, dim3(R.nwg, nrhs_of(y)), dim3(256), 0, st, a, (const typename Unit<P>::unit*)x.p,
+                     (typename Unit<P>::unit*)y.p, n, R.partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs_of(y)), dim3(256), 0, st, R.partial, R.nwg, 1, out);
+}
+void axpy_norm2(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
+                double* out) {
+  DISPATCH_PREC(y.prec, axpy_norm_go, st, g, a, x, y, R, out);
 }
 
 }  // namespace psms

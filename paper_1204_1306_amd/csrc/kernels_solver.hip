@@ -46,6 +46,21 @@ void gcr_proj(hipStream_t st, const double2* c, const double* nw, int k, int m, 
   if (k <= 0) return;
   hipLaunchKernelGGL(k_gcr_proj, dim3((nrhs * k + 255) / 256), dim3(256), 0, st, c, nw, k, m, nrhs, a, T);
 }
+// From nd[r*3] = {|w_k|^2, Re (w_k, r), Im (w_k, r)}: nw[r*m + k] = |w_k|^2 and alpha as in k_gcr_alpha
+__global__ void k_gcr_alpha_nd(const double* __restrict__ nd, int k, int m, int nrhs, const int* __restrict__ active,
+                               double* __restrict__ nw, double2* __restrict__ alpha, double2* __restrict__ neg_alpha) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double n = nd[3 * r];
+  nw[r * m + k] = n;
+  double2 v = (active[r] && n > 0) ? make_double2(nd[3 * r + 1] / n, nd[3 * r + 2] / n) : make_double2(0, 0);
+  alpha[k * nrhs + r] = v;
+  neg_alpha[r] = make_double2(-v.x, -v.y);
+}
+void gcr_alpha_nd(hipStream_t st, const double* nd, int k, int m, int nrhs, const int* active, double* nw, double2* alpha,
+                  double2* neg_alpha) {
+  hipLaunchKernelGGL(k_gcr_alpha_nd, dim3((nrhs + 255) / 256), dim3(256), 0, st, nd, k, m, nrhs, active, nw, alpha, neg_alpha);
+}
 void gcr_alpha(hipStream_t st, const double2* d, const double* nw, int k, int m, int nrhs, const int* active, double2* alpha,
                double2* neg_alpha) {
   hipLaunchKernelGGL(k_gcr_alpha, dim3((nrhs + 255) / 256), dim3(256), 0, st, d, nw, k, m, nrhs, active, alpha, neg_alpha);

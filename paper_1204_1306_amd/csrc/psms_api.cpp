@@ -542,10 +542,11 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
   double2* BETA = dscratch<double2>(c, "gcr_beta", size_t(nr) * m);
   double2* D1 = dscratch<double2>(c, "gcr_d", nr);
   int* active = dscratch<int>(c, "gcr_active", nr);
+  double* ND = dscratch<double>(c, "gcr_nd", size_t(nr) * 3);
   const double2* ONE = const_cx(c, "one", nr, 1.0, 0.0);
   const double2* MONE = const_cx(c, "mone", nr, -1.0, 0.0);
   const bool same = cf.wprec == cf.rprec;
-  Reducer R = reducer(c, nr, m);
+  Reducer R = reducer(c, nr, std::max(m, 2));  // the fused |w|^2, (w, r) pass needs 3 doubles per partial
 
   {
     ProfScope ps(c, FAM_BLAS, 0);
@@ -588,14 +589,18 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
           gcr_proj(st, C, NW, k, m, nr, A, T);
           launch_lincomb(st, g, W, vstride, k, A, m, Wk, -1);
         }
-        reduce_norm2(st, g, Wk, R, nw1);
-        scatter_col(st, nw1, k, m, nr, NW);
-        if (same) reduce_multidot(st, g, Wk, vstride, 1, r, R, D1);
-        else reduce_dot_mixed(st, g, Wk, r, R, D1);
-        gcr_alpha(st, D1, NW, k, m, nr, active, ALPHA, NEGA);
-        if (same) launch_axpby(st, g, NEGA, Wk, nullptr, r, +1);
-        else launch_axpy_mixed(st, g, NEGA, Wk, r, +1);
-        reduce_norm2(st, g, r, R, rn2);
+        if (same) {  // fused passes: |w_k|^2 with (w_k, r), then r -= alpha w_k with |r|^2
+          reduce_norm_dot(st, g, Wk, r, R, ND);
+          gcr_alpha_nd(st, ND, k, m, nr, active, NW, ALPHA, NEGA);
+          axpy_norm2(st, g, NEGA, Wk, r, R, rn2);
+        } else {
+          reduce_norm2(st, g, Wk, R, nw1);
+          scatter_col(st, nw1, k, m, nr, NW);
+          reduce_dot_mixed(st, g, Wk, r, R, D1);
+          gcr_alpha(st, D1, NW, k, m, nr, active, ALPHA, NEGA);
+          launch_axpy_mixed(st, g, NEGA, Wk, r, +1);
+          reduce_norm2(st, g, r, R, rn2);
+        }
       }
       // Residual norms go to pinned host memory behind an event; the check of
       // iteration k - 1 happens after iteration k is enqueued, so the host never idles
