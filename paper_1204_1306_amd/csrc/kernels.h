@@ -134,6 +134,12 @@ void scatter_col(hipStream_t st, const double* src, int k, int m, int nrhs, doub
 void defect_scales(hipStream_t st, const double* v, const int* active, int nrhs, double* inv, double2* sq);
 void launch_axpy_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, int sgn);
 void reduce_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double2* out);
+// fused passes for a BF16 basis vector x and an FP32 residual y (fused_mixed_ok)
+bool fused_mixed_ok(const FieldBatch& x, const FieldBatch& y);
+void reduce_norm_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
+                           double* out3);
+void axpy_norm2_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
+                      double* out);
 
 // --- gauge-covariant network
 // one layer (forward, or adjoint with adj = 1) on F32 activations [batch][channel][field]

@@ -177,4 +177,110 @@ void reduce_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const F
   hipLaunchKernelGGL(k_reduce_pairs, dim3(y.nprop * y.nrhs), dim3(64), 0, st, R.partial, R.nwg, (double*)out);
 }
 
+
+// |x|^2 and (x, y) in one site-level pass for a BF16 x and an FP32 y;
+// partial [(r * nwg + w) * 3 + {|x|^2, Re, Im}]
+__global__ void k_norm_dot_bf16_f32(Geo g, const uint4* __restrict__ x, const float4* __restrict__ y,
+                                    double* __restrict__ partial) {
+  __shared__ double sm[3][16];
+  const int r = blockIdx.y;
+  double xx = 0, re = 0, im = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * g.Vh; t += gridDim.x * blockDim.x) {
+    const int p = t / g.Vh, i = t - p * g.Vh;
+    Spinor<float> xv, yv;
+    StBF16::load(x + (size_t(r) * 2 + p) * StBF16::NC * g.Vh, g.Vh, i, xv);
+    StF32::load(y + (size_t(r) * 2 + p) * StF32::NC * g.Vh, g.Vh, i, yv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double xr = xv.v[q][c].re, xi = xv.v[q][c].im, yr = yv.v[q][c].re, yi = yv.v[q][c].im;
+        xx += xr * xr + xi * xi;
+        re += xr * yr + xi * yi;
+        im += xr * yi - xi * yr;
+      }
+  }
+  xx = wave_sum(xx);
+  re = wave_sum(re);
+  im = wave_sum(im);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+    sm[0][w] = xx;
+    sm[1][w] = re;
+    sm[2][w] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0, c = 0;
+    for (int k = 0; k < nw; ++k) {
+      a += sm[0][k];
+      b += sm[1][k];
+      c += sm[2][k];
+    }
+    const size_t q = size_t(r) * gridDim.x + blockIdx.x;
+    partial[3 * q] = a;
+    partial[3 * q + 1] = b;
+    partial[3 * q + 2] = c;
+  }
+}
+
+// y += a[r] x (BF16 x, FP32 y) and the partial sums of |y|^2 in one site-level pass
+__global__ void k_axpy_norm_bf16_f32(Geo g, const double2* __restrict__ a, const uint4* __restrict__ x,
+                                     float4* __restrict__ y, double* __restrict__ partial) {
+  __shared__ double sm[16];
+  const int r = blockIdx.y;
+  const cx<float> A = {float(a[r].x), float(a[r].y)};
+  double acc = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * g.Vh; t += gridDim.x * blockDim.x) {
+    const int p = t / g.Vh, i = t - p * g.Vh;
+    Spinor<float> xv, yv;
+    StBF16::load(x + (size_t(r) * 2 + p) * StBF16::NC * g.Vh, g.Vh, i, xv);
+    float4* yp = y + (size_t(r) * 2 + p) * StF32::NC * g.Vh;
+    StF32::load(yp, g.Vh, i, yv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        yv.v[q][c] = yv.v[q][c] + cmul(A, xv.v[q][c]);
+        acc += double(yv.v[q][c].re) * yv.v[q][c].re + double(yv.v[q][c].im) * yv.v[q][c].im;
+      }
+    StF32::store(yp, g.Vh, i, yv);  // FP32 storage holds these float values exactly
+  }
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) sm[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int k = 0; k < nw; ++k) s += sm[k];
+    partial[size_t(r) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out[r * width + c] = sum_w partial[(r * nwg + w) * width + c], in order
+__global__ void k_reduce_width(const double* __restrict__ partial, int nwg, int width, double* __restrict__ out) {
+  const int r = blockIdx.x;
+  if (threadIdx.x < width) {
+    double s = 0;
+    for (int w = 0; w < nwg; ++w) s += partial[(size_t(r) * nwg + w) * width + threadIdx.x];
+    out[size_t(r) * width + threadIdx.x] = s;
+  }
+}
+
+bool fused_mixed_ok(const FieldBatch& x, const FieldBatch& y) { return x.prec == P_BF16 && y.prec == P_F32; }
+
+void reduce_norm_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
+                           double* out3) {
+  dim3 grid(R.nwg, y.nprop * y.nrhs);
+  hipLaunchKernelGGL(k_norm_dot_bf16_f32, grid, dim3(256), 0, st, g, (const uint4*)x.p, (const float4*)y.p, R.partial);
+  hipLaunchKernelGGL(k_reduce_width, dim3(y.nprop * y.nrhs), dim3(64), 0, st, R.partial, R.nwg, 3, out3);
+}
+
+void axpy_norm2_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
+                      double* out) {
+  dim3 grid(R.nwg, y.nprop * y.nrhs);
+  hipLaunchKernelGGL(k_axpy_norm_bf16_f32, grid, dim3(256), 0, st, g, a, (const uint4*)x.p, (float4*)y.p, R.partial);
+  hipLaunchKernelGGL(k_reduce_width, dim3(y.nprop * y.nrhs), dim3(64), 0, st, R.partial, R.nwg, 1, out);
+}
+
 }  // namespace psms

@@ -593,6 +593,10 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
           reduce_norm_dot(st, g, Wk, r, R, ND);
           gcr_alpha_nd(st, ND, k, m, nr, active, NW, ALPHA, NEGA);
           axpy_norm2(st, g, NEGA, Wk, r, R, rn2);
+        } else if (fused_mixed_ok(Wk, r)) {
+          reduce_norm_dot_mixed(st, g, Wk, r, R, ND);
+          gcr_alpha_nd(st, ND, k, m, nr, active, NW, ALPHA, NEGA);
+          axpy_norm2_mixed(st, g, NEGA, Wk, r, R, rn2);
         } else {
           reduce_norm2(st, g, Wk, R, nw1);
           scatter_col(st, nw1, k, m, nr, NW);
