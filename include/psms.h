@@ -216,11 +216,11 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
  * per block, 1 flexible GCR on the block-diagonal operator) and "block_lanes" (block
  * solver for 256-site blocks with 12-real links: 1 or 2 lanes per site, 0 = two lanes
  * when the launch has fewer than two workgroups per compute unit) and "block_eo" (block
- * solver for 256-site blocks: 1 works on the even-odd Schur complement of each block,
- * where an iteration counts as about two plain ones; 0 plain; 2, the default, even-odd
- * for block inverses to a tolerance and, for Schwarz sweeps, when the launch has fewer
- * than two workgroups per compute unit or runs in FP64, with block_iters/2 iterations
- * rounded up). Unknown keys or values give
+ * solver: 0 plain minimal residual; 1 minimal residual on the even-odd Schur complement of
+ * each block, where an iteration counts as about two plain ones, 12-real links staged in
+ * LDS; 3 the same with links read from L2; 2, the default, even-odd throughout, links
+ * staged when the launch has fewer than two workgroups per compute unit, and Schwarz
+ * sweeps with block_iters/2 iterations rounded up). Unknown keys or values give
  * PSMS_EINVAL. Results do not depend on the tuning beyond rounding; only speed does. */
 psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);
 psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);

@@ -21,7 +21,8 @@ struct BlockArgs {
   double tol, kappa;
   int face;  // 1: first apply the residual update across the block faces (see face_update)
   int lanes;  // LDS-resident form: 1 or 2 lanes per site (0: by grid size)
-  int eo;     // 1: even-odd preconditioned minimal residual (k_block_mr_eo, k_block_mr_eo_g)
+  int eo;     // 1: even-odd preconditioned minimal residual (k_block_mr_eo, k_block_mr_eo_g);
+              // 2: the same with 12-real links read from L2 instead of LDS
   const void* rho_in;  // non-null: read the initial rho from here (same shape) instead of rho
   int x_assign;        // 1: x = delta instead of x += delta (x need not be initialised)
   int* iters;
@@ -719,10 +720,12 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
 // Thread (j, h): site j of each parity; every hop phase gives each site two lanes
 // (h = 0 forward hops, h = 1 backward hops, wave-uniform), so no SIMD idles while
 // only one parity computes. The even-site state lives in lane 0, the odd in lane 1.
-template <class S, class LK, class T>
+template <class S, class LK, class T, bool STAGE = true>
 __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   constexpr int H = 128;  // sites per parity
-  constexpr bool LL = LdsLinks<LK>::on;
+  // STAGE: 12-real links staged in LDS (98 KB, one workgroup per CU); otherwise read
+  // from L2 at each hop (49 KB, two workgroups per CU)
+  constexpr bool LL = LdsLinks<LK>::on && STAGE;
   __shared__ cx<T> ev[12][H];     // an even-site field
   __shared__ cx<T> od[2][12][H];  // odd-site partial sums of the two lanes
   __shared__ cx<T> eb[12][H];     // even-site partial sum of lane 1
@@ -942,6 +945,10 @@ template <class S, class LK, class T>
 static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
   if (2 * a.g.Vbh == 256) {
     const dim3 grid(a.g.nblk_c, a.nrhs, nprop);
+    if (a.eo == 2 && LdsLinks<LK>::on) {
+      launch_timed((k_block_mr_eo<S, LK, T, false>), grid, dim3(256), 0, st, a);
+      return;
+    }
     if (a.eo) {
       launch_timed((k_block_mr_eo<S, LK, T>), grid, dim3(256), 0, st, a);
       return;

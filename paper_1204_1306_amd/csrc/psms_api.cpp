@@ -468,13 +468,18 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
     launch_copy(c->st, c->g, r, rho, nullptr);
     launch_zero(c->st, xs, c->Vh);
   }
-  // Block solver form: even-odd minimal residual (block_eo 1), plain (0), or by launch
-  // shape (2): even-odd when the grid has fewer than two workgroups per CU or the
-  // solver runs in FP64 (both forms then hold one workgroup per CU), with half the
-  // iterations, one even-odd iteration reducing the residual about as much as two plain.
+  // Block solver form: plain minimal residual (block_eo 0) or even-odd with the 12-real
+  // links staged in LDS (1) or read from L2 (3); by launch shape (2, the default): even-odd,
+  // staged when the grid has fewer than two workgroups per CU (one 98 KB workgroup per CU
+  // is then no loss), else from L2 so that two workgroups share a CU. With 2 and 3 the
+  // Schwarz sweeps run half the iterations, one even-odd iteration reducing the residual
+  // about as much as two plain ones.
   const int wgs = c->g.nblk_c * r.nrhs * r.nprop;
-  const bool eo = c->block_eo == 1 || (c->block_eo == 2 && (wgs < 512 || sc.prec == P_F64));
-  const int iters = (eo && c->block_eo == 2) ? (sc.iters + 1) / 2 : sc.iters;
+  const int eo_form = c->block_eo == 0 ? 0
+                      : c->block_eo == 1 ? 1
+                      : c->block_eo == 3 ? 2
+                                         : (wgs < 512 ? 1 : 2);
+  const int iters = c->block_eo >= 2 ? (sc.iters + 1) / 2 : sc.iters;
   // Each sweep first applies rho_col -= D_{col,other} delta_other across its block
   // faces (fused into the block kernel), except the very first, where no delta exists.
   for (int cy = 0; cy < sc.cycles; ++cy) {
@@ -482,7 +487,7 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
       BlockMRParams bp{col, iters, 0.0, c->geom.kappa};
       bp.face = (cy > 0 || col > 0) ? 1 : 0;
       bp.lanes = c->block_lanes;
-      bp.eo = eo ? 1 : 0;
+      bp.eo = eo_form;
       if (direct && cy == 0) {
         bp.rho_in = r.p;
         bp.x_assign = 1;
@@ -1898,7 +1903,7 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
   if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 6, "stencil variant must be in [0, 6]");
   else if (!std::strcmp(key, "block_eo"))
-    REQUIRE(value >= 0 && value <= 2, "block_eo must be 0 (plain), 1 (even-odd) or 2 (by launch shape)");
+    REQUIRE(value >= 0 && value <= 3, "block_eo must be 0 (plain), 1 (even-odd), 2 (by launch shape) or 3 (even-odd, links from L2)");
   else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
   else if (!std::strcmp(key, "block_lanes"))

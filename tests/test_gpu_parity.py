@@ -158,7 +158,7 @@ def test_dhat_even_odd(psms):
     assert rel(ctx.apply_dhat_ee(0, psi), ref) < 1e-13
 
 
-@pytest.mark.parametrize("eo", [0, 1])
+@pytest.mark.parametrize("eo", [0, 1, 3])
 @pytest.mark.parametrize("prec", ["f64", "mixed_f32", "mixed_bf16"])
 def test_solve_parity(psms, prec, eo):
     """Full solves with Schwarz blocks solved by plain or even-odd minimal residual: FP64
