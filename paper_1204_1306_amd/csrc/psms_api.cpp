@@ -308,6 +308,24 @@ void build_geo(psms_ctx* c, const int* L, const int* b, int apbc, Geo& g) {
   g.border = dord;
 }
 
+// Host-only checks of a geometry, before any device work: a bad geometry is
+// PSMS_EINVAL with a message, whether or not a GPU is present.
+void check_geometry(const psms_geom* gm) {
+  REQUIRE(gm->kappa > 0 && std::isfinite(gm->kappa), "kappa must be positive");
+  const bool any = gm->sap_b[0] || gm->sap_b[1] || gm->sap_b[2] || gm->sap_b[3];
+  for (int m = 0; m < 4; ++m) {
+    REQUIRE(gm->L[m] > 0 && gm->L[m] <= 255, "L[mu] must be in [1, 255]");
+    REQUIRE(gm->b[m] > 0 && gm->L[m] % gm->b[m] == 0, "L[mu] must be a multiple of b[mu]");
+    REQUIRE(gm->b[m] % 2 == 0, "b[mu] must be even (even-odd order inside blocks)");
+    REQUIRE((gm->L[m] / gm->b[m]) % 2 == 0, "L[mu]/b[mu] must be even (consistent block colouring)");
+    if (any) {
+      REQUIRE(gm->sap_b[m] > 0 && gm->b[m] % gm->sap_b[m] == 0, "sap_b[mu] must divide b[mu]");
+      REQUIRE(gm->sap_b[m] % 2 == 0, "sap_b[mu] must be even");
+      REQUIRE((gm->L[m] / gm->sap_b[m]) % 2 == 0, "L[mu]/sap_b[mu] must be even");
+    }
+  }
+}
+
 void setup_geometry(psms_ctx* c, const psms_geom* gm) {
   REQUIRE(gm->kappa > 0 && std::isfinite(gm->kappa), "kappa must be positive");
   build_geo(c, gm->L, gm->b, gm->antiperiodic_t ? 1 : 0, c->g);
@@ -1264,6 +1282,12 @@ const char* psms_status_string(psms_status s) {
 psms_status psms_create(const psms_geom* geom, int device, void* hip_stream, psms_ctx** out) {
   if (!geom || !out) return PSMS_EINVAL;
   *out = nullptr;
+  try {
+    check_geometry(geom);
+  } catch (const Err& e) {
+    fprintf(stderr, "psms_create: %s\n", e.msg.c_str());
+    return e.st;
+  }
   psms_ctx* c = new psms_ctx();
   try {
     c->geom = *geom;

@@ -47,3 +47,27 @@ def test_null_and_bad_arguments_are_rejected_on_the_host():
     assert lib.psms_status_string(-4) == b"solver did not converge"
     p = psms.default_params()
     assert p.tol == 1e-10 and p.restart == 16 and p.pc == psms.PC_SAP
+
+
+@pytest.mark.parametrize("L,b,sap_b,kappa", [
+    ((8, 8, 8, 8), (3, 4, 4, 4), (0, 0, 0, 0), 0.15),   # L not a multiple of b
+    ((8, 8, 8, 8), (4, 4, 4, 8), (0, 0, 0, 0), 0.15),   # L/b odd in direction 3 (inconsistent colouring)
+    ((6, 6, 6, 6), (3, 3, 3, 3), (0, 0, 0, 0), 0.15),   # odd block extent (no even-odd order inside blocks)
+    ((8, 8, 8, 8), (4, 4, 4, 4), (0, 0, 0, 0), -0.1),   # negative kappa
+    ((8, 8, 8, 8), (4, 4, 4, 4), (2, 2, 2, 3), 0.15),   # Schwarz block does not divide the block
+    ((0, 8, 8, 8), (4, 4, 4, 4), (0, 0, 0, 0), 0.15),   # empty lattice
+])
+def test_bad_geometries_are_rejected_before_any_device_work(L, b, sap_b, kappa):
+    from paper_1204_1306_amd import psms
+
+    if not os.path.exists(psms.LIB_PATH):
+        pytest.skip("libpsms.so not built")
+    lib = psms.load_library()
+    g = psms.Geom()
+    for m in range(4):
+        g.L[m], g.b[m], g.sap_b[m] = L[m], b[m], sap_b[m]
+    g.antiperiodic_t = 1
+    g.kappa = kappa
+    out = ctypes.c_void_p()
+    assert lib.psms_create(ctypes.byref(g), 0, None, ctypes.byref(out)) == -1  # PSMS_EINVAL
+    assert not out.value
