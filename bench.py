@@ -79,10 +79,11 @@ TRAFFIC = {
     # even-odd FP32 block kernel, 8 blocks x 16 right-hand sides, Schwarz sweeps
     ("block_mr", "c2", "mixed"): {"bytes_per_launch": 24626704, "source": "kernels_block.hip",
                                   "sha256": "873d28cc390218d9b7cb9ef677c15132cf5c8a6a51d626747f43e2f9c1c066f6"},
-    # full-lattice FP64 stencil at 32^4, four lanes per site (variant 6) and split form (variant 1)
-    ("dslash_f64_v6", "32x32x32x32", "dw"): {"bytes_per_launch": 1748566215, "source": "kernels_dirac.hip",
+    # full-lattice FP64 stencil at 32^4 with 8^4 blocks, four lanes per site (variant 6) and
+    # split form (variant 1); keyed by lattice/blocks
+    ("dslash_f64_v6", "32x32x32x32/8x8x8x8", "dw"): {"bytes_per_launch": 1748566215, "source": "kernels_dirac.hip",
                                              "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
-    ("dslash_f64_v1", "32x32x32x32", "dw"): {"bytes_per_launch": 1703598494, "source": "kernels_dirac.hip",
+    ("dslash_f64_v1", "32x32x32x32/8x8x8x8", "dw"): {"bytes_per_launch": 1703598494, "source": "kernels_dirac.hip",
                                              "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
 }
 
@@ -132,6 +133,18 @@ def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=Fal
     return dt, stats, fam, d
 
 
+def dw_blocks(L, spec: str = "auto"):
+    """Block layout of the D_w leg. The operator does not depend on it; the layout sets
+    which sites a workgroup tile and its concurrent neighbours touch. "auto" takes blocks
+    of L/8, L/8, L/4, L/2 (4x4x8x16 at 32^4: long along the fastest direction, measured
+    best among the shapes tried), else an explicit "b0,b1,b2,b3"."""
+    if spec != "auto":
+        return tuple(int(v) for v in spec.split(","))
+    b = (L[0] // 8, L[1] // 8, L[2] // 4, L[3] // 2)
+    ok = all(x >= 2 and x % 2 == 0 and l % x == 0 and (l // x) % 2 == 0 for x, l in zip(b, L))
+    return b if ok else tuple(max(2, v // 4) for v in L)
+
+
 def dw_bandwidth(psms, L, b, kappa, reps=20):
     """Full-lattice D_w launches on device-resident fields (FP64 and mixed), HIP events on
     the library's stream, on an L lattice (32^4 by default: its working set exceeds the
@@ -145,7 +158,7 @@ def dw_bandwidth(psms, L, b, kappa, reps=20):
     ctx.gauge_load(0, torch.from_numpy(synth.gauge_field(L, 0.6, 5001)).to(dev))
     tune = ctx.autotune(0, None)
     psi = torch.from_numpy(synth.gaussian_noise(L, 1, 7)).to(dev)
-    out = {"lattice": "x".join(map(str, L)), "tuning": tune}
+    out = {"lattice": "x".join(map(str, L)), "blocks": "x".join(map(str, b)), "tuning": tune}
     for name, prec in (("f64", psms.F64), ("mixed", psms.MIXED)):
         ctx.apply_dw(0, psi, prec)
         torch.cuda.synchronize()
@@ -351,6 +364,7 @@ def main():
     ap.add_argument("--learned-pairs", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--dw-lattice", default="32,32,32,32")
+    ap.add_argument("--dw-blocks", default="auto")
     ap.add_argument("--batched-workload", default="c3", help="'none' skips the batched leg")
     ap.add_argument("--no-net-leg", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2)
@@ -413,7 +427,7 @@ def main():
     copy = copy_ceiling()
     log(f"copy: {copy}")
     dwL = tuple(int(v) for v in args.dw_lattice.split(","))
-    dw = dw_bandwidth(psms, dwL, tuple(max(2, v // 4) for v in dwL), w["kappa"])
+    dw = dw_bandwidth(psms, dwL, dw_blocks(dwL, args.dw_blocks), w["kappa"])
     log(f"D_w: {dw}")
 
     # roofline of the dominant kernel family (by time) among those with a bytes model
@@ -452,13 +466,14 @@ def main():
         "batched": batched,
         "network": net,
         "dw_lattice": dw["lattice"],
+        "dw_blocks": dw["blocks"],
         "dw_tuning": dw["tuning"],
         "dw_gbs": {k: round(v["gbs"], 1) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
         "dw_us_per_launch": {k: round(v["us_per_launch"], 2) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
         "dw_frac_of_hbm_peak": {k: round(v["gbs"] / HBM_PEAK_GBS, 4) for k, v in dw.items()
                                 if isinstance(v, dict) and "gbs" in v},
         "dw_traffic_bytes_per_launch": {"f64": traffic_for(f"dslash_f64_v{dw['tuning']['dslash_variant_f64']}",
-                                                          dw["lattice"], "dw")},
+                                                          f"{dw['lattice']}/{dw['blocks']}", "dw")},
         "copy_ceiling": copy,
         "solver": {"fast": stats[-1], "plain": stp[-1]},
         "tuning": tune,
