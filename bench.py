@@ -76,15 +76,16 @@ FAMILIES = ("dslash", "dslash_part", "block_mr", "block_solve", "blas", "net")
 # holds only for the kernel source it was taken on: `sha256` is that of the file
 # holding the kernel, and a changed file turns the figure into null.
 TRAFFIC = {
-    # even-odd FP32 block kernel, 8 blocks x 16 right-hand sides, Schwarz sweeps
-    ("block_mr", "c2", "mixed"): {"bytes_per_launch": 24626704, "source": "kernels_block.hip",
-                                  "sha256": "873d28cc390218d9b7cb9ef677c15132cf5c8a6a51d626747f43e2f9c1c066f6"},
-    # full-lattice FP64 stencil at 32^4 with 8^4 blocks, four lanes per site (variant 6) and
-    # split form (variant 1); keyed by lattice/blocks
-    ("dslash_f64_v6", "32x32x32x32/8x8x8x8", "dw"): {"bytes_per_launch": 1748566215, "source": "kernels_dirac.hip",
-                                             "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
-    ("dslash_f64_v1", "32x32x32x32/8x8x8x8", "dw"): {"bytes_per_launch": 1703598494, "source": "kernels_dirac.hip",
-                                             "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
+    # even-odd FP32 block kernel (links staged in LDS), 8 blocks x 16 right-hand sides,
+    # Schwarz sweeps
+    ("block_mr", "c2", "mixed"): {"bytes_per_launch": 23955677, "source": "kernels_block.hip",
+                                  "sha256": "9d344fe3448ac5204775d759bed5bc967a8b8a020ee36ba7162e1f67f66d687b"},
+    # full-lattice FP64 stencil at 32^4 on 4x4x8x16 blocks, four lanes per site (variant 6)
+    # and split form (variant 1); keyed by lattice/block shape
+    ("dslash_f64_v6", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1343731749, "source": "kernels_dirac.hip",
+                                              "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
+    ("dslash_f64_v1", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1322391961, "source": "kernels_dirac.hip",
+                                              "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
 }
 
 
