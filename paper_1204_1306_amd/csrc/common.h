@@ -278,8 +278,9 @@ template <class T> __device__ __forceinline__ void su3_dag_mul(const SU3<T>& u, 
   for (int a = 0; a < 3; ++a) o[a] = cjmul(u.m[0][a], v[0]) + cjmul(u.m[1][a], v[1]) + cjmul(u.m[2][a], v[2]);
 }
 
-// acc += c * U(x,mu) (1 - gamma_mu) psi   (psi = psi(x+mu), c includes the boundary sign)
-template <class T> __device__ __forceinline__ void hop_fwd(int mu, const SU3<T>& U, const Spinor<T>& p, T c, Spinor<T>& acc) {
+// acc += c * U(x,mu) (1 - gamma_mu) psi   (psi = psi(x+mu), c includes the boundary sign).
+// P is Spinor<T> or any view whose p.v[spin][colour] yields cx<T>.
+template <class T, class P> __device__ __forceinline__ void hop_fwd(int mu, const SU3<T>& U, const P& p, T c, Spinor<T>& acc) {
   cx<T> h0[3], h1[3], u0[3], u1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -308,7 +309,7 @@ template <class T> __device__ __forceinline__ void hop_fwd(int mu, const SU3<T>&
 }
 
 // acc += c * U(x-mu,mu)^+ (1 + gamma_mu) psi   (psi = psi(x-mu))
-template <class T> __device__ __forceinline__ void hop_bwd(int mu, const SU3<T>& U, const Spinor<T>& p, T c, Spinor<T>& acc) {
+template <class T, class P> __device__ __forceinline__ void hop_bwd(int mu, const SU3<T>& U, const P& p, T c, Spinor<T>& acc) {
   cx<T> h0[3], h1[3], w0[3], w1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {

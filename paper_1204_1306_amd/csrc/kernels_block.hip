@@ -25,6 +25,7 @@ struct BlockArgs {
               // 2: the same with 12-real links read from L2 instead of LDS
   const void* rho_in;  // non-null: read the initial rho from here (same shape) instead of rho
   int x_assign;        // 1: x = delta instead of x += delta (x need not be initialised)
+  int eo_lanes;        // even-odd form on 256-site blocks: lanes per site (2, 4, 8; 0 = by grid)
   int* iters;
 };
 
@@ -941,16 +942,316 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
 }
 
+// Even-odd block solver for 256-site blocks with NL lanes per site (NL = 4 or 8:
+// 512 or 1024 threads, two or four waves per SIMD). The algorithm is that of
+// k_block_mr_eo; here each hop phase is spread NL ways. Lane (j, m) takes the hops
+// of site j in direction m & 1 (0 forward, 1 backward) along the dimension pair
+// {2(m >> 1), 2(m >> 1) + 1} (NL = 4) or the dimension m >> 1 (NL = 8) and writes
+// its partial sum to LDS plane m; the NL planes are summed afterwards. The solver
+// state is spread as well: lane (j, m) holds the spinor components k = m (mod NL)
+// of the even and odd site j, so inner products and updates use every lane.
+// Read-only view of site q of a [12][N] LDS field as a spinor (p.v[spin][colour]), so
+// a hop reads each component where it uses it instead of copying the spinor first.
+template <class T, int N> struct LdsSpinor {
+  struct Row {
+    const cx<T> (*f)[N];
+    int q, i;
+    __device__ __forceinline__ cx<T> operator[](int c) const { return f[3 * i + c][q]; }
+  };
+  struct Rows {
+    const cx<T> (*f)[N];
+    int q;
+    __device__ __forceinline__ Row operator[](int i) const { return {f, q, i}; }
+  };
+  Rows v;
+};
+
+template <class S, class LK, class T, bool STAGE, int NL>
+__global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
+  constexpr int H = 128;                  // sites per parity
+  constexpr int NT = NL * H;              // threads
+  constexpr int NMU = NL == 4 ? 2 : 1;    // dimensions per lane and hop phase
+  constexpr int KC = (12 + NL - 1) / NL;  // state components per lane
+  static_assert(NL == 4 || NL == 8, "4 or 8 lanes per site");
+  constexpr bool LL = LdsLinks<LK>::on && STAGE;
+  __shared__ cx<T> fv[12][H];      // the field a hop phase reads
+  __shared__ cx<T> pt[NL][12][H];  // partial sums of the lane groups
+  __shared__ float4 lk_lds[LL ? 12 : 1][LL ? 2 * H : 1];
+  __shared__ double sm[3][16];
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int blk = a.colour * g.nblk_c + blockIdx.x;
+  const int prop = blockIdx.z;
+  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  using unit = typename S::unit;
+  unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
+  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
+  unit* x = reinterpret_cast<unit*>(a.x) + roff;
+  unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const T kp = T(a.kappa), mk = T(-a.kappa);
+  const int t = threadIdx.x;
+  const int j = t & (H - 1);
+  const int m = __builtin_amdgcn_readfirstlane(t >> 7);
+  const int h = m & 1;
+  const int s = blk * H + j;
+
+  // in-block neighbours of this lane's hops: nA for the odd site j, nB for the even
+  // site j (-1 when the hop leaves the block); gA, gB their indices in the field
+  int nA[4], nB[4], gA[4], gB[4];
+  {
+    SiteInfo so, se;
+    site_info(g, 1, s, so);
+    site_info(g, 0, s, se);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      Nbr n = neighbour(g, so, mu, h == 0 ? +1 : -1);
+      nA[mu] = n.cross ? -1 : n.s - blk * H;
+      gA[mu] = n.s;
+      Nbr q = neighbour(g, se, mu, h == 0 ? +1 : -1);
+      nB[mu] = q.cross ? -1 : q.s - blk * H;
+      gB[mu] = q.s;
+    }
+  }
+  if constexpr (LL) {  // forward links of both parities, [mu * 3 + k][parity * H + site]
+    const float4* lf = reinterpret_cast<const float4*>(lk);
+    for (int i = t; i < 12 * 2 * H; i += NT) {
+      const int k = i / (2 * H), xq = i - k * 2 * H, gp = xq / H;
+      lk_lds[k][xq] = lf[(size_t(gp * 4 + k / 3) * 3 + k % 3) * Vh + size_t(blk) * H + (xq - gp * H)];
+    }
+  }
+  auto link = [&](int mu, int gp, int q, int gs, SU3<T>& U) {
+    if constexpr (LL) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float4 v = lk_lds[mu * 3 + k][gp * H + q];
+        U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
+        U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
+      }
+      cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
+      cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
+      cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
+      U.m[2][0] = {c0.re, -c0.im};
+      U.m[2][1] = {c1.re, -c1.im};
+      U.m[2][2] = {c2.re, -c2.im};
+    } else {
+      LK::load(lk + size_t(gp * 4 + mu) * LK::NC * Vh, Vh, gs, U);
+    }
+  };
+  // this lane's hops of site j of parity gp (neighbours, of the other parity, read
+  // from fv), scaled by c, into plane m
+  auto phase = [&](int gp, const int (&nn)[4], const int (&gn)[4], T c) {
+    Spinor<T> acc;
+    zero(acc);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      if ((mu >> (NMU - 1)) != (m >> 1)) continue;  // wave-uniform
+      const int q = nn[mu];
+      if (q >= 0) {
+        SU3<T> U;
+        if (h == 0) link(mu, gp, j, s, U);    // U(x, mu)
+        else link(mu, 1 - gp, q, gn[mu], U);  // U(x - mu, mu), stored at the neighbour
+        const LdsSpinor<T, H> nb{{fv, q}};
+        if (h == 0) hop_fwd(mu, U, nb, c, acc);
+        else hop_bwd(mu, U, nb, c, acc);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pt[m][k][j] = acc.v[k / 3][k % 3];
+  };
+  // sum over all planes of component k of site j
+  auto psum = [&](int k) {
+    cx<T> v = pt[0][k][j];
+#pragma unroll
+    for (int q = 1; q < NL; ++q) v = v + pt[q][k][j];
+    return v;
+  };
+  // component k of this lane's state slot i, or -1
+  auto comp = [&](int i) { return m + NL * i < 12 ? m + NL * i : -1; };
+
+  // rho of both parities with the face update, spread like the hops: plane m gets
+  // the hops leaving the block from parity fp = (m >> 1) & 1 in direction h (for
+  // NL = 8 only the dimension pair m >> 2) and, in one plane per parity, rho itself
+  {
+    const int fp = (m >> 1) & 1;
+    Spinor<T> acc;
+    zero(acc);
+    if (h == 0 && m < 4) S::load(rin + size_t(fp) * S::NC * Vh, Vh, s, acc);
+    if (a.face) {
+      SiteInfo si;
+      site_info(g, fp, s, si);
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        if (NL == 8 && (mu >> 1) != (m >> 2)) continue;  // wave-uniform
+        Nbr n = neighbour(g, si, mu, h == 0 ? +1 : -1);
+        if (n.cross) {
+          SU3<T> U;
+          Spinor<T> nb;
+          S::load(dl + size_t(1 - fp) * S::NC * Vh, Vh, n.s, nb);
+          if (h == 0) {
+            LK::load(lk + size_t(fp * 4 + mu) * LK::NC * Vh, Vh, s, U);
+            hop_fwd(mu, U, nb, kp * T(n.sign), acc);
+          } else {
+            LK::load(lk + size_t((1 - fp) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+            hop_bwd(mu, U, nb, kp * T(n.sign), acc);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pt[m][k][j] = acc.v[k / 3][k % 3];
+  }
+  __syncthreads();
+  cx<T> r[KC], ro[KC], d[KC], ap[KC];
+  double b2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < KC; ++i) {
+    const int k = comp(i);
+    r[i] = ro[i] = d[i] = ap[i] = {T(0), T(0)};
+    if (k >= 0) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        if (((q >> 1) & 1) == 0) r[i] = r[i] + pt[q][k][j];
+        else ro[i] = ro[i] + pt[q][k][j];
+      }
+      b2 += double(r[i].re) * r[i].re + double(r[i].im) * r[i].im + double(ro[i].re) * ro[i].re +
+            double(ro[i].im) * ro[i].im;
+      fv[k][j] = ro[i];
+    }
+  }
+  b2 = wg_sum(b2, sm[0]);  // its barriers also publish fv and free pt
+  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
+
+  // even right-hand side rho_e + k H_eo rho_o
+  phase(0, nB, gB, kp);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < KC; ++i)
+    if (comp(i) >= 0) r[i] = r[i] + psum(comp(i));
+
+  int it = 0;
+  if (b2 > 0.0) {
+    for (; it < a.niter; ++it) {
+      // ap = (1 - k^2 H_eo H_oe) r on the even sites
+#pragma unroll
+      for (int i = 0; i < KC; ++i)
+        if (comp(i) >= 0) fv[comp(i)][j] = r[i];
+      __syncthreads();
+      phase(1, nA, gA, kp);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < KC; ++i)
+        if (comp(i) >= 0) fv[comp(i)][j] = psum(comp(i));
+      __syncthreads();
+      phase(0, nB, gB, mk);
+      __syncthreads();
+      double prr = 0.0, pri = 0.0, pp = 0.0;
+#pragma unroll
+      for (int i = 0; i < KC; ++i) {
+        if (comp(i) >= 0) {
+          ap[i] = r[i] + psum(comp(i));
+          const double ar = ap[i].re, ai = ap[i].im, br = r[i].re, bi = r[i].im;
+          prr += ar * br + ai * bi;
+          pri += ar * bi - ai * br;
+          pp += ar * ar + ai * ai;
+        }
+      }
+      wg_sum3(prr, pri, pp, sm);
+      if (!(pp > 0.0)) break;
+      const cx<T> alpha = {T(prr / pp), T(pri / pp)};
+      double rr = 0.0;
+#pragma unroll
+      for (int i = 0; i < KC; ++i) {
+        if (comp(i) >= 0) {
+          d[i] = d[i] + cmul(alpha, r[i]);
+          r[i] = r[i] - cmul(alpha, ap[i]);
+          rr += double(r[i].re) * r[i].re + double(r[i].im) * r[i].im;
+        }
+      }
+      if (stop2 > 0) {
+        rr = wg_sum(rr, sm[0]);
+        if (rr <= stop2) {
+          ++it;
+          break;
+        }
+      }
+    }
+  }
+  // x_o = rho_o + k H_oe x_e; the odd residual is then zero
+#pragma unroll
+  for (int i = 0; i < KC; ++i)
+    if (comp(i) >= 0) fv[comp(i)][j] = d[i];
+  __syncthreads();
+  phase(1, nA, gA, kp);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < KC; ++i)
+    if (comp(i) >= 0) ro[i] = ro[i] + psum(comp(i));
+  __syncthreads();
+  // gather the even residual (plane 0), even delta (plane 1) and odd delta (plane 2)
+  // per site, then store whole spinors: lane group m = 0 rho_e, 1 delta_e and x_e,
+  // 2 rho_o (zero), 3 delta_o and x_o
+#pragma unroll
+  for (int i = 0; i < KC; ++i) {
+    if (comp(i) >= 0) {
+      pt[0][comp(i)][j] = r[i];
+      pt[1][comp(i)][j] = d[i];
+      pt[2][comp(i)][j] = ro[i];
+    }
+  }
+  __syncthreads();
+  if (m < 4) {
+    const int p = m >> 1;
+    Spinor<T> v;
+    if (m == 2) zero(v);
+    else {
+      const int plane = m == 0 ? 0 : (m == 1 ? 1 : 2);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v.v[k / 3][k % 3] = pt[plane][k][j];
+    }
+    if (h == 0) {
+      S::store(rho + size_t(p) * S::NC * Vh, Vh, s, v);
+    } else {
+      S::store(dl + size_t(p) * S::NC * Vh, Vh, s, v);
+      Spinor<T> xv;
+      if (a.x_assign) zero(xv);
+      else S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + v.v[q][c];
+      S::store(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+    }
+  }
+  if (a.iters && t == 0) atomicMax(a.iters, it);
+}
+
 template <class S, class LK, class T>
 static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
   if (2 * a.g.Vbh == 256) {
     const dim3 grid(a.g.nblk_c, a.nrhs, nprop);
-    if (a.eo == 2 && LdsLinks<LK>::on) {
-      launch_timed((k_block_mr_eo<S, LK, T, false>), grid, dim3(256), 0, st, a);
-      return;
-    }
     if (a.eo) {
-      launch_timed((k_block_mr_eo<S, LK, T>), grid, dim3(256), 0, st, a);
+      // links staged in LDS (eo 1) or read from L2 (eo 2); 2, 4 or 8 lanes per site,
+      // by default 4 when an FP32 grid leaves compute units idle (the iteration's latency
+      // then sets the time, and four lanes halve the hops per lane), else 2 (fewer
+      // barriers and LDS passes when the CUs are full; FP64 with 4 lanes spills)
+      constexpr bool LL = LdsLinks<LK>::on;
+      const bool stage = a.eo != 2;
+      const int nl = a.eo_lanes > 0 ? a.eo_lanes : (sizeof(T) == 4 && grid.x * grid.y * grid.z < 256 ? 4 : 2);
+      if (nl == 4) {
+        if (LL && stage) launch_timed((k_block_mr_eo_n<S, LK, T, true, 4>), grid, dim3(512), 0, st, a);
+        else launch_timed((k_block_mr_eo_n<S, LK, T, false, 4>), grid, dim3(512), 0, st, a);
+        return;
+      }
+      if constexpr (sizeof(T) == 4) {
+        if (nl == 8) {
+          if (LL && stage) launch_timed((k_block_mr_eo_n<S, LK, T, true, 8>), grid, dim3(1024), 0, st, a);
+          else launch_timed((k_block_mr_eo_n<S, LK, T, false, 8>), grid, dim3(1024), 0, st, a);
+          return;
+        }
+      }
+      if (LL && !stage) launch_timed((k_block_mr_eo<S, LK, T, false>), grid, dim3(256), 0, st, a);
+      else launch_timed((k_block_mr_eo<S, LK, T>), grid, dim3(256), 0, st, a);
       return;
     }
     if constexpr (LdsLinks<LK>::on) {
@@ -995,6 +1296,7 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
   a.eo = bp.eo;
   a.rho_in = bp.rho_in;
   a.x_assign = bp.x_assign;
+  a.eo_lanes = bp.eo_lanes;
   a.iters = iters_out;
   if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);
   else if (rho.prec == P_F32 && linkfmt == LK_F32C12) block_go<StF32, LkF32C12, float>(st, a, rho.nprop);

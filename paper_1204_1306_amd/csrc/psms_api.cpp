@@ -77,6 +77,7 @@ struct psms_ctx {
   int block_solver = 0;        // block inverses to tolerance: 0 minimal residual, 1 flexible GCR
   int block_lanes = 0;         // LDS-resident block solver: lanes per site (1, 2; 0 = by grid size)
   int block_eo = 2;            // LDS-resident block solver: 1 even-odd, 0 plain, 2 by launch shape
+  int block_eo_lanes = 0;      // even-odd form on 256-site blocks: lanes per site (2, 4, 8; 0 = default)
   // pinned host slots for the lagged convergence check of the GCR iteration
   double* pinned[2] = {nullptr, nullptr};
   size_t pinned_n = 0;
@@ -505,6 +506,7 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
       BlockMRParams bp{col, iters, 0.0, c->geom.kappa};
       bp.face = (cy > 0 || col > 0) ? 1 : 0;
       bp.lanes = c->block_lanes;
+      bp.eo_lanes = c->block_eo_lanes;
       bp.eo = eo_form;
       if (direct && cy == 0) {
         bp.rho_in = r.p;
@@ -914,6 +916,7 @@ double solve_colour_mixed(psms_ctx* c, const int* slots, int col, const FieldBat
       ProfScope ps(c, FAM_BLOCK_SOLVE, block_bytes(c, L32, rho));
       BlockMRParams bp{col, maxit - total, 1e-5, c->geom.kappa};
       bp.lanes = c->block_lanes;
+      bp.eo_lanes = c->block_eo_lanes;
       bp.eo = c->block_eo != 0 ? 1 : 0;
       launch_block_mr(c->st, c->g, L32.p, L32.fmt, rho, e, dl, pb, bp, it);
     }
@@ -994,6 +997,7 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
     ProfScope ps(c, FAM_BLOCK_SOLVE, block_bytes(c, L, rho));
     BlockMRParams bp{col, maxit, tol, c->geom.kappa};
     bp.lanes = c->block_lanes;
+    bp.eo_lanes = c->block_eo_lanes;
     bp.eo = c->block_eo != 0 ? 1 : 0;  // to a tolerance the even-odd form always pays
     launch_block_mr(c->st, c->g, L.p, L.fmt, rho, x, dl, pb, bp, it);
   }
@@ -1915,10 +1919,12 @@ static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "block_solver")) return &c->block_solver;
   if (!std::strcmp(key, "block_lanes")) return &c->block_lanes;
   if (!std::strcmp(key, "block_eo")) return &c->block_eo;
+  if (!std::strcmp(key, "block_eo_lanes")) return &c->block_eo_lanes;
   return nullptr;
 }
 static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
-                                    "xcd_map", "net_mfma", "block_solver", "block_lanes", "block_eo"};
+                                    "xcd_map", "net_mfma", "block_solver", "block_lanes", "block_eo",
+                                    "block_eo_lanes"};
 
 psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   API_BEGIN(c)
@@ -1930,6 +1936,8 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
     REQUIRE(value >= 0 && value <= 3, "block_eo must be 0 (plain), 1 (even-odd), 2 (by launch shape) or 3 (even-odd, links from L2)");
   else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
+  else if (!std::strcmp(key, "block_eo_lanes"))
+    REQUIRE(value == 0 || value == 2 || value == 4 || value == 8, "even-odd lanes per site must be 0 (default), 2, 4 or 8");
   else if (!std::strcmp(key, "block_lanes"))
     REQUIRE(value >= 0 && value <= 2, "lanes per site must be 0 (by grid size), 1 or 2");
   else REQUIRE(value == 1 || value == 2 || value == 4, "right-hand sides per thread must be 1, 2 or 4");

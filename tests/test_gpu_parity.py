@@ -158,19 +158,21 @@ def test_dhat_even_odd(psms):
     assert rel(ctx.apply_dhat_ee(0, psi), ref) < 1e-13
 
 
-@pytest.mark.parametrize("eo", [0, 1, 3])
+@pytest.mark.parametrize("eo,lanes", [(0, 0), (1, 2), (3, 2), (1, 4), (3, 4), (1, 8), (3, 8)])
 @pytest.mark.parametrize("prec", ["f64", "mixed_f32", "mixed_bf16"])
-def test_solve_parity(psms, prec, eo):
-    """Full solves with Schwarz blocks solved by plain or even-odd minimal residual: FP64
-    true residual <= 1e-10 through the oracle's operator."""
+def test_solve_parity(psms, prec, eo, lanes):
+    """Full solves with Schwarz blocks solved by plain or even-odd minimal residual (links
+    staged in LDS or read from L2, 2, 4 or 8 lanes per site): FP64 true residual <= 1e-10
+    through the oracle's operator."""
     L, b = (8, 8, 8, 8), (4, 4, 4, 4)
     kappa = 0.15
-    say("case solve", prec, "eo", eo)
+    say("case solve", prec, "eo", eo, "lanes", lanes)
     U = synth.gauge_field(L, 0.6, 2001)
     bvec = synth.gaussian_noise(L, 2, 41)
     ctx = make_ctx(psms, L, b, kappa)
     ctx.gauge_load(0, U)
     ctx.set_tuning("block_eo", eo)
+    ctx.set_tuning("block_eo_lanes", lanes)
     kw = dict(tol=1e-10)
     if prec != "f64":
         kw.update(prec=psms.MIXED, inner_storage=psms.SPINOR_BF16 if prec == "mixed_bf16" else psms.SPINOR_F32)
@@ -196,13 +198,15 @@ def test_solve_small_against_lu(psms):
         assert rel(x, op.solve(bvec)) < 1e-10
 
 
-@pytest.mark.parametrize("eo", [0, 1])
+@pytest.mark.parametrize("eo,lanes", [(0, 0), (1, 2), (1, 4), (1, 8)])
 @pytest.mark.parametrize("colour", [0, 1])
-def test_block_solve_parity(psms, colour, eo):
+def test_block_solve_parity(psms, colour, eo, lanes):
     """D_bb^-1 / D_ww^-1 (Dirichlet blocks of 256 sites, 16 blocks): plain and even-odd
-    preconditioned minimal residual to 1e-12 against the oracle's per-block dense LU."""
+    preconditioned minimal residual (2, 4 or 8 lanes per site) to 1e-12 against the
+    oracle's per-block dense LU."""
     L, b = (8, 8, 8, 8), (4, 4, 4, 4)
     kappa = 0.15
+    say("case block", colour, "eo", eo, "lanes", lanes)
     U = synth.gauge_field(L, 0.6, 51)
     g = schur.Geometry(L, b)
     op = schur.Operator(g, U, kappa)
@@ -210,6 +214,7 @@ def test_block_solve_parity(psms, colour, eo):
     ctx = make_ctx(psms, L, b, kappa)
     ctx.gauge_load(0, U)
     ctx.set_tuning("block_eo", eo)
+    ctx.set_tuning("block_eo_lanes", lanes)
     x, st = ctx.solve_block(0, colour, bvec, psms.default_params(tol=1e-12, max_iter=5000))
     say(" block stats", st)
     mask = g.black if colour == 0 else g.white
