@@ -221,8 +221,9 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
  * LDS; 3 the same with links read from L2; 2, the default, even-odd throughout, links
  * staged when the launch has fewer than two workgroups per compute unit, and Schwarz
  * sweeps with block_iters/2 iterations rounded up) and "block_eo_lanes" (even-odd block
- * solver on 256-site blocks: 2, 4 or 8 lanes per site, 8 in FP32 only; 0, the default,
- * 4 when an FP32 launch has fewer workgroups than the GPU has compute units, else 2).
+ * solver on 256-site blocks in FP32 or BF16 storage: 2 or 4 lanes per site; 0, the
+ * default, 4 when the launch has fewer workgroups than the GPU has compute units, else
+ * 2; FP64 block solves always use 2).
  * Unknown keys or values give
  * PSMS_EINVAL. Results do not depend on the tuning beyond rounding; only speed does. */
 psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);

@@ -114,7 +114,7 @@ struct BlockMRParams {
   int eo = 0;     // even-odd preconditioned minimal residual
   const void* rho_in = nullptr;  // non-null: initial rho read from here (rho is still written)
   int x_assign = 0;              // 1: x = delta instead of x += delta
-  int eo_lanes = 0;              // even-odd form on 256-site blocks: lanes per site (2, 4, 8; 0 = by grid)
+  int eo_lanes = 0;              // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
 };
 // For every block of the colour: (optionally) the face update of rho_b from the
 // other colour's delta, then delta = MR approximation of D_b^-1 rho_b, x += delta,

@@ -25,7 +25,7 @@ struct BlockArgs {
               // 2: the same with 12-real links read from L2 instead of LDS
   const void* rho_in;  // non-null: read the initial rho from here (same shape) instead of rho
   int x_assign;        // 1: x = delta instead of x += delta (x need not be initialised)
-  int eo_lanes;        // even-odd form on 256-site blocks: lanes per site (2, 4, 8; 0 = by grid)
+  int eo_lanes;        // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int* iters;
 };
 
@@ -942,14 +942,6 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
 }
 
-// Even-odd block solver for 256-site blocks with NL lanes per site (NL = 4 or 8:
-// 512 or 1024 threads, two or four waves per SIMD). The algorithm is that of
-// k_block_mr_eo; here each hop phase is spread NL ways. Lane (j, m) takes the hops
-// of site j in direction m & 1 (0 forward, 1 backward) along the dimension pair
-// {2(m >> 1), 2(m >> 1) + 1} (NL = 4) or the dimension m >> 1 (NL = 8) and writes
-// its partial sum to LDS plane m; the NL planes are summed afterwards. The solver
-// state is spread as well: lane (j, m) holds the spinor components k = m (mod NL)
-// of the even and odd site j, so inner products and updates use every lane.
 // Read-only view of site q of a [12][N] LDS field as a spinor (p.v[spin][colour]), so
 // a hop reads each component where it uses it instead of copying the spinor first.
 template <class T, int N> struct LdsSpinor {
@@ -966,17 +958,27 @@ template <class T, int N> struct LdsSpinor {
   Rows v;
 };
 
-template <class S, class LK, class T, bool STAGE, int NL>
-__global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
-  constexpr int H = 128;                  // sites per parity
-  constexpr int NT = NL * H;              // threads
-  constexpr int NMU = NL == 4 ? 2 : 1;    // dimensions per lane and hop phase
-  constexpr int KC = (12 + NL - 1) / NL;  // state components per lane
-  static_assert(NL == 4 || NL == 8, "4 or 8 lanes per site");
-  constexpr bool LL = LdsLinks<LK>::on && STAGE;
+// Even-odd block solver for 256-site blocks with four lanes per site (512 threads,
+// two waves per SIMD), for FP32 arithmetic. The algorithm is that of k_block_mr_eo;
+// here each hop phase is spread four ways. Lane (j, m) takes the hops of site j in
+// direction m & 1 (0 forward, 1 backward) along the dimension pair
+// {2(m >> 1), 2(m >> 1) + 1} and writes its partial sum to LDS plane m; the four
+// planes are summed afterwards. The solver state is spread as well: lane (j, m)
+// holds the spinor components k = m, m + 4, m + 8 of the even and odd site j, so
+// inner products and updates use every lane. With staged links the block's links
+// are staged whole (row 2 rebuilt once) and pre-multiplied by kappa, so a hop
+// neither rebuilds nor scales them.
+template <class S, class LK, class T, bool STAGE>
+__global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
+  constexpr int NL = 4;          // lanes per site
+  constexpr int H = 128;         // sites per parity
+  constexpr int NT = NL * H;     // threads
+  constexpr int KC = 12 / NL;    // state components per lane
+  static_assert(sizeof(T) == 4, "FP32 arithmetic (FP64 state does not fit the registers)");
+  constexpr bool LL = LdsLinks<LK>::on && STAGE;  // whole kappa-scaled links in LDS
   __shared__ cx<T> fv[12][H];      // the field a hop phase reads
   __shared__ cx<T> pt[NL][12][H];  // partial sums of the lane groups
-  __shared__ float4 lk_lds[LL ? 12 : 1][LL ? 2 * H : 1];
+  __shared__ float4 lk_lds[LL ? 20 : 1][LL ? 2 * H : 1];  // 5 float4 per link
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
@@ -989,75 +991,84 @@ __global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
-  const T kp = T(a.kappa), mk = T(-a.kappa);
+  const T kp = T(a.kappa);
+  const T ch = LL ? T(1) : kp;  // hop coefficient (kappa is in the staged links)
   const int t = threadIdx.x;
   const int j = t & (H - 1);
   const int m = __builtin_amdgcn_readfirstlane(t >> 7);
   const int h = m & 1;
+  const int fp = m >> 1;  // parity of this lane's face update and stores
   const int s = blk * H + j;
+
+  // global reads that depend on nothing else go first: this lane's rho (one lane per
+  // site and parity), x (the lane that updates it), the links to stage
+  Spinor<T> acc, xv;
+  zero(acc);
+  zero(xv);
+  if (h == 0) S::load(rin + size_t(fp) * S::NC * Vh, Vh, s, acc);
+  else if (!a.x_assign) S::load(x + size_t(fp) * S::NC * Vh, Vh, s, xv);
+  if constexpr (LL) {  // link (parity gp, site q, mu) -> planes mu * 5 + e, kappa U
+    for (int i = t; i < 4 * 2 * H; i += NT) {
+      const int mu = i / (2 * H), xq = i - mu * 2 * H, gp = xq / H;
+      SU3<T> U;
+      LK::load(lk + size_t(gp * 4 + mu) * LK::NC * Vh, Vh, blk * H + (xq - gp * H), U);
+      cx<T> e[10];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) e[k] = scale(kp, U.m[k / 3][k % 3]);
+      e[9] = {T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        lk_lds[mu * 5 + k][xq] = make_float4(float(e[2 * k].re), float(e[2 * k].im), float(e[2 * k + 1].re), float(e[2 * k + 1].im));
+    }
+  }
 
   // in-block neighbours of this lane's hops: nA for the odd site j, nB for the even
   // site j (-1 when the hop leaves the block); gA, gB their indices in the field
   int nA[4], nB[4], gA[4], gB[4];
-  {
-    SiteInfo so, se;
-    site_info(g, 1, s, so);
-    site_info(g, 0, s, se);
+  SiteInfo so, se;
+  site_info(g, 1, s, so);
+  site_info(g, 0, s, se);
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      Nbr n = neighbour(g, so, mu, h == 0 ? +1 : -1);
-      nA[mu] = n.cross ? -1 : n.s - blk * H;
-      gA[mu] = n.s;
-      Nbr q = neighbour(g, se, mu, h == 0 ? +1 : -1);
-      nB[mu] = q.cross ? -1 : q.s - blk * H;
-      gB[mu] = q.s;
-    }
-  }
-  if constexpr (LL) {  // forward links of both parities, [mu * 3 + k][parity * H + site]
-    const float4* lf = reinterpret_cast<const float4*>(lk);
-    for (int i = t; i < 12 * 2 * H; i += NT) {
-      const int k = i / (2 * H), xq = i - k * 2 * H, gp = xq / H;
-      lk_lds[k][xq] = lf[(size_t(gp * 4 + k / 3) * 3 + k % 3) * Vh + size_t(blk) * H + (xq - gp * H)];
-    }
+  for (int mu = 0; mu < 4; ++mu) {
+    Nbr n = neighbour(g, so, mu, h == 0 ? +1 : -1);
+    nA[mu] = n.cross ? -1 : n.s - blk * H;
+    gA[mu] = n.s;
+    Nbr q = neighbour(g, se, mu, h == 0 ? +1 : -1);
+    nB[mu] = q.cross ? -1 : q.s - blk * H;
+    gB[mu] = q.s;
   }
   auto link = [&](int mu, int gp, int q, int gs, SU3<T>& U) {
     if constexpr (LL) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        float4 v = lk_lds[mu * 3 + k][gp * H + q];
+      for (int k = 0; k < 5; ++k) {
+        float4 v = lk_lds[mu * 5 + k][gp * H + q];
         U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
-        U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
+        if (k < 4) U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
       }
-      cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
-      cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
-      cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
-      U.m[2][0] = {c0.re, -c0.im};
-      U.m[2][1] = {c1.re, -c1.im};
-      U.m[2][2] = {c2.re, -c2.im};
     } else {
       LK::load(lk + size_t(gp * 4 + mu) * LK::NC * Vh, Vh, gs, U);
     }
   };
-  // this lane's hops of site j of parity gp (neighbours, of the other parity, read
-  // from fv), scaled by c, into plane m
-  auto phase = [&](int gp, const int (&nn)[4], const int (&gn)[4], T c) {
-    Spinor<T> acc;
-    zero(acc);
+  // kappa times this lane's hops of site j of parity gp (neighbours, of the other
+  // parity, read from fv), into plane m
+  auto phase = [&](int gp, const int (&nn)[4], const int (&gn)[4]) {
+    Spinor<T> hs;
+    zero(hs);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-      if ((mu >> (NMU - 1)) != (m >> 1)) continue;  // wave-uniform
+      if ((mu >> 1) != (m >> 1)) continue;  // wave-uniform
       const int q = nn[mu];
       if (q >= 0) {
         SU3<T> U;
         if (h == 0) link(mu, gp, j, s, U);    // U(x, mu)
         else link(mu, 1 - gp, q, gn[mu], U);  // U(x - mu, mu), stored at the neighbour
         const LdsSpinor<T, H> nb{{fv, q}};
-        if (h == 0) hop_fwd(mu, U, nb, c, acc);
-        else hop_bwd(mu, U, nb, c, acc);
+        if (h == 0) hop_fwd(mu, U, nb, ch, hs);
+        else hop_bwd(mu, U, nb, ch, hs);
       }
     }
 #pragma unroll
-    for (int k = 0; k < 12; ++k) pt[m][k][j] = acc.v[k / 3][k % 3];
+    for (int k = 0; k < 12; ++k) pt[m][k][j] = hs.v[k / 3][k % 3];
   };
   // sum over all planes of component k of site j
   auto psum = [&](int k) {
@@ -1066,68 +1077,59 @@ __global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
     for (int q = 1; q < NL; ++q) v = v + pt[q][k][j];
     return v;
   };
-  // component k of this lane's state slot i, or -1
-  auto comp = [&](int i) { return m + NL * i < 12 ? m + NL * i : -1; };
+  // spinor component held in this lane's state slot i
+  auto comp = [&](int i) { return m + NL * i; };
 
   // rho of both parities with the face update, spread like the hops: plane m gets
-  // the hops leaving the block from parity fp = (m >> 1) & 1 in direction h (for
-  // NL = 8 only the dimension pair m >> 2) and, in one plane per parity, rho itself
-  {
-    const int fp = (m >> 1) & 1;
-    Spinor<T> acc;
-    zero(acc);
-    if (h == 0 && m < 4) S::load(rin + size_t(fp) * S::NC * Vh, Vh, s, acc);
-    if (a.face) {
-      SiteInfo si;
-      site_info(g, fp, s, si);
+  // the hops leaving the block from parity fp in direction h and, in one plane per
+  // parity, rho itself. The reads are issued for every dimension at once (a hop that
+  // stays in the block reads its own site and is weighted zero), so their latencies
+  // overlap.
+  if (a.face) {
+    const SiteInfo& si = fp ? so : se;
+    const unit* dsrc = dl + size_t(1 - fp) * S::NC * Vh;
+    SU3<T> U[4];
+    Spinor<T> nb[4];
+    T cf[4];
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) {
-        if (NL == 8 && (mu >> 1) != (m >> 2)) continue;  // wave-uniform
-        Nbr n = neighbour(g, si, mu, h == 0 ? +1 : -1);
-        if (n.cross) {
-          SU3<T> U;
-          Spinor<T> nb;
-          S::load(dl + size_t(1 - fp) * S::NC * Vh, Vh, n.s, nb);
-          if (h == 0) {
-            LK::load(lk + size_t(fp * 4 + mu) * LK::NC * Vh, Vh, s, U);
-            hop_fwd(mu, U, nb, kp * T(n.sign), acc);
-          } else {
-            LK::load(lk + size_t((1 - fp) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
-            hop_bwd(mu, U, nb, kp * T(n.sign), acc);
-          }
-        }
-      }
+    for (int mu = 0; mu < 4; ++mu) {
+      Nbr n = neighbour(g, si, mu, h == 0 ? +1 : -1);
+      const int ns = n.cross ? n.s : s;
+      cf[mu] = n.cross ? kp * T(n.sign) : T(0);
+      S::load(dsrc, Vh, ns, nb[mu]);
+      if (h == 0) LK::load(lk + size_t(fp * 4 + mu) * LK::NC * Vh, Vh, s, U[mu]);
+      else LK::load(lk + size_t((1 - fp) * 4 + mu) * LK::NC * Vh, Vh, ns, U[mu]);
     }
 #pragma unroll
-    for (int k = 0; k < 12; ++k) pt[m][k][j] = acc.v[k / 3][k % 3];
+    for (int mu = 0; mu < 4; ++mu) {
+      if (h == 0) hop_fwd(mu, U[mu], nb[mu], cf[mu], acc);
+      else hop_bwd(mu, U[mu], nb[mu], cf[mu], acc);
+    }
   }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) pt[m][k][j] = acc.v[k / 3][k % 3];
   __syncthreads();
   cx<T> r[KC], ro[KC], d[KC], ap[KC];
   double b2 = 0.0;
 #pragma unroll
   for (int i = 0; i < KC; ++i) {
     const int k = comp(i);
-    r[i] = ro[i] = d[i] = ap[i] = {T(0), T(0)};
-    if (k >= 0) {
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        if (((q >> 1) & 1) == 0) r[i] = r[i] + pt[q][k][j];
-        else ro[i] = ro[i] + pt[q][k][j];
-      }
-      b2 += double(r[i].re) * r[i].re + double(r[i].im) * r[i].im + double(ro[i].re) * ro[i].re +
-            double(ro[i].im) * ro[i].im;
-      fv[k][j] = ro[i];
-    }
+    d[i] = ap[i] = {T(0), T(0)};
+    r[i] = pt[0][k][j] + pt[1][k][j];  // planes 0, 1: parity 0; 2, 3: parity 1
+    ro[i] = pt[2][k][j] + pt[3][k][j];
+    b2 += double(r[i].re) * r[i].re + double(r[i].im) * r[i].im + double(ro[i].re) * ro[i].re +
+          double(ro[i].im) * ro[i].im;
+    fv[k][j] = ro[i];
   }
   b2 = wg_sum(b2, sm[0]);  // its barriers also publish fv and free pt
   const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
 
   // even right-hand side rho_e + k H_eo rho_o
-  phase(0, nB, gB, kp);
+  phase(0, nB, gB);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < KC; ++i)
-    if (comp(i) >= 0) r[i] = r[i] + psum(comp(i));
+    r[i] = r[i] + psum(comp(i));
 
   int it = 0;
   if (b2 > 0.0) {
@@ -1135,21 +1137,21 @@ __global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
       // ap = (1 - k^2 H_eo H_oe) r on the even sites
 #pragma unroll
       for (int i = 0; i < KC; ++i)
-        if (comp(i) >= 0) fv[comp(i)][j] = r[i];
+        fv[comp(i)][j] = r[i];
       __syncthreads();
-      phase(1, nA, gA, kp);
+      phase(1, nA, gA);
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < KC; ++i)
-        if (comp(i) >= 0) fv[comp(i)][j] = psum(comp(i));
+        fv[comp(i)][j] = psum(comp(i));
       __syncthreads();
-      phase(0, nB, gB, mk);
+      phase(0, nB, gB);
       __syncthreads();
       double prr = 0.0, pri = 0.0, pp = 0.0;
 #pragma unroll
       for (int i = 0; i < KC; ++i) {
-        if (comp(i) >= 0) {
-          ap[i] = r[i] + psum(comp(i));
+        {
+          ap[i] = r[i] - psum(comp(i));
           const double ar = ap[i].re, ai = ap[i].im, br = r[i].re, bi = r[i].im;
           prr += ar * br + ai * bi;
           pri += ar * bi - ai * br;
@@ -1162,11 +1164,9 @@ __global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
       double rr = 0.0;
 #pragma unroll
       for (int i = 0; i < KC; ++i) {
-        if (comp(i) >= 0) {
-          d[i] = d[i] + cmul(alpha, r[i]);
-          r[i] = r[i] - cmul(alpha, ap[i]);
-          rr += double(r[i].re) * r[i].re + double(r[i].im) * r[i].im;
-        }
+        d[i] = d[i] + cmul(alpha, r[i]);
+        r[i] = r[i] - cmul(alpha, ap[i]);
+        rr += double(r[i].re) * r[i].re + double(r[i].im) * r[i].im;
       }
       if (stop2 > 0) {
         rr = wg_sum(rr, sm[0]);
@@ -1180,28 +1180,25 @@ __global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
   // x_o = rho_o + k H_oe x_e; the odd residual is then zero
 #pragma unroll
   for (int i = 0; i < KC; ++i)
-    if (comp(i) >= 0) fv[comp(i)][j] = d[i];
+    fv[comp(i)][j] = d[i];
   __syncthreads();
-  phase(1, nA, gA, kp);
+  phase(1, nA, gA);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < KC; ++i)
-    if (comp(i) >= 0) ro[i] = ro[i] + psum(comp(i));
+    ro[i] = ro[i] + psum(comp(i));
   __syncthreads();
   // gather the even residual (plane 0), even delta (plane 1) and odd delta (plane 2)
   // per site, then store whole spinors: lane group m = 0 rho_e, 1 delta_e and x_e,
   // 2 rho_o (zero), 3 delta_o and x_o
 #pragma unroll
   for (int i = 0; i < KC; ++i) {
-    if (comp(i) >= 0) {
-      pt[0][comp(i)][j] = r[i];
-      pt[1][comp(i)][j] = d[i];
-      pt[2][comp(i)][j] = ro[i];
-    }
+    pt[0][comp(i)][j] = r[i];
+    pt[1][comp(i)][j] = d[i];
+    pt[2][comp(i)][j] = ro[i];
   }
   __syncthreads();
-  if (m < 4) {
-    const int p = m >> 1;
+  {
     Spinor<T> v;
     if (m == 2) zero(v);
     else {
@@ -1210,17 +1207,14 @@ __global__ void __launch_bounds__(NL * 128) k_block_mr_eo_n(BlockArgs a) {
       for (int k = 0; k < 12; ++k) v.v[k / 3][k % 3] = pt[plane][k][j];
     }
     if (h == 0) {
-      S::store(rho + size_t(p) * S::NC * Vh, Vh, s, v);
+      S::store(rho + size_t(fp) * S::NC * Vh, Vh, s, v);
     } else {
-      S::store(dl + size_t(p) * S::NC * Vh, Vh, s, v);
-      Spinor<T> xv;
-      if (a.x_assign) zero(xv);
-      else S::load(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+      S::store(dl + size_t(fp) * S::NC * Vh, Vh, s, v);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + v.v[q][c];
-      S::store(x + size_t(p) * S::NC * Vh, Vh, s, xv);
+      S::store(x + size_t(fp) * S::NC * Vh, Vh, s, xv);
     }
   }
   if (a.iters && t == 0) atomicMax(a.iters, it);
@@ -1231,22 +1225,17 @@ static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
   if (2 * a.g.Vbh == 256) {
     const dim3 grid(a.g.nblk_c, a.nrhs, nprop);
     if (a.eo) {
-      // links staged in LDS (eo 1) or read from L2 (eo 2); 2, 4 or 8 lanes per site,
-      // by default 4 when an FP32 grid leaves compute units idle (the iteration's latency
-      // then sets the time, and four lanes halve the hops per lane), else 2 (fewer
-      // barriers and LDS passes when the CUs are full; FP64 with 4 lanes spills)
+      // links staged in LDS (eo 1) or read from L2 (eo 2); in FP32 2 or 4 lanes per
+      // site, by default 4 when the grid leaves compute units idle (the iteration's
+      // latency then sets the time, and four lanes halve the hops per lane), else 2
+      // (fewer barriers and LDS passes when the CUs are full). FP64 uses 2.
       constexpr bool LL = LdsLinks<LK>::on;
       const bool stage = a.eo != 2;
-      const int nl = a.eo_lanes > 0 ? a.eo_lanes : (sizeof(T) == 4 && grid.x * grid.y * grid.z < 256 ? 4 : 2);
-      if (nl == 4) {
-        if (LL && stage) launch_timed((k_block_mr_eo_n<S, LK, T, true, 4>), grid, dim3(512), 0, st, a);
-        else launch_timed((k_block_mr_eo_n<S, LK, T, false, 4>), grid, dim3(512), 0, st, a);
-        return;
-      }
       if constexpr (sizeof(T) == 4) {
-        if (nl == 8) {
-          if (LL && stage) launch_timed((k_block_mr_eo_n<S, LK, T, true, 8>), grid, dim3(1024), 0, st, a);
-          else launch_timed((k_block_mr_eo_n<S, LK, T, false, 8>), grid, dim3(1024), 0, st, a);
+        const int nl = a.eo_lanes > 0 ? a.eo_lanes : (grid.x * grid.y * grid.z < 256 ? 4 : 2);
+        if (nl == 4) {
+          if (LL && stage) launch_timed((k_block_mr_eo4<S, LK, T, true>), grid, dim3(512), 0, st, a);
+          else launch_timed((k_block_mr_eo4<S, LK, T, false>), grid, dim3(512), 0, st, a);
           return;
         }
       }

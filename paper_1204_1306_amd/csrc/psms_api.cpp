@@ -77,7 +77,7 @@ struct psms_ctx {
   int block_solver = 0;        // block inverses to tolerance: 0 minimal residual, 1 flexible GCR
   int block_lanes = 0;         // LDS-resident block solver: lanes per site (1, 2; 0 = by grid size)
   int block_eo = 2;            // LDS-resident block solver: 1 even-odd, 0 plain, 2 by launch shape
-  int block_eo_lanes = 0;      // even-odd form on 256-site blocks: lanes per site (2, 4, 8; 0 = default)
+  int block_eo_lanes = 0;      // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   // pinned host slots for the lagged convergence check of the GCR iteration
   double* pinned[2] = {nullptr, nullptr};
   size_t pinned_n = 0;
@@ -1937,7 +1937,7 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
   else if (!std::strcmp(key, "block_eo_lanes"))
-    REQUIRE(value == 0 || value == 2 || value == 4 || value == 8, "even-odd lanes per site must be 0 (default), 2, 4 or 8");
+    REQUIRE(value == 0 || value == 2 || value == 4, "even-odd lanes per site must be 0 (default), 2 or 4");
   else if (!std::strcmp(key, "block_lanes"))
     REQUIRE(value >= 0 && value <= 2, "lanes per site must be 0 (by grid size), 1 or 2");
   else REQUIRE(value == 1 || value == 2 || value == 4, "right-hand sides per thread must be 1, 2 or 4");

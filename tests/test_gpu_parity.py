@@ -158,11 +158,11 @@ def test_dhat_even_odd(psms):
     assert rel(ctx.apply_dhat_ee(0, psi), ref) < 1e-13
 
 
-@pytest.mark.parametrize("eo,lanes", [(0, 0), (1, 2), (3, 2), (1, 4), (3, 4), (1, 8), (3, 8)])
+@pytest.mark.parametrize("eo,lanes", [(0, 0), (1, 2), (3, 2), (1, 4), (3, 4)])
 @pytest.mark.parametrize("prec", ["f64", "mixed_f32", "mixed_bf16"])
 def test_solve_parity(psms, prec, eo, lanes):
     """Full solves with Schwarz blocks solved by plain or even-odd minimal residual (links
-    staged in LDS or read from L2, 2, 4 or 8 lanes per site): FP64 true residual <= 1e-10
+    staged in LDS or read from L2, 2 or 4 lanes per site): FP64 true residual <= 1e-10
     through the oracle's operator."""
     L, b = (8, 8, 8, 8), (4, 4, 4, 4)
     kappa = 0.15
@@ -198,11 +198,11 @@ def test_solve_small_against_lu(psms):
         assert rel(x, op.solve(bvec)) < 1e-10
 
 
-@pytest.mark.parametrize("eo,lanes", [(0, 0), (1, 2), (1, 4), (1, 8)])
+@pytest.mark.parametrize("eo,lanes", [(0, 0), (1, 2), (1, 4)])
 @pytest.mark.parametrize("colour", [0, 1])
 def test_block_solve_parity(psms, colour, eo, lanes):
     """D_bb^-1 / D_ww^-1 (Dirichlet blocks of 256 sites, 16 blocks): plain and even-odd
-    preconditioned minimal residual (2, 4 or 8 lanes per site) to 1e-12 against the
+    preconditioned minimal residual (2 or 4 lanes per site) to 1e-12 against the
     oracle's per-block dense LU."""
     L, b = (8, 8, 8, 8), (4, 4, 4, 4)
     kappa = 0.15
