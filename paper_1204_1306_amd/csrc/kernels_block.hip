@@ -1082,9 +1082,10 @@ __global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
 
   // rho of both parities with the face update, spread like the hops: plane m gets
   // the hops leaving the block from parity fp in direction h and, in one plane per
-  // parity, rho itself. The reads are issued for every dimension at once (a hop that
-  // stays in the block reads its own site and is weighted zero), so their latencies
-  // overlap.
+  // parity, rho itself. The reads are issued for every dimension at once, so their
+  // latencies overlap: a hop that stays in the block reads a valid site (its own
+  // index) and its spinor is replaced by zero, since that memory may hold anything,
+  // NaN included, which a zero weight would not cancel.
   if (a.face) {
     const SiteInfo& si = fp ? so : se;
     const unit* dsrc = dl + size_t(1 - fp) * S::NC * Vh;
@@ -1099,6 +1100,9 @@ __global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
       S::load(dsrc, Vh, ns, nb[mu]);
       if (h == 0) LK::load(lk + size_t(fp * 4 + mu) * LK::NC * Vh, Vh, s, U[mu]);
       else LK::load(lk + size_t((1 - fp) * 4 + mu) * LK::NC * Vh, Vh, ns, U[mu]);
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        if (!n.cross) nb[mu].v[k / 3][k % 3] = {T(0), T(0)};
     }
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
