@@ -209,7 +209,9 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
 
 /* Launch tuning of the context. Keys: "dslash_variant_f64", "dslash_variant_f32",
  * "dslash_variant_bf16" (full-lattice stencil form, 0..5: one lane or two wave groups
- * per site, times three register budgets; 6: four lanes per site), "nr_f64", "nr_low" (right-hand sides per
+ * per site, times three register budgets; 6: four lanes per site; 7: one workgroup per
+ * block of at most 256 sites with the block's input spinor in LDS, other blocks as 0),
+ * "nr_f64", "nr_low" (right-hand sides per
  * stencil thread: 1, 2 or 4), "xcd_map" (1: each XCD sweeps a contiguous range of
  * tiles), "net_mfma" (1: network channel mixing on the matrix cores in bf16, 0: FP32 on
  * the vector units), "block_solver" (block inverses to tolerance: 0 minimal residual

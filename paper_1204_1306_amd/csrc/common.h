@@ -268,6 +268,22 @@ __device__ __forceinline__ Nbr neighbour(const Geo& g, const SiteInfo& si, int m
   return n;
 }
 
+// Read-only view of site q of a [12][N] LDS field as a spinor (p.v[spin][colour]), so
+// a hop reads each component where it uses it instead of copying the spinor first.
+template <class T, int N> struct LdsSpinor {
+  struct Row {
+    const cx<T> (*f)[N];
+    int q, i;
+    __device__ __forceinline__ cx<T> operator[](int c) const { return f[3 * i + c][q]; }
+  };
+  struct Rows {
+    const cx<T> (*f)[N];
+    int q;
+    __device__ __forceinline__ Row operator[](int i) const { return {f, q, i}; }
+  };
+  Rows v;
+};
+
 // ----------------------------------------------------------------- SU(3) x vector
 template <class T> __device__ __forceinline__ void su3_mul(const SU3<T>& u, const cx<T> (&v)[3], cx<T> (&o)[3]) {
 #pragma unroll

@@ -942,22 +942,6 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
 }
 
-// Read-only view of site q of a [12][N] LDS field as a spinor (p.v[spin][colour]), so
-// a hop reads each component where it uses it instead of copying the spinor first.
-template <class T, int N> struct LdsSpinor {
-  struct Row {
-    const cx<T> (*f)[N];
-    int q, i;
-    __device__ __forceinline__ cx<T> operator[](int c) const { return f[3 * i + c][q]; }
-  };
-  struct Rows {
-    const cx<T> (*f)[N];
-    int q;
-    __device__ __forceinline__ Row operator[](int i) const { return {f, q, i}; }
-  };
-  Rows v;
-};
-
 // Even-odd block solver for 256-site blocks with four lanes per site (512 threads,
 // two waves per SIMD), for FP32 arithmetic. The algorithm is that of k_block_mr_eo;
 // here each hop phase is spread four ways. Lane (j, m) takes the hops of site j in

@@ -344,14 +344,106 @@ static void dslash_quad_go(hipStream_t st, const DslashArgs& a, int nprop) {
   launch_timed((k_dslash_quad<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
 }
 
+// Block-tile form (variant 7) for blocks of at most 256 sites: one workgroup per block,
+// one lane per site of either parity. The block's input spinor (both parities) is read
+// once into LDS; a hop that stays in the block reads its neighbour from there and only
+// the hops that leave the block read the neighbour's spinor from memory. This cuts the
+// L1 -> L2 requests per site, which bound the one-lane forms.
+template <class SI, class SO, class LK, class T, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k_dslash_block(DslashArgs a) {
+  __shared__ cx<T> sp[2][12][128];
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int Vbh = g.Vbh;
+  const int nwg = gridDim.x, w = blockIdx.x;
+  const int q = (a.xcd_map && (nwg & 7) == 0) ? (w & 7) * (nwg >> 3) + (w >> 3) : w;
+  const int blk = g.border[q];
+  const int t = threadIdx.x;
+  const int p = t >= Vbh ? 1 : 0;
+  const int i = t - p * Vbh;
+  const bool active = t < 2 * Vbh;
+  const int s = blk * Vbh + i;
+  const int prop = blockIdx.z;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const typename SI::unit* in = reinterpret_cast<const typename SI::unit*>(a.in) + size_t(prop * a.nrhs + blockIdx.y) * a.in_rhs_stride;
+  typename SO::unit* out = reinterpret_cast<typename SO::unit*>(a.out) + size_t(prop * a.nrhs + blockIdx.y) * a.out_rhs_stride;
+
+  Spinor<T> acc;
+  if (active) {
+    SI::load(in + size_t(p) * SI::NC * Vh, Vh, s, acc);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) sp[p][k][i] = acc.v[k / 3][k % 3];
+  }
+  __syncthreads();
+  if (!active) return;  // no barrier follows
+  const T cd = T(a.cdiag), ch = T(a.chop);
+#pragma unroll
+  for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc.v[sc][c] = scale(cd, acc.v[sc][c]);
+  SiteInfo si;
+  site_info(g, p, s, si);
+  const cx<T>(*nbr)[128] = sp[1 - p];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    {  // forward hop: U(x,mu) (1 - gamma_mu) psi(x + mu)
+      Nbr n = neighbour(g, si, mu, +1);
+      SU3<T> U;
+      LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+      if (!n.cross) {
+        const LdsSpinor<T, 128> nb{{nbr, n.s - blk * Vbh}};
+        hop_fwd(mu, U, nb, ch, acc);
+      } else {
+        Spinor<T> nb;
+        SI::load(in + size_t(1 - p) * SI::NC * Vh, Vh, n.s, nb);
+        hop_fwd(mu, U, nb, ch * T(n.sign), acc);
+      }
+    }
+    {  // backward hop: U(x - mu, mu)^+ (1 + gamma_mu) psi(x - mu)
+      Nbr n = neighbour(g, si, mu, -1);
+      SU3<T> U;
+      LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+      if (!n.cross) {
+        const LdsSpinor<T, 128> nb{{nbr, n.s - blk * Vbh}};
+        hop_bwd(mu, U, nb, ch, acc);
+      } else {
+        Spinor<T> nb;
+        SI::load(in + size_t(1 - p) * SI::NC * Vh, Vh, n.s, nb);
+        hop_bwd(mu, U, nb, ch * T(n.sign), acc);
+      }
+    }
+  }
+  typename SO::unit* op = out + size_t(p) * SO::NC * Vh;
+  if (a.accumulate) {
+    Spinor<T> d;
+    SO::load(op, Vh, s, d);
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.v[sc][c] = acc.v[sc][c] + d.v[sc][c];
+  }
+  if (a.nt_out) SO::store_nt(op, Vh, s, acc);
+  else SO::store(op, Vh, s, acc);
+}
+
+template <class SI, class SO, class LK, class T, int W>
+static void dslash_block_go(hipStream_t st, const DslashArgs& a, int nprop) {
+  dim3 grid(a.g.nblk, a.nrhs, nprop);
+  launch_timed((k_dslash_block<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
+}
+
 // Full-lattice stencil variants (form x register budget), chosen by the autotuner:
 //   0: one lane per site          1: two wave groups per site
 //   2: one lane, >= 4 waves/SIMD  3: split, >= 4 waves/SIMD
 //   4: one lane, >= 6 waves/SIMD  5: split, >= 6 waves/SIMD
 //   6: four lanes per site, >= 2 waves/SIMD
+//   7: one workgroup per block of <= 256 sites, the block's input spinor in LDS
+//      (other block sizes, or part of the lattice: variant 0)
 template <class SI, class SO, class LK, class T>
 static void dslash_variant(hipStream_t st, const DslashArgs& a, int nprop, int v) {
+  if (v == 7 && !(2 * a.g.Vbh <= 256 && a.np == 2 && a.p0 == 0 && a.nb == a.g.nblk)) v = 0;
   switch (v) {
+    case 7: dslash_block_go<SI, SO, LK, T, 1>(st, a, nprop); break;
     case 1: dslash_split_go<SI, SO, LK, T, 1>(st, a, nprop); break;
     case 2: dslash_one_go<SI, SO, LK, T, 4>(st, a, nprop); break;
     case 3: dslash_split_go<SI, SO, LK, T, 4>(st, a, nprop); break;

@@ -1931,7 +1931,7 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   REQUIRE(key != nullptr, "null key");
   int* t = tuning_slot(c, key);
   REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
-  if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 6, "stencil variant must be in [0, 6]");
+  if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 7, "stencil variant must be in [0, 7]");
   else if (!std::strcmp(key, "block_eo"))
     REQUIRE(value >= 0 && value <= 3, "block_eo must be 0 (plain), 1 (even-odd), 2 (by launch shape) or 3 (even-odd, links from L2)");
   else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
@@ -2011,7 +2011,7 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     launch_zero(c->st, in, c->Vh);
     int best = 0;
     double tbest = 1e30;
-    for (int v = 0; v <= 6; ++v) {
+    for (int v = 0; v <= 7; ++v) {
       c->variant[pr] = v;
       double t = time_dslash(c, L, in, out, reps);
       if (t < tbest) { tbest = t; best = v; }
