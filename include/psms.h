@@ -67,7 +67,9 @@ typedef struct {
   psms_pc pc;          /* right preconditioner of the flexible GCR */
   int sap_cycles;      /* Schwarz cycles per preconditioner application */
   int block_iters;     /* minimal-residual iterations per block solve inside the Schwarz cycle */
-  double inner_tol;    /* mixed: relative residual reduction asked of each inner solve */
+  double inner_tol;    /* mixed: relative residual reduction asked of each inner solve; a
+                          later pass asks only half the reduction still needed to reach
+                          tol, when that is looser */
   psms_inner_storage inner_storage;
   int net_fallback;    /* PC_NET: fall back to SAP when the residual stalls */
   int rhs_chunk;       /* psms_logdet_ratio: right-hand sides solved together (0: all) */

@@ -816,7 +816,15 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
         ProfScope ps(c, FAM_BLAS, 0);
         launch_copy(st, c->g, r64, rin, inv);
       }
-      GcrResult gr = fgcr(c, L32, cf, rin, e, &act);
+      // A pass only has to bring every residual down to tol |b|: once the residual is
+      // small, the inner tolerance loosens to half the reduction still needed (never
+      // tighter than inner_tol), so the last pass does not over-solve.
+      double need = 1.0;
+      for (int i = 0; i < nr; ++i)
+        if (act[i]) need = std::min(need, pp->tol * std::sqrt(hb[i] / hr[i]));
+      GcrCfg ci = cf;
+      ci.tol = std::max(cf.tol, 0.5 * need);
+      GcrResult gr = fgcr(c, L32, ci, rin, e, &act);
       o.inner += gr.iters;
       if (cf.pc == PSMS_PC_NET && pp->net_fallback) {
         // a network-preconditioned inner solve that does not halve the residual
