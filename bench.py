@@ -42,7 +42,7 @@ def mode_params(psms, mode: str, tol: float):
                                    inner_tol=1e-6)
     if mode == "mixed_bf16":
         return psms.default_params(tol=tol, prec=psms.MIXED, pc=psms.PC_SAP, inner_storage=psms.SPINOR_BF16,
-                                   inner_tol=5e-3, restart=32)
+                                   inner_tol=1e-2, restart=32)
     if mode == "learned":
         return psms.default_params(tol=tol, prec=psms.MIXED, pc=psms.PC_NET, inner_storage=psms.SPINOR_F32,
                                    inner_tol=1e-4, restart=32, max_iter=4000)
