@@ -78,14 +78,14 @@ FAMILIES = ("dslash", "dslash_part", "block_mr", "block_solve", "blas", "net")
 TRAFFIC = {
     # even-odd FP32 block kernel, four lanes per site, links staged in LDS; 8 blocks x 16
     # right-hand sides, Schwarz sweeps
-    ("block_mr", "c2", "mixed"): {"bytes_per_launch": 26458449, "source": "kernels_block.hip",
-                                  "sha256": "73db51707630bb8782df8329d166c74962e74b0782bf922c9152f8167f913336"},
+    ("block_mr", "c2", "mixed"): {"bytes_per_launch": 26457990, "source": "kernels_block.hip",
+                                  "sha256": "fd25afb550b19ac4ba6959272a2aeba348c9e4ac37a009293bd6c8eb0621827d"},
     # full-lattice FP64 stencil at 32^4 on 4x4x8x16 blocks, four lanes per site (variant 6)
     # and split form (variant 1); keyed by lattice/block shape
-    ("dslash_f64_v6", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1343731749, "source": "kernels_dirac.hip",
-                                              "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
-    ("dslash_f64_v1", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1322391961, "source": "kernels_dirac.hip",
-                                              "sha256": "6971eab845e337124782e9761754f50be86699400f62c5e64639fb356b006683"},
+    ("dslash_f64_v6", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1346631627, "source": "kernels_dirac.hip",
+                                              "sha256": "32ebb8c2ff28342c88e02bd90d75fecdc897061fa4ce60d96888daf6719d5d8f"},
+    ("dslash_f64_v1", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1323022657, "source": "kernels_dirac.hip",
+                                              "sha256": "32ebb8c2ff28342c88e02bd90d75fecdc897061fa4ce60d96888daf6719d5d8f"},
 }
 
 
