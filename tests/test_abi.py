@@ -71,3 +71,17 @@ def test_bad_geometries_are_rejected_before_any_device_work(L, b, sap_b, kappa):
     out = ctypes.c_void_p()
     assert lib.psms_create(ctypes.byref(g), 0, None, ctypes.byref(out)) == -1  # PSMS_EINVAL
     assert not out.value
+
+
+def test_every_tuning_key_is_documented_and_accepted_by_the_library():
+    """The binding's tuning keys are the library's: each is named in the header's
+    description of psms_set_tuning, and each is a string the library itself holds."""
+    from paper_1204_1306_amd import psms
+
+    header = open(HEADER).read()
+    for key in psms.Context.TUNING_KEYS:
+        assert f'"{key}"' in header, key
+    if os.path.exists(psms.LIB_PATH):
+        blob = open(psms.LIB_PATH, "rb").read()
+        for key in psms.Context.TUNING_KEYS:
+            assert key.encode() + b"\0" in blob, key
