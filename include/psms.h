@@ -159,6 +159,14 @@ psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* 
                               int nnoise, int n_interp, const psms_solve_params* params, double* delta,
                               psms_solve_stats* stats);
 
+/* The estimate of the log-determinant ratio from the Deltas of psms_logdet_ratio
+ * (Sec. 4.1, eq. stacc: the mean of e^-Delta over Gaussian noise is det(M^+ M)^-1):
+ *   out[p] = ln( (1/nnoise) sum_j exp(-delta[p*nnoise + j]) ),   p < nprop.
+ * Host arrays, FP64; the largest -delta of each row is factored out first, so large
+ * |delta| neither overflow nor underflow. Needs no context. PSMS_EINVAL for null
+ * pointers, nprop or nnoise < 1, or a non-finite delta. */
+psms_status psms_log_ratio_estimate(const double* delta, int nprop, int nnoise, double* out);
+
 /* ---- Learned preconditioner (not from the paper; wraps its solves) ----------------
  * A gauge-covariant linear network N with layers
  *   Psi_c(x) = sum_{t=0..8} sum_c' W[t][c][c'] (T_t Phi_c')(x),

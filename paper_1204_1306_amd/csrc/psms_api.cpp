@@ -1677,6 +1677,21 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
   return PSMS_OK;
 }
 
+psms_status psms_log_ratio_estimate(const double* delta, int nprop, int nnoise, double* out) {
+  if (!delta || !out || nprop < 1 || nnoise < 1) return PSMS_EINVAL;
+  for (size_t i = 0; i < size_t(nprop) * nnoise; ++i)
+    if (!std::isfinite(delta[i])) return PSMS_EINVAL;
+  for (int p = 0; p < nprop; ++p) {
+    const double* d = delta + size_t(p) * nnoise;
+    double top = -d[0];
+    for (int j = 1; j < nnoise; ++j) top = std::max(top, -d[j]);
+    double sum = 0.0;
+    for (int j = 0; j < nnoise; ++j) sum += std::exp(-d[j] - top);
+    out[p] = top + std::log(sum / nnoise);
+  }
+  return PSMS_OK;
+}
+
 psms_status psms_net_init(psms_ctx* c, const int* channels, int nlayers, unsigned long long seed, double scale) {
   API_BEGIN(c)
   REQUIRE(channels != nullptr && nlayers >= 1 && nlayers <= 16, "bad network shape");

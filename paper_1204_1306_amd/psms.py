@@ -88,6 +88,7 @@ _SIGS = {
                                        C.c_void_p]),
     "psms_logdet_ratio": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "psms_log_ratio_estimate": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "psms_net_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_ulonglong, C.c_double]),
     "psms_net_num_weights": (C.c_longlong, [C.c_void_p]),
     "psms_net_set_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_longlong]),
@@ -129,6 +130,19 @@ def default_params(**kw) -> SolveParams:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def log_ratio_estimate(delta) -> np.ndarray:
+    """ln mean_j exp(-delta[p, j]) per proposal p (psms_log_ratio_estimate)."""
+    d = np.ascontiguousarray(np.asarray(delta, np.float64))
+    if d.ndim == 1:
+        d = d[None, :]
+    out = np.empty(d.shape[0], np.float64)
+    s = load_library().psms_log_ratio_estimate(C.c_void_p(d.ctypes.data), d.shape[0], d.shape[1],
+                                               C.c_void_p(out.ctypes.data))
+    if s != 0:
+        raise PsmsError(s, "psms_log_ratio_estimate: null, empty or non-finite input")
+    return out
 
 
 def _is_torch(a) -> bool:

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -85,3 +86,29 @@ def test_every_tuning_key_is_documented_and_accepted_by_the_library():
         blob = open(psms.LIB_PATH, "rb").read()
         for key in psms.Context.TUNING_KEYS:
             assert key.encode() + b"\0" in blob, key
+
+
+def test_log_ratio_estimate_matches_the_oracle():
+    """psms_log_ratio_estimate (host code of the library, no GPU) against the oracle's
+    ln mean_j exp(-Delta_j), on Deltas of ordinary size and on Deltas whose exponentials
+    overflow or underflow FP64; bad input gives PSMS_EINVAL."""
+    from oracle import estimator
+    from paper_1204_1306_amd import psms
+
+    if not os.path.exists(psms.LIB_PATH):
+        pytest.skip("libpsms.so not built")
+    rng = np.random.default_rng(77)
+    d = rng.normal(0.3, 1.2, size=(5, 16))
+    got = psms.log_ratio_estimate(d)
+    for p in range(5):
+        assert got[p] == pytest.approx(estimator.log_ratio_estimate(d[p]), rel=1e-13, abs=1e-14)
+    big = np.array([[-800.0, -799.0, -798.5], [900.0, 901.0, 950.0]])  # e^800 overflows, e^-900 underflows
+    got = psms.log_ratio_estimate(big)
+    for p in range(2):
+        assert np.isfinite(got[p])
+        assert got[p] == pytest.approx(estimator.log_ratio_estimate(big[p]), rel=1e-13)
+    assert psms.log_ratio_estimate([0.0, 0.0])[0] == 0.0  # Delta = 0 exactly: ln 1
+    with pytest.raises(psms.PsmsError):
+        psms.log_ratio_estimate([[0.0, np.nan]])
+    with pytest.raises(psms.PsmsError):
+        psms.log_ratio_estimate(np.zeros((1, 0)))
