@@ -82,8 +82,8 @@ def test_c2_bench_configuration_against_oracle(psms):
     w, U, Ups, eta = synth.workload_inputs("c2")
     ctx = _load(psms, w, U, Ups)
     ctx.autotune(0, None)
-    d_mx, s_mx = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "mixed", w["tol"]))
-    d_64, s_64 = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "plain", w["tol"]))
+    d_mx, s_mx = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "mixed", w["tol"], "c2"))
+    d_64, s_64 = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "plain", w["tol"], "c2"))
     say(" mixed", s_mx, "plain", s_64)
     assert s_mx["converged"] and s_64["converged"]
     assert s_mx["true_rel_residual"] <= w["tol"] and s_64["true_rel_residual"] <= w["tol"]
