@@ -474,6 +474,9 @@ def main():
         "plain_f64_s_per_estimate": s_plain,
         "speedup_vs_plain_f64": s_plain / value,
         "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
+        # ln mean_j exp(-Delta_pj) per proposal, from the same noise in both modes
+        "log_ratio_estimate": {"fast": [round(float(v), 10) for v in psms.log_ratio_estimate(d_fast)],
+                               "plain": [round(float(v), 10) for v in psms.log_ratio_estimate(d_plain)]},
         "learned": learned,
         "batched": batched,
         "network": net,

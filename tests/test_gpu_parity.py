@@ -289,6 +289,9 @@ def test_logdet_ratio_small_workload(psms):
         ref = _oracle_deltas(w, U, Ups, eta, kind)
         say(" delta", kind, d.ravel(), ref.ravel(), st)
         assert np.abs(d - ref).max() < 1e-8
+        # the log-ratio estimate from these Deltas against the oracle's from its own
+        lhat = psms.log_ratio_estimate(d)
+        assert abs(lhat[0] - estimator.log_ratio_estimate(ref[0])) < 1e-8
 
 
 def test_logdet_ratio_mixed_vs_f64_8x4(psms):
