@@ -154,6 +154,8 @@ psms_status psms_apply_schur_inv(psms_ctx* ctx, int slot, const double* in, doub
  *   op FULL : M = D(U')^-1 D(U),                 xi_j = eta_j;
  *   op SCHUR: M = (1 - PQ(U'))^-1 (1 - PQ(U)),   xi_j = P eta_j.
  * noise holds nnoise fields with density exp(-|eta|^2); n_interp must be 1.
+ * SCHUR: the full solve inside (1 - PQ(U'))^-1 starts from the exact solution of the
+ * same system with U, a by-product of applying (1 - PQ(U)); tol still refers to |b|.
  * delta may be host or device memory (nprop*nnoise doubles). */
 psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise,
                               int nnoise, int n_interp, const psms_solve_params* params, double* delta,

@@ -691,20 +691,25 @@ struct FullSolveOut {
 };
 
 FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& b64,
-                             const FieldBatch& x64);
+                             const FieldBatch& x64, const FieldBatch* x0 = nullptr);
 
 // Full-lattice solve D x = b. With a separate Schwarz block size the right-hand sides
 // are permuted into the solver layout, solved there and the solutions permuted back.
 FullSolveOut solve_full(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& b64,
-                        const FieldBatch& x64) {
-  if (!c->split || c->solver_view) return solve_full_impl(c, slots, pp, b64, x64);
+                        const FieldBatch& x64, const FieldBatch* x0 = nullptr) {
+  if (!c->split || c->solver_view) return solve_full_impl(c, slots, pp, b64, x64, x0);
   FieldBatch bs = field(c, "sv_b", P_F64, b64.nprop, b64.nrhs), xs = field(c, "sv_x", P_F64, b64.nprop, b64.nrhs);
   launch_permute(c->st, c->g, c->gs, b64, bs);
+  FieldBatch x0s{};
+  if (x0) {
+    x0s = field(c, "sv_x0", P_F64, x0->nprop, x0->nrhs);
+    launch_permute(c->st, c->g, c->gs, *x0, x0s);
+  }
   std::swap(c->g, c->gs);
   c->solver_view = true;
   FullSolveOut o;
   try {
-    o = solve_full_impl(c, slots, pp, bs, xs);
+    o = solve_full_impl(c, slots, pp, bs, xs, x0 ? &x0s : nullptr);
   } catch (...) {
     std::swap(c->g, c->gs);
     c->solver_view = false;
@@ -716,8 +721,10 @@ FullSolveOut solve_full(psms_ctx* c, const int* slots, const psms_solve_params* 
   return o;
 }
 
+// x0 (optional): an initial guess of the same shape; convergence is still judged
+// against |b|.
 FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& b64,
-                             const FieldBatch& x64) {
+                             const FieldBatch& x64, const FieldBatch* x0) {
   FullSolveOut o;
   const int np = b64.nprop, nrb = b64.nrhs, nr = np * nrb;
   const hipStream_t st = c->st;
@@ -735,7 +742,30 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
       cf.net_links = &L32;
       if (pp->net_fallback) cf.maxit = std::min(pp->max_iter, 8 * restart);
     }
-    GcrResult gr = fgcr(c, L64, cf, b64, x64);
+    // with a guess: D e = b - D x0 to the same absolute residual, x = x0 + e
+    FieldBatch rb = b64;
+    if (x0) {
+      rb = field(c, "fs_r0", P_F64, np, nrb);
+      apply_D(c, L64, *x0, rb);
+      {
+        ProfScope ps(c, FAM_BLAS, 0);
+        launch_axpby(st, c->g, const_cx(c, "one", nr, 1, 0), b64, const_cx(c, "mone", nr, -1, 0), rb, +1);
+      }
+      double* n1 = dscratch<double>(c, "fs_g1", nr);
+      double* n2 = dscratch<double>(c, "fs_g2", nr);
+      norm2(c, rb, n1);
+      norm2(c, b64, n2);
+      std::vector<double> h1 = to_host(c, n1, nr), h2 = to_host(c, n2, nr);
+      double ratio = 1e300;
+      for (int i = 0; i < nr; ++i)
+        if (h1[i] > 0) ratio = std::min(ratio, std::sqrt(h2[i] / h1[i]));
+      cf.tol = ratio < 1e300 ? pp->tol * ratio : pp->tol;
+    }
+    GcrResult gr = fgcr(c, L64, cf, rb, x64);
+    if (x0) {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_axpby(st, c->g, const_cx(c, "one", nr, 1, 0), *x0, nullptr, x64, +1);
+    }
     o.inner = gr.iters;
     o.outer = 1;
     o.nan = gr.nan;
@@ -788,7 +818,15 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
     int* dact = dscratch<int>(c, "dc_active", nr);
     const double2* ONE = const_cx(c, "one", nr, 1.0, 0.0);
     const double2* MONE = const_cx(c, "mone", nr, -1.0, 0.0);
-    {
+    if (x0) {  // start from the guess: x = x0, r = b - D x0
+      {
+        ProfScope ps(c, FAM_BLAS, 0);
+        launch_copy(st, c->g, *x0, x64, nullptr);
+      }
+      apply_D(c, L64, x64, r64);
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_axpby(st, c->g, ONE, b64, MONE, r64, +1);
+    } else {
       ProfScope ps(c, FAM_BLAS, 0);
       launch_copy(st, c->g, b64, r64, nullptr);
       launch_zero(st, x64, c->Vh);
@@ -1035,8 +1073,11 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
 }
 
 // out = (1 - P Q) xi, Q = D_bb^-1 D_bw D_ww^-1 D_wb. Returns worst block-solve residual.
+// With zg: also zg = [-Q xi]_black + [D_ww^-1 D_wb xi]_white, which solves
+// D z = 0 (+) D_wb (1 - PQ) xi exactly (D_wb P = D_wb): the solution that the inverse
+// of eq. inverseschur needs for these links, and a close guess for nearby links.
 double schur_apply(psms_ctx* c, const int* slots, const FieldBatch& xi, const FieldBatch& out, double tol, int maxit,
-                   bool mixed = false) {
+                   bool mixed = false, const FieldBatch* zg = nullptr) {
   const int np = xi.nprop, nrb = xi.nrhs;
   Links L = links_of(c, slots, np, LK_F64);
   FieldBatch t1 = field(c, "sc_t1", P_F64, np, nrb);
@@ -1049,14 +1090,16 @@ double schur_apply(psms_ctx* c, const int* slots, const FieldBatch& xi, const Fi
   double r1 = solve_colour(c, slots, 1, t1, t2, tol, maxit, nullptr, mixed);  // D_ww^-1
   {
     ProfScope ps(c, FAM_BLAS, 0);
+    if (zg) launch_copy(c->st, c->g, t2, *zg, nullptr);  // white part (black sites are zero)
     launch_zero(c->st, t1, c->Vh);
   }
   dslash(c, L, t2, t1, HOP_CROSS, 0, 0.0, -c->geom.kappa, 0);  // D_bw (black sites)
   double r2 = solve_colour(c, slots, 0, t1, t2, tol, maxit, nullptr, mixed);  // D_bb^-1
   {
     ProfScope ps(c, FAM_BLAS, 0);
-    launch_project(c->st, c->g, t2, t1);
     const int nr = np * nrb;
+    if (zg) launch_axpby(c->st, c->g, const_cx(c, "mone", nr, -1, 0), t2, nullptr, *zg, +1);  // black part -Q xi
+    launch_project(c->st, c->g, t2, t1);
     launch_copy(c->st, c->g, xi, out, nullptr);
     launch_axpby(c->st, c->g, const_cx(c, "mone", nr, -1, 0), t1, nullptr, out, +1);
   }
@@ -1065,7 +1108,7 @@ double schur_apply(psms_ctx* c, const int* slots, const FieldBatch& xi, const Fi
 
 // out = phi - P [D^-1 (0 + D_wb phi)]  (eq. inverseschur)
 FullSolveOut schur_inverse(psms_ctx* c, const int* slots, const psms_solve_params* pp, const FieldBatch& phi,
-                           const FieldBatch& out) {
+                           const FieldBatch& out, const FieldBatch* x0 = nullptr) {
   const int np = phi.nprop, nrb = phi.nrhs, nr = np * nrb;
   Links L64 = links_of(c, slots, np, LK_F64);
   FieldBatch v = field(c, "si_v", P_F64, np, nrb);
@@ -1075,7 +1118,7 @@ FullSolveOut schur_inverse(psms_ctx* c, const int* slots, const psms_solve_param
     launch_zero(c->st, v, c->Vh);
   }
   dslash(c, L64, phi, v, HOP_CROSS, 1, 0.0, -c->geom.kappa, 0);
-  FullSolveOut o = solve_full(c, slots, pp, v, x);
+  FullSolveOut o = solve_full(c, slots, pp, v, x, x0);
   ProfScope ps(c, FAM_BLAS, 0);
   launch_project(c->st, c->g, x, v);
   launch_copy(c->st, c->g, phi, out, nullptr);
@@ -1625,9 +1668,12 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
     FieldBatch phi = field(c, "ld_phi", P_F64, 1, nj);
     launch_pack(c->st, c->g, dn + size_t(j0) * fd, eta);
     double* xin2 = dscratch<double>(c, "ld_xin2", nj);
+    // SCHUR: the full solve inside (1 - PQ(U'))^-1 starts from the solution of the same
+    // system with U, which (1 - PQ(U)) xi yields as a by-product
+    FieldBatch z0 = field(c, "ld_z0", P_F64, 1, nj);
     if (op == PSMS_OP_SCHUR) {
       launch_project(c->st, c->g, eta, xi);
-      double rel = schur_apply(c, &slot_U, xi, phi, pp->tol, pp->max_iter, pp->prec == PSMS_MIXED);
+      double rel = schur_apply(c, &slot_U, xi, phi, pp->tol, pp->max_iter, pp->prec == PSMS_MIXED, &z0);
       if (!(rel <= pp->tol * 1.0001)) agg.converged = false;
     } else {
       launch_copy(c->st, c->g, eta, xi, nullptr);
@@ -1644,7 +1690,10 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
         HIPCHK(hipMemcpyAsync((char*)rhs.p + p * fb, phi.p, fb, hipMemcpyDeviceToDevice, c->st));
       FullSolveOut o;
       if (op == PSMS_OP_SCHUR) {
-        o = schur_inverse(c, slot_Up + p0, pp, rhs, y);
+        FieldBatch z0p = field(c, "ld_z0p", P_F64, npp, nj);
+        for (int p = 0; p < npp; ++p)
+          HIPCHK(hipMemcpyAsync((char*)z0p.p + p * fb, z0.p, fb, hipMemcpyDeviceToDevice, c->st));
+        o = schur_inverse(c, slot_Up + p0, pp, rhs, y, &z0p);
       } else {
         o = solve_full(c, slot_Up + p0, pp, rhs, y);
       }

@@ -230,6 +230,23 @@ def test_schur_inverse_formula(L, b, kappa):
     assert np.sqrt(norm2(op.schur_apply(y1) - xi) / norm2(xi)) < 1e-12
 
 
+@pytest.mark.parametrize("L,b,kappa", [((4, 4, 4, 4), (2, 2, 2, 2), 0.12), ((8, 8, 8, 8), (4, 4, 4, 4), 0.15)])
+def test_inverse_schur_solution_for_the_same_links(L, b, kappa):
+    """For phi = (1 - PQ) xi, the full solve inside eq. inverseschur, D z = 0 (+) D_wb phi,
+    has the solution z = [-Q xi]_black + [D_ww^-1 D_wb xi]_white (block elimination, with
+    D_wb P = D_wb): the by-product of (1 - PQ) xi that starts the solve for nearby links."""
+    g = schur.Geometry(L, b)
+    op = schur.Operator(g, synth.gauge_field(L, 0.6, 79), kappa)
+    xi = g.project(synth.gaussian_noise(L, 1, 80)[0])
+    phi = op.schur_apply(xi)
+    z = op.solve(op.D_wb(phi), tol=1e-14)
+    w = op.solve_colour(op.D_wb(xi), "white")
+    guess = g.restrict(-op.Q(xi), g.black) + g.restrict(w, g.white)
+    assert np.sqrt(norm2(z - guess) / norm2(z)) < 1e-11
+    # and it reproduces the inverse: phi - P z_black = xi
+    assert np.sqrt(norm2(phi - g.project(g.restrict(guess, g.black)) - xi) / norm2(xi)) < 1e-12
+
+
 def test_schur_interior_gauge_invariance():
     """1 - PQ on range(P) is unchanged by gauge transformations supported on block-interior sites
     (Sec. 4.4, last paragraph)."""
