@@ -34,10 +34,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Schwarz cycles x block iterations measured best per workload and mode (the library
-# default, 3 x 8, is best at 16^4). At 8^4 the step is latency-bound and more, shorter
-# cycles pay: mixed 4 x 6 (10 inner iterations, against 12 at 3 x 8), plain 5 x 6.
-SAP_TUNED = {("c2", "mixed"): (4, 6), ("c2", "plain"): (5, 6)}
+# Schwarz cycles x block iterations where the measured best differs from the library
+# default (4 x 6, best for mixed at 8^4 and for both modes at 16^4 and 32^4): plain
+# FP64 at 8^4 prefers 5 x 6.
+SAP_TUNED = {("c2", "plain"): (5, 6)}
 
 
 def mode_params(psms, mode: str, tol: float, workload: str | None = None):

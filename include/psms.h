@@ -87,7 +87,7 @@ typedef struct {
 typedef struct psms_ctx psms_ctx;
 
 /* Fills params with defaults: tol 1e-10, max_iter 2000, restart 16, F64, SAP,
- * 3 cycles, 8 block iterations, inner_tol 1e-2 (BF16 inner storage clamps it to
+ * 4 cycles, 6 block iterations, inner_tol 1e-2 (BF16 inner storage clamps it to
  * >= 5e-3), F32 inner storage, fallback on, rhs_chunk 0. */
 void psms_default_params(psms_solve_params* params);
 

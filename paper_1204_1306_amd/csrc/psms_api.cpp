@@ -1313,8 +1313,8 @@ void psms_default_params(psms_solve_params* p) {
   p->restart = 16;
   p->prec = PSMS_F64;
   p->pc = PSMS_PC_SAP;
-  p->sap_cycles = 3;
-  p->block_iters = 8;
+  p->sap_cycles = 4;
+  p->block_iters = 6;
   p->inner_tol = 1e-2;
   p->inner_storage = PSMS_SPINOR_F32;
   p->net_fallback = 1;
