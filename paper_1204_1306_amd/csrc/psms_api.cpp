@@ -451,6 +451,16 @@ std::vector<double> to_host(psms_ctx* c, const double* d, int n) {
   return h;
 }
 
+// Two device arrays (n1 and n2 doubles) to the host behind one synchronisation.
+void to_host2(psms_ctx* c, const double* d1, int n1, std::vector<double>& h1, const double* d2, int n2,
+              std::vector<double>& h2) {
+  h1.resize(n1);
+  h2.resize(n2);
+  HIPCHK(hipMemcpyAsync(h1.data(), d1, n1 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(h2.data(), d2, n2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+}
+
 // ------------------------------------------------------------------ Schwarz preconditioner
 struct SapCfg {
   int cycles, iters;
@@ -729,6 +739,7 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
   const int np = b64.nprop, nrb = b64.nrhs, nr = np * nrb;
   const hipStream_t st = c->st;
   Links L64 = links_of(c, slots, np, LK_F64);
+  std::vector<double> fin_r2, fin_b2;  // |b - D x|^2 and |b|^2 when already on the host
   int restart = std::max(2, std::min(pp->restart, 64));
   const bool use_net = pp->pc == PSMS_PC_NET;
   if (use_net) REQUIRE(c->net.nlayers > 0, "PC_NET needs a network (psms_net_init or psms_net_load)");
@@ -755,7 +766,8 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
       double* n2 = dscratch<double>(c, "fs_g2", nr);
       norm2(c, rb, n1);
       norm2(c, b64, n2);
-      std::vector<double> h1 = to_host(c, n1, nr), h2 = to_host(c, n2, nr);
+      std::vector<double> h1, h2;
+      to_host2(c, n1, nr, h1, n2, nr, h2);
       double ratio = 1e300;
       for (int i = 0; i < nr; ++i)
         if (h1[i] > 0) ratio = std::min(ratio, std::sqrt(h2[i] / h1[i]));
@@ -784,7 +796,8 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
       double* n2 = dscratch<double>(c, "fb_n2", nr);
       norm2(c, r64, n1);
       norm2(c, b64, n2);
-      std::vector<double> h1 = to_host(c, n1, nr), h2 = to_host(c, n2, nr);
+      std::vector<double> h1, h2;
+      to_host2(c, n1, nr, h1, n2, nr, h2);
       double ratio = 1.0;
       for (int i = 0; i < nr; ++i)
         if (h1[i] > 0) ratio = std::min(ratio, std::sqrt(h2[i] / h1[i]));
@@ -832,11 +845,15 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
       launch_zero(st, x64, c->Vh);
     }
     norm2(c, b64, bn2);
-    std::vector<double> hb = to_host(c, bn2, nr);
+    std::vector<double> hb, hr;
     const double tol2 = pp->tol * pp->tol;
     while (true) {
       norm2(c, r64, rn2);
-      std::vector<double> hr = to_host(c, rn2, nr);
+      if (hb.empty()) {
+        to_host2(c, bn2, nr, hb, rn2, nr, hr);
+      } else {
+        hr = to_host(c, rn2, nr);
+      }
       std::vector<int> act(nr);
       bool all = true;
       for (int i = 0; i < nr; ++i) {
@@ -846,6 +863,9 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
       }
       if (all || o.nan || o.inner >= pp->max_iter) {
         o.converged = all && !o.nan;
+        // r64 = b - D x64 was just formed in FP64: it is the true residual
+        fin_r2 = hr;
+        fin_b2 = hb;
         break;
       }
       HIPCHK(hipMemcpyAsync(dact, act.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
@@ -889,18 +909,24 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
       launch_axpby(st, c->g, ONE, b64, MONE, r64, +1);
     }
   }
-  // true FP64 residual
-  FieldBatch r64 = field(c, "fs_r", P_F64, np, nrb);
-  apply_D(c, L64, x64, r64);
-  {
-    ProfScope ps(c, FAM_BLAS, 0);
-    launch_axpby(st, c->g, const_cx(c, "one", nr, 1, 0), b64, const_cx(c, "mone", nr, -1, 0), r64, +1);
+  // true FP64 residual (the defect-correction loop ends with it in hand)
+  std::vector<double> h1, h2;
+  if (!fin_r2.empty()) {
+    h1.swap(fin_r2);
+    h2.swap(fin_b2);
+  } else {
+    FieldBatch r64 = field(c, "fs_r", P_F64, np, nrb);
+    apply_D(c, L64, x64, r64);
+    {
+      ProfScope ps(c, FAM_BLAS, 0);
+      launch_axpby(st, c->g, const_cx(c, "one", nr, 1, 0), b64, const_cx(c, "mone", nr, -1, 0), r64, +1);
+    }
+    double* t1 = dscratch<double>(c, "fs_n1", nr);
+    double* t2 = dscratch<double>(c, "fs_n2", nr);
+    norm2(c, r64, t1);
+    norm2(c, b64, t2);
+    to_host2(c, t1, nr, h1, t2, nr, h2);
   }
-  double* t1 = dscratch<double>(c, "fs_n1", nr);
-  double* t2 = dscratch<double>(c, "fs_n2", nr);
-  norm2(c, r64, t1);
-  norm2(c, b64, t2);
-  std::vector<double> h1 = to_host(c, t1, nr), h2 = to_host(c, t2, nr);
   o.max_rel = 0;
   for (int i = 0; i < nr; ++i) {
     double rel = h2[i] > 0 ? std::sqrt(h1[i] / h2[i]) : std::sqrt(h1[i]);
@@ -1066,7 +1092,8 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
   }
   norm2(c, rt, n1);
   norm2(c, bc, n2);
-  std::vector<double> h1 = to_host(c, n1, nr), h2 = to_host(c, n2, nr);
+  std::vector<double> h1, h2;
+  to_host2(c, n1, nr, h1, n2, nr, h2);
   double mx = 0;
   for (int i = 0; i < nr; ++i) mx = std::max(mx, h2[i] > 0 ? std::sqrt(h1[i] / h2[i]) : std::sqrt(h1[i]));
   return mx;
@@ -1680,7 +1707,7 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
       apply_D(c, LU, xi, phi);
     }
     norm2(c, xi, xin2);
-    std::vector<double> hx = to_host(c, xin2, nj);
+    std::vector<double> hx;  // fetched with the first chunk's |y|^2
     for (int p0 = 0; p0 < nprop; p0 += pchunk) {
       const int npp = std::min(pchunk, nprop - p0);
       FieldBatch rhs = field(c, "ld_rhs", P_F64, npp, nj);
@@ -1705,7 +1732,12 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
       agg.used_fallback |= o.used_fallback;
       double* yn2 = dscratch<double>(c, "ld_yn2", size_t(npp) * nj);
       norm2(c, y, yn2);
-      std::vector<double> hy = to_host(c, yn2, npp * nj);
+      std::vector<double> hy;
+      if (hx.empty()) {
+        to_host2(c, xin2, nj, hx, yn2, npp * nj, hy);
+      } else {
+        hy = to_host(c, yn2, npp * nj);
+      }
       for (int p = 0; p < npp; ++p)
         for (int j = 0; j < nj; ++j) hdelta[size_t(p0 + p) * nnoise + j0 + j] = hy[size_t(p) * nj + j] - hx[j];
     }
