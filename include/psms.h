@@ -237,7 +237,10 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
  * sweeps with block_iters/2 iterations rounded up) and "block_eo_lanes" (even-odd block
  * solver on 256-site blocks in FP32 or BF16 storage: 2 or 4 lanes per site; 0, the
  * default, 4 when the launch has fewer workgroups than the GPU has compute units, else
- * 2; FP64 block solves always use 2).
+ * 2; FP64 block solves always use 2) and "block_tol_prec" (block inverses to tolerance in
+ * a mixed-precision solve with SU(3) links: 1 FP32 block passes inside FP64 defect
+ * correction, 2 FP64 block solves, 0, the default, FP32 passes for blocks of more than
+ * 256 sites and FP64 for smaller ones).
  * Unknown keys or values give
  * PSMS_EINVAL. Results do not depend on the tuning beyond rounding; only speed does. */
 psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);

@@ -94,11 +94,28 @@ struct Reducer {
   int nwg;           // workgroups per rhs in pass one
 };
 void reduce_norm2(hipStream_t st, const Geo& g, const FieldBatch& x, const Reducer& R, double* out);
-// out[r*m + j] = (X_j, y)_r for j < m, X_j = basis + j*vstride
+// Scalar steps of flexible GCR for basis vector k (capacity m, nrhs right-hand sides)
+// that the last pass of a reduction can take over; the reduced values then go only
+// into these arrays (out is not written).
+struct GcrStep {
+  int k, m, nrhs;
+  const int* active;   // right-hand sides still iterating
+  double* nw;          // [r*m + j] |w_j|^2
+  double2* a;          // [r*m + j] projection coefficients (w_j, w_k) / |w_j|^2
+  double2* T;          // [(r*m + j)*m + k] the same, kept for the back substitution
+  double2* alpha;      // [k*nrhs + r] step length (w_k, r) / |w_k|^2
+  double2* neg_alpha;  // [r] -alpha
+};
+// out[r*m + j] = (X_j, y)_r for j < m, X_j = basis + j*vstride. With gs (m = gs->k):
+// gs->a[r*m' + j] = out / gs->nw[r*m' + j] (0 when that norm is 0; m' = gs->m) and
+// gs->T[(r*m' + j)*m' + k] = gs->a[r*m' + j].
 void reduce_multidot(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m,
-                     const FieldBatch& y, const Reducer& R, double2* out);
-// out3[r*3] = {|x|^2, Re (x, y), Im (x, y)} in one pass (x, y of one storage)
-void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double* out3);
+                     const FieldBatch& y, const Reducer& R, double2* out, const GcrStep* gs = nullptr);
+// out3[r*3] = {|x|^2, Re (x, y), Im (x, y)} in one pass (x, y of one storage). With gs
+// (x = w_k, y = r): gs->nw[r*m + k] = |x|^2, gs->alpha[k*nrhs + r] = (x, y) / |x|^2 for
+// active right-hand sides with a nonzero norm (else 0), gs->neg_alpha[r] = -alpha.
+void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double* out3,
+                     const GcrStep* gs = nullptr);
 // y += a[r] x and out[r] = |y|^2 in one pass (x, y of one storage)
 void axpy_norm2(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
                 double* out);
@@ -124,12 +141,8 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
                      int* iters_out);
 
 // --- flexible GCR scalar kernels and mixed-storage site-level ops
-void gcr_proj(hipStream_t st, const double2* c, const double* nw, int k, int m, int nrhs, double2* a, double2* T);
 void gcr_alpha(hipStream_t st, const double2* d, const double* nw, int k, int m, int nrhs, const int* active, double2* alpha,
                double2* neg_alpha);
-// the same from nd[r*3] = {|w_k|^2, (w_k, r)}, also storing nw[r*m + k] = |w_k|^2
-void gcr_alpha_nd(hipStream_t st, const double* nd, int k, int m, int nrhs, const int* active, double* nw, double2* alpha,
-                  double2* neg_alpha);
 void gcr_backsub(hipStream_t st, const double2* T, const double2* alpha, int n, int m, int nrhs, double2* beta);
 void scatter_col(hipStream_t st, const double* src, int k, int m, int nrhs, double* dst);
 void defect_scales(hipStream_t st, const double* v, const int* active, int nrhs, double* inv, double2* sq);
@@ -138,7 +151,7 @@ void reduce_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const F
 // fused passes for a BF16 basis vector x and an FP32 residual y (fused_mixed_ok)
 bool fused_mixed_ok(const FieldBatch& x, const FieldBatch& y);
 void reduce_norm_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
-                           double* out3);
+                           double* out3, const GcrStep* gs = nullptr);
 void axpy_norm2_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
                       double* out);
 

@@ -245,6 +245,49 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int nwg, int 
   }
 }
 
+// The last pass of reduce_multidot with the projection step of flexible GCR: entry
+// q = r * k + j is (W_j, w_k)_r, summed exactly as k_reduce_final sums it; then
+// a[r*m + j] = entry / nw[r*m + j] (0 when nw is 0) and T[(r*m + j)*m + k] = a.
+__global__ void k_reduce_final_proj(const double* __restrict__ partial, int nwg, GcrStep gs) {
+  __shared__ double sm[16];
+  const int q = blockIdx.x;
+  double v[2];
+  for (int c = 0; c < 2; ++c) {
+    double acc = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += blockDim.x) acc += partial[(size_t(q) * nwg + w) * 2 + c];
+    v[c] = block_sum(acc, sm);
+  }
+  if (threadIdx.x == 0) {
+    const int r = q / gs.k, j = q - r * gs.k;
+    const double n = gs.nw[r * gs.m + j];
+    const double2 e = n > 0 ? make_double2(v[0] / n, v[1] / n) : make_double2(0, 0);
+    gs.a[r * gs.m + j] = e;
+    gs.T[(size_t(r) * gs.m + j) * gs.m + gs.k] = e;
+  }
+}
+
+// The last pass of reduce_norm_dot with the step length of flexible GCR: from
+// {|w_k|^2, (w_k, r)} of right-hand side r (summed as k_reduce_final sums them),
+// nw[r*m + k] = |w_k|^2, alpha[k*nrhs + r] = (w_k, r) / |w_k|^2 for active right-hand
+// sides with a nonzero norm (else 0) and neg_alpha[r] = -alpha.
+__global__ void k_reduce_final_alpha(const double* __restrict__ partial, int nwg, GcrStep gs) {
+  __shared__ double sm[16];
+  const int r = blockIdx.x;
+  double v[3];
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += blockDim.x) acc += partial[(size_t(r) * nwg + w) * 3 + c];
+    v[c] = block_sum(acc, sm);
+  }
+  if (threadIdx.x == 0) {
+    const double n = v[0];
+    gs.nw[r * gs.m + gs.k] = n;
+    const double2 e = (gs.active[r] && n > 0) ? make_double2(v[1] / n, v[2] / n) : make_double2(0, 0);
+    gs.alpha[gs.k * gs.nrhs + r] = e;
+    gs.neg_alpha[r] = make_double2(-e.x, -e.y);
+  }
+}
+
 template <Prec P> static void norm2_go(hipStream_t st, const Geo& g, const FieldBatch& x, const Reducer& R, double* out) {
   size_t n = units_per_field(P, g.Vh);
   hipLaunchKernelGGL(k_norm2_p1<P>, dim3(R.nwg, nrhs_of(x)), dim3(256), 0, st, (const typename Unit<P>::unit*)x.p, n, R.partial);
@@ -298,17 +341,18 @@ __global__ void k_multidot_p1(const typename Unit<P>::unit* __restrict__ basis, 
 }
 
 template <Prec P> static void multidot_go(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const FieldBatch& y,
-                                          const Reducer& R, double2* out) {
+                                          const Reducer& R, double2* out, const GcrStep* gs) {
   size_t n = units_per_field(P, g.Vh);
   for (int j0 = 0; j0 < m; j0 += 16)
     hipLaunchKernelGGL((k_multidot_p1<P, 16>), dim3(R.nwg, nrhs_of(y)), dim3(256), 0, st, (const typename Unit<P>::unit*)basis.p,
                        vstride, j0, m, (const typename Unit<P>::unit*)y.p, n, R.partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs_of(y) * m), dim3(256), 0, st, R.partial, R.nwg, 2, (double*)out);
+  if (gs) hipLaunchKernelGGL(k_reduce_final_proj, dim3(nrhs_of(y) * m), dim3(256), 0, st, R.partial, R.nwg, *gs);
+  else hipLaunchKernelGGL(k_reduce_final, dim3(nrhs_of(y) * m), dim3(256), 0, st, R.partial, R.nwg, 2, (double*)out);
 }
 void reduce_multidot(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const FieldBatch& y,
-                     const Reducer& R, double2* out) {
+                     const Reducer& R, double2* out, const GcrStep* gs) {
   if (m <= 0) return;
-  DISPATCH_PREC(y.prec, multidot_go, st, g, basis, vstride, m, y, R, out);
+  DISPATCH_PREC(y.prec, multidot_go, st, g, basis, vstride, m, y, R, out, gs);
 }
 
 // |x|^2 and (x, y) (conj on x) in one pass; partial [(r * nwg + w) * 3 + {|x|^2, Re, Im}]
@@ -342,14 +386,16 @@ __global__ void k_norm_dot_p1(const typename Unit<P>::unit* __restrict__ x, cons
   }
 }
 template <Prec P> static void norm_dot_go(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
-                                          double* out3) {
+                                          double* out3, const GcrStep* gs) {
   size_t n = units_per_field(P, g.Vh);
   hipLaunchKernelGGL(k_norm_dot_p1<P>, dim3(R.nwg, nrhs_of(x)), dim3(256), 0, st, (const typename Unit<P>::unit*)x.p,
                      (const typename Unit<P>::unit*)y.p, n, R.partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs_of(x)), dim3(256), 0, st, R.partial, R.nwg, 3, out3);
+  if (gs) hipLaunchKernelGGL(k_reduce_final_alpha, dim3(nrhs_of(x)), dim3(256), 0, st, R.partial, R.nwg, *gs);
+  else hipLaunchKernelGGL(k_reduce_final, dim3(nrhs_of(x)), dim3(256), 0, st, R.partial, R.nwg, 3, out3);
 }
-void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double* out3) {
-  DISPATCH_PREC(x.prec, norm_dot_go, st, g, x, y, R, out3);
+void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double* out3,
+                     const GcrStep* gs) {
+  DISPATCH_PREC(x.prec, norm_dot_go, st, g, x, y, R, out3, gs);
 }
 
 // y += a[r] * x and the partial sums of |y|^2 (new y) in one pass

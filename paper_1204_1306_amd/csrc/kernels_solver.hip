@@ -4,18 +4,6 @@
 
 namespace psms {
 
-// a[r*m + j] = c[r*k + j] / nw[r*m + j] for j < k (0 when nw == 0); T[(r*m + j)*m + k] = a
-__global__ void k_gcr_proj(const double2* __restrict__ c, const double* __restrict__ nw, int k, int m, int nrhs,
-                           double2* __restrict__ a, double2* __restrict__ T) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrhs * k) return;
-  int r = t / k, j = t - r * k;
-  double n = nw[r * m + j];
-  double2 v = n > 0 ? make_double2(c[r * k + j].x / n, c[r * k + j].y / n) : make_double2(0, 0);
-  a[r * m + j] = v;
-  T[(size_t(r) * m + j) * m + k] = v;
-}
-
 // alpha[k*nrhs + r] = d[r] / nw[r*m + k] for active right-hand sides, else 0
 __global__ void k_gcr_alpha(const double2* __restrict__ d, const double* __restrict__ nw, int k, int m, int nrhs,
                             const int* __restrict__ active, double2* __restrict__ alpha, double2* __restrict__ neg_alpha) {
@@ -42,25 +30,6 @@ __global__ void k_gcr_backsub(const double2* __restrict__ T, const double2* __re
   }
 }
 
-void gcr_proj(hipStream_t st, const double2* c, const double* nw, int k, int m, int nrhs, double2* a, double2* T) {
-  if (k <= 0) return;
-  hipLaunchKernelGGL(k_gcr_proj, dim3((nrhs * k + 255) / 256), dim3(256), 0, st, c, nw, k, m, nrhs, a, T);
-}
-// From nd[r*3] = {|w_k|^2, Re (w_k, r), Im (w_k, r)}: nw[r*m + k] = |w_k|^2 and alpha as in k_gcr_alpha
-__global__ void k_gcr_alpha_nd(const double* __restrict__ nd, int k, int m, int nrhs, const int* __restrict__ active,
-                               double* __restrict__ nw, double2* __restrict__ alpha, double2* __restrict__ neg_alpha) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  const double n = nd[3 * r];
-  nw[r * m + k] = n;
-  double2 v = (active[r] && n > 0) ? make_double2(nd[3 * r + 1] / n, nd[3 * r + 2] / n) : make_double2(0, 0);
-  alpha[k * nrhs + r] = v;
-  neg_alpha[r] = make_double2(-v.x, -v.y);
-}
-void gcr_alpha_nd(hipStream_t st, const double* nd, int k, int m, int nrhs, const int* active, double* nw, double2* alpha,
-                  double2* neg_alpha) {
-  hipLaunchKernelGGL(k_gcr_alpha_nd, dim3((nrhs + 255) / 256), dim3(256), 0, st, nd, k, m, nrhs, active, nw, alpha, neg_alpha);
-}
 void gcr_alpha(hipStream_t st, const double2* d, const double* nw, int k, int m, int nrhs, const int* active, double2* alpha,
                double2* neg_alpha) {
   hipLaunchKernelGGL(k_gcr_alpha, dim3((nrhs + 255) / 256), dim3(256), 0, st, d, nw, k, m, nrhs, active, alpha, neg_alpha);
@@ -269,11 +238,34 @@ __global__ void k_reduce_width(const double* __restrict__ partial, int nwg, int 
 
 bool fused_mixed_ok(const FieldBatch& x, const FieldBatch& y) { return x.prec == P_BF16 && y.prec == P_F32; }
 
+// k_reduce_width (width 3) with the step length of flexible GCR: from the three sums
+// {|w_k|^2, (w_k, r)} of right-hand side r, nw[r*m + k] = |w_k|^2, alpha[k*nrhs + r] =
+// (w_k, r) / |w_k|^2 for active right-hand sides with a nonzero norm (else 0) and
+// neg_alpha[r] = -alpha
+__global__ void k_reduce_width_alpha(const double* __restrict__ partial, int nwg, GcrStep gs) {
+  __shared__ double v[3];
+  const int r = blockIdx.x;
+  if (threadIdx.x < 3) {
+    double s = 0;
+    for (int w = 0; w < nwg; ++w) s += partial[(size_t(r) * nwg + w) * 3 + threadIdx.x];
+    v[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double n = v[0];
+    gs.nw[r * gs.m + gs.k] = n;
+    const double2 e = (gs.active[r] && n > 0) ? make_double2(v[1] / n, v[2] / n) : make_double2(0, 0);
+    gs.alpha[gs.k * gs.nrhs + r] = e;
+    gs.neg_alpha[r] = make_double2(-e.x, -e.y);
+  }
+}
+
 void reduce_norm_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
-                           double* out3) {
+                           double* out3, const GcrStep* gs) {
   dim3 grid(R.nwg, y.nprop * y.nrhs);
   hipLaunchKernelGGL(k_norm_dot_bf16_f32, grid, dim3(256), 0, st, g, (const uint4*)x.p, (const float4*)y.p, R.partial);
-  hipLaunchKernelGGL(k_reduce_width, dim3(y.nprop * y.nrhs), dim3(64), 0, st, R.partial, R.nwg, 3, out3);
+  if (gs) hipLaunchKernelGGL(k_reduce_width_alpha, dim3(y.nprop * y.nrhs), dim3(64), 0, st, R.partial, R.nwg, *gs);
+  else hipLaunchKernelGGL(k_reduce_width, dim3(y.nprop * y.nrhs), dim3(64), 0, st, R.partial, R.nwg, 3, out3);
 }
 
 void axpy_norm2_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,

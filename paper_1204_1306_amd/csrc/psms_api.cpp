@@ -78,6 +78,7 @@ struct psms_ctx {
   int block_lanes = 0;         // LDS-resident block solver: lanes per site (1, 2; 0 = by grid size)
   int block_eo = 2;            // LDS-resident block solver: 1 even-odd, 0 plain, 2 by launch shape
   int block_eo_lanes = 0;      // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
+  int block_tol_prec = 0;      // mixed block inverses to tolerance: 1 FP32 passes, 2 FP64, 0 = by block size
   // pinned host slots for the lagged convergence check of the GCR iteration
   double* pinned[2] = {nullptr, nullptr};
   size_t pinned_n = 0;
@@ -569,7 +570,6 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
   double* rn2 = dscratch<double>(c, "gcr_rn2", nr);
   double* nw1 = dscratch<double>(c, "gcr_nw1", nr);
   double* NW = dscratch<double>(c, "gcr_NW", size_t(nr) * m);
-  double2* C = dscratch<double2>(c, "gcr_C", size_t(nr) * m);
   double2* A = dscratch<double2>(c, "gcr_A", size_t(nr) * m);
   double2* T = dscratch<double2>(c, "gcr_T", size_t(nr) * m * m);
   double2* ALPHA = dscratch<double2>(c, "gcr_alpha", size_t(nr) * m);
@@ -619,18 +619,18 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
       apply_D(c, L, Zk, Wk);
       {
         ProfScope ps(c, FAM_BLAS, 0);
+        // the scalar steps (projection coefficients, step length) run in the last
+        // pass of the reductions that feed them
+        const GcrStep gs{k, m, nr, active, NW, A, T, ALPHA, NEGA};
         if (k > 0) {
-          reduce_multidot(st, g, W, vstride, k, Wk, R, C);   // C[r*k + j]
-          gcr_proj(st, C, NW, k, m, nr, A, T);
+          reduce_multidot(st, g, W, vstride, k, Wk, R, nullptr, &gs);  // A, T from (W_j, w_k)
           launch_lincomb(st, g, W, vstride, k, A, m, Wk, -1);
         }
         if (same) {  // fused passes: |w_k|^2 with (w_k, r), then r -= alpha w_k with |r|^2
-          reduce_norm_dot(st, g, Wk, r, R, ND);
-          gcr_alpha_nd(st, ND, k, m, nr, active, NW, ALPHA, NEGA);
+          reduce_norm_dot(st, g, Wk, r, R, ND, &gs);
           axpy_norm2(st, g, NEGA, Wk, r, R, rn2);
         } else if (fused_mixed_ok(Wk, r)) {
-          reduce_norm_dot_mixed(st, g, Wk, r, R, ND);
-          gcr_alpha_nd(st, ND, k, m, nr, active, NW, ALPHA, NEGA);
+          reduce_norm_dot_mixed(st, g, Wk, r, R, ND, &gs);
           axpy_norm2_mixed(st, g, NEGA, Wk, r, R, rn2);
         } else {
           reduce_norm2(st, g, Wk, R, nw1);
@@ -1027,7 +1027,8 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
                     int* iters_host, bool mixed = false) {
   const int np = b.nprop, nrb = b.nrhs, nr = np * nrb;
   Links L = links_of(c, slots, np, LK_F64);
-  if (mixed && c->block_solver == 0 && 2 * c->g.Vbh != 256) {
+  const bool passes32 = c->block_tol_prec == 1 || (c->block_tol_prec == 0 && 2 * c->g.Vbh != 256);
+  if (mixed && c->block_solver == 0 && passes32) {
     bool su3 = true;
     for (int i = 0; i < np; ++i) su3 &= c->slots[slots[i]].su3;
     if (su3) return solve_colour_mixed(c, slots, col, b, x, tol, maxit, iters_host);
@@ -2024,11 +2025,12 @@ static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "block_lanes")) return &c->block_lanes;
   if (!std::strcmp(key, "block_eo")) return &c->block_eo;
   if (!std::strcmp(key, "block_eo_lanes")) return &c->block_eo_lanes;
+  if (!std::strcmp(key, "block_tol_prec")) return &c->block_tol_prec;
   return nullptr;
 }
 static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
                                     "xcd_map", "net_mfma", "block_solver", "block_lanes", "block_eo",
-                                    "block_eo_lanes"};
+                                    "block_eo_lanes", "block_tol_prec"};
 
 psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   API_BEGIN(c)
@@ -2042,6 +2044,8 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
   else if (!std::strcmp(key, "block_eo_lanes"))
     REQUIRE(value == 0 || value == 2 || value == 4, "even-odd lanes per site must be 0 (default), 2 or 4");
+  else if (!std::strcmp(key, "block_tol_prec"))
+    REQUIRE(value >= 0 && value <= 2, "block_tol_prec must be 0 (by block size), 1 (FP32 passes) or 2 (FP64)");
   else if (!std::strcmp(key, "block_lanes"))
     REQUIRE(value >= 0 && value <= 2, "lanes per site must be 0 (by grid size), 1 or 2");
   else REQUIRE(value == 1 || value == 2 || value == 4, "right-hand sides per thread must be 1, 2 or 4");
