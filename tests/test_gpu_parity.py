@@ -313,6 +313,14 @@ def test_logdet_ratio_mixed_vs_f64_8x4(psms):
     assert np.all(np.abs(d64[0, :2] - ref[0]) < bound)
     assert np.all(np.abs(dmx[0, :2] - ref[0]) < bound)
     assert np.abs(d64 - dmx).max() < bound.max()
+    # the block inverses to tolerance as FP32 passes inside FP64 defect correction
+    ctx.set_tuning("block_tol_prec", 1)
+    dp, sp = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10, prec=psms.MIXED))
+    ctx.set_tuning("block_tol_prec", 0)
+    say(" dp32", dp.ravel(), sp)
+    assert sp["converged"] == 1
+    assert np.all(np.abs(dp[0, :2] - ref[0]) < bound)
+    assert np.abs(dp - d64).max() < bound.max()
 
 
 def test_split_schwarz_blocks_same_results(psms):
