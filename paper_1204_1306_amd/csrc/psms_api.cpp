@@ -438,10 +438,8 @@ double* pinned_slot(psms_ctx* c, int slot, int n) {
     for (auto& p : c->pinned) HIPCHK(hipHostMalloc((void**)&p, size_t(n) * sizeof(double), hipHostMallocDefault));
     c->pinned_n = n;
   }
-  if (!c->rn_ev[0]) {
-    HIPCHK(hipEventCreateWithFlags(&c->rn_ev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->rn_ev[1], hipEventDisableTiming));
-  }
+  if (!c->rn_ev[0])
+    for (auto& e : c->rn_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return c->pinned[slot];
 }
 
@@ -1058,13 +1056,18 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
   FieldBatch rho = field(c, "bs_rho", P_F64, np, nrb);
   FieldBatch dl = field(c, "bs_delta", P_F64, np, nrb);
   FieldBatch pb = field(c, "bs_p", P_F64, np, nrb);
+  FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
   int* it = dscratch<int>(c, "bs_iters", 1);
+  double* n1 = dscratch<double>(c, "bs_n1", nr);
+  double* n2 = dscratch<double>(c, "bs_n2", nr);
   {
     ProfScope ps(c, FAM_BLAS, 0);
-    launch_copy(c->st, c->g, b, rho, nullptr);
-    launch_keep_colour(c->st, c->g, rho, col);
+    launch_copy(c->st, c->g, b, bc, nullptr);
+    launch_keep_colour(c->st, c->g, bc, col);
+    launch_copy(c->st, c->g, bc, rho, nullptr);
     launch_zero(c->st, x, c->Vh);
   }
+  norm2(c, bc, n2);
   HIPCHK(hipMemsetAsync(it, 0, sizeof(int), c->st));
   {
     ProfScope ps(c, FAM_BLOCK_SOLVE, block_bytes(c, L, rho));
@@ -1075,15 +1078,7 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
     launch_block_mr(c->st, c->g, L.p, L.fmt, rho, x, dl, pb, bp, it);
   }
   if (iters_host) HIPCHK(hipMemcpyAsync(iters_host, it, sizeof(int), hipMemcpyDeviceToHost, c->st));
-  // relative residual |b_c - D_cc x| / |b_c| (rho holds it after the solve)
-  double* n1 = dscratch<double>(c, "bs_n1", nr);
-  double* n2 = dscratch<double>(c, "bs_n2", nr);
-  FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
-  {
-    ProfScope ps(c, FAM_BLAS, 0);
-    launch_copy(c->st, c->g, b, bc, nullptr);
-    launch_keep_colour(c->st, c->g, bc, col);
-  }
+  // true relative residual |b_c - D_cc x| / |b_c|
   FieldBatch rt = field(c, "bs_rt", P_F64, np, nrb);
   dslash(c, L, x, rt, HOP_INTRA, col, 1.0, -c->geom.kappa, 0);
   {
@@ -1092,7 +1087,6 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
     launch_axpby(c->st, c->g, const_cx(c, "one", nr, 1, 0), bc, const_cx(c, "mone", nr, -1, 0), rt, +1);
   }
   norm2(c, rt, n1);
-  norm2(c, bc, n2);
   std::vector<double> h1, h2;
   to_host2(c, n1, nr, h1, n2, nr, h2);
   double mx = 0;
