@@ -162,3 +162,42 @@ def test_c5_one_proposal_batch(psms):
     b = 2 * x2 * w["tol"] * COND
     say(f"  (p=0, j=3): bf16 {d_bf[0, 3]:.10f} f64 {d_64[0, 3]:.10f} certified {ref:.10f} bound {b:.1e}")
     assert abs(d_bf[0, 3] - ref) < b and abs(d_64[0, 3] - ref) < b
+
+
+def test_c4_network_full_size(psms):
+    """16^4 at kappa 0.157 with the 1->8->8->8->1 network: the forward pass in both
+    channel-mixing forms (FP32 vector units, bf16 matrix cores) against the FP64
+    network oracle on the whole lattice, then flexible GCR right-preconditioned by
+    that network (Schwarz fallback allowed) meeting the FP64 true residual that the
+    oracle's operator computes."""
+    from oracle import dirac
+    from oracle import network as net
+
+    w, U, _, _ = synth.workload_inputs("c4", nprop=0, nnoise=0)
+    L, kappa = w["L"], w["kappa"]
+    chans = (1, 8, 8, 8, 1)
+    rng = np.random.default_rng(4601)
+    ws = [0.15 * (rng.standard_normal((9, co, ci, 4, 4)) + 1j * rng.standard_normal((9, co, ci, 4, 4)))
+          for ci, co in zip(chans[:-1], chans[1:])]
+    flat = np.concatenate([x.ravel() for x in ws])
+    r = synth.gaussian_noise(L, 2, 4602)
+    say("case c4 network forward, oracle on the CPU")
+    ref, _ = net.forward(U, ws, r[0], L)
+    ctx = psms.Context(L, w["b"], kappa)
+    ctx.gauge_load(0, U)
+    ctx.net_init(chans)
+    ctx.net_set_weights(flat)
+    for mfma, tol in ((0, 2e-5), (1, 3e-2)):
+        ctx.set_tuning("net_mfma", mfma)
+        out = ctx.net_apply(0, r)
+        err = float(np.linalg.norm((out[0] - ref).ravel()) / np.linalg.norm(ref.ravel()))
+        say(f" mfma {mfma}: relative error {err:.2e}")
+        assert err < tol
+    say("case c4 network-preconditioned solve")
+    x, st = ctx.solve(0, r, psms.default_params(pc=psms.PC_NET, tol=w["tol"], prec=psms.MIXED))
+    say(" stats", st)
+    assert st["converged"] == 1
+    for k in range(r.shape[0]):
+        res = r[k] - dirac.apply_D(U, x[k], kappa, L)
+        assert np.linalg.norm(res) / np.linalg.norm(r[k]) <= 1.01 * w["tol"]
+    ctx.close()
