@@ -11,7 +11,9 @@ from paper_1204_1306_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-GEOMS = [((4, 4, 4, 4), (2, 2, 2, 2)), ((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (4, 2, 2, 2))]
+# the last shape has 384 sites per parity: a ragged tail for 256-site tiles
+GEOMS = [((4, 4, 4, 4), (2, 2, 2, 2)), ((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (4, 2, 2, 2)),
+         ((12, 4, 4, 4), (2, 2, 2, 2))]
 
 
 def say(*a):
@@ -50,7 +52,8 @@ def test_dw_f64_matches_oracle(psms, L, b):
 
 
 @pytest.mark.parametrize("L,b", [((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (4, 2, 2, 2)),
-                                 ((16, 16, 16, 16), (8, 8, 8, 8)), ((8, 16, 16, 16), (4, 8, 8, 8))])
+                                 ((16, 16, 16, 16), (8, 8, 8, 8)), ((8, 16, 16, 16), (4, 8, 8, 8)),
+                                 ((12, 4, 4, 4), (2, 2, 2, 2))])
 def test_dw_every_stencil_form(psms, L, b):
     """Every full-lattice stencil form the autotuner can pick (variants 0..7, one right-hand
     side per thread, three right-hand sides per launch), FP64 against the oracle to 1e-13
