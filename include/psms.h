@@ -247,13 +247,17 @@ psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);
 psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);
 
 /* Autotuner: times every stencil form and right-hand-side blocking on this context's
- * geometry with gauge slot `slot` (HIP events; the mean of repeated launches, best of three
- * interleaved rounds after a warm-up round). Stencil forms are timed on two launch shapes, 16 and 64
- * right-hand sides below 2^20 sites and 1 and 8 from there up; the form kept is the one
- * whose worst slowdown against the fastest form of either shape is smallest. For the
- * right-hand-side blocking the fastest is kept. If cache_path names a JSON-lines file
- * holding an entry for this GPU architecture and geometry, that entry is used instead and
- * nothing is timed; a fresh result is appended to the file. cache_path may be NULL. */
+ * geometry (HIP events; the mean of repeated launches, best of three interleaved rounds
+ * after a warm-up round). Stencil forms are timed on two launch shapes: gauge slot `slot`
+ * with 16 right-hand sides (1 from 2^20 sites up), and every other loaded gauge slot as
+ * the proposals of one launch (up to the proposals one launch addresses, SU(3) slots only
+ * for the reduced-precision forms; `slot` itself when there is no other) with 128
+ * right-hand sides in all (8 from 2^20 sites up). The
+ * form kept is the one whose worst slowdown against the fastest form of either shape is
+ * smallest. For the right-hand-side blocking the fastest is kept. If cache_path names a
+ * JSON-lines file holding an entry for this GPU architecture and geometry, that entry is
+ * used instead and nothing is timed; a fresh result is appended to the file. cache_path
+ * may be NULL. Load the gauge fields before tuning. */
 psms_status psms_autotune(psms_ctx* ctx, int slot, const char* cache_path);
 
 /* Kernel timing with HIP events on the context's stream. enable=1 starts recording

@@ -116,6 +116,12 @@ void reduce_multidot(hipStream_t st, const Geo& g, const FieldBatch& basis, size
 // active right-hand sides with a nonzero norm (else 0), gs->neg_alpha[r] = -alpha.
 void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double* out3,
                      const GcrStep* gs = nullptr);
+// y -= sum_{j<m} c[r*cstride + j] X_j, then gs->nw, gs->alpha and gs->neg_alpha from |y|^2
+// and (y, z) as reduce_norm_dot with gs makes them (x = y, y = z there); y, z and the
+// basis of one storage. The reduction order is that of launch_lincomb followed by
+// reduce_norm_dot.
+void lincomb_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const double2* c, int cstride,
+                      const FieldBatch& y, const FieldBatch& z, const Reducer& R, const GcrStep& gs);
 // y += a[r] x and out[r] = |y|^2 in one pass (x, y of one storage)
 void axpy_norm2(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
                 double* out);

@@ -385,6 +385,69 @@ __global__ void k_norm_dot_p1(const typename Unit<P>::unit* __restrict__ x, cons
     partial[3 * q + 2] = t2;
   }
 }
+// The orthogonalisation of flexible GCR with the pass that follows it: y -= sum_j
+// c[r][j] X_j (as k_lincomb with sign -1), then the partial sums of |y|^2 and (y, z)
+// (conj on y) over the stored y, with the same work split and layout as k_norm_dot_p1,
+// so that the sums equal those of the two passes bit for bit.
+template <Prec P>
+__global__ void k_lincomb_norm_dot(const typename Unit<P>::unit* __restrict__ basis, size_t vstride, int m,
+                                   const double2* __restrict__ c, int cstride, typename Unit<P>::unit* __restrict__ y,
+                                   const typename Unit<P>::unit* __restrict__ z, size_t n, double* __restrict__ partial) {
+  using U = Unit<P>;
+  using T = typename U::T;
+  __shared__ double sm[16];
+  const int r = blockIdx.y;
+  const size_t off = size_t(r) * n;
+  double xx = 0.0, re = 0.0, im = 0.0;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    cx<T> yv[U::N], zv[U::N];
+    cx<double> acc[U::N];
+    U::ld(y[off + i], yv);
+    U::ld(z[off + i], zv);
+#pragma unroll
+    for (int k = 0; k < U::N; ++k) acc[k] = {double(yv[k].re), double(yv[k].im)};
+    for (int j = 0; j < m; ++j) {
+      cx<double> cj = {-c[r * cstride + j].x, -c[r * cstride + j].y};
+      cx<T> xv[U::N];
+      U::ld(basis[j * vstride + off + i], xv);
+#pragma unroll
+      for (int k = 0; k < U::N; ++k) acc[k] = acc[k] + cmul(cj, cx<double>{double(xv[k].re), double(xv[k].im)});
+    }
+#pragma unroll
+    for (int k = 0; k < U::N; ++k) yv[k] = {T(acc[k].re), T(acc[k].im)};
+    typename U::unit u;
+    U::st(u, yv);
+    y[off + i] = u;
+    U::ld(u, yv);  // the stored (rounded) values enter the sums
+#pragma unroll
+    for (int e = 0; e < U::N; ++e) {
+      const double xr = yv[e].re, xi = yv[e].im, yr = zv[e].re, yi = zv[e].im;
+      xx += xr * xr + xi * xi;
+      re += xr * yr + xi * yi;
+      im += xr * yi - xi * yr;
+    }
+  }
+  const double t0 = block_sum(xx, sm), t1 = block_sum(re, sm), t2 = block_sum(im, sm);
+  if (threadIdx.x == 0) {
+    const size_t q = size_t(r) * gridDim.x + blockIdx.x;
+    partial[3 * q] = t0;
+    partial[3 * q + 1] = t1;
+    partial[3 * q + 2] = t2;
+  }
+}
+template <Prec P> static void lincomb_norm_dot_go(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m,
+                                                  const double2* c, int cstride, const FieldBatch& y, const FieldBatch& z,
+                                                  const Reducer& R, const GcrStep& gs) {
+  size_t n = units_per_field(P, g.Vh);
+  hipLaunchKernelGGL(k_lincomb_norm_dot<P>, dim3(R.nwg, nrhs_of(y)), dim3(256), 0, st, (const typename Unit<P>::unit*)basis.p,
+                     vstride, m, c, cstride, (typename Unit<P>::unit*)y.p, (const typename Unit<P>::unit*)z.p, n, R.partial);
+  hipLaunchKernelGGL(k_reduce_final_alpha, dim3(nrhs_of(y)), dim3(256), 0, st, R.partial, R.nwg, gs);
+}
+void lincomb_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const double2* c, int cstride,
+                      const FieldBatch& y, const FieldBatch& z, const Reducer& R, const GcrStep& gs) {
+  DISPATCH_PREC(y.prec, lincomb_norm_dot_go, st, g, basis, vstride, m, c, cstride, y, z, R, gs);
+}
+
 template <Prec P> static void norm_dot_go(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
                                           double* out3, const GcrStep* gs) {
   size_t n = units_per_field(P, g.Vh);

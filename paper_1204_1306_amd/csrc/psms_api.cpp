@@ -632,23 +632,26 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
         // the scalar steps (projection coefficients, step length) run in the last
         // pass of the reductions that feed them
         const GcrStep gs{k, m, nr, active, NW, A, T, ALPHA, NEGA};
-        if (k > 0) {
-          reduce_multidot(st, g, W, vstride, k, Wk, R, nullptr, &gs);  // A, T from (W_j, w_k)
-          launch_lincomb(st, g, W, vstride, k, A, m, Wk, -1);
-        }
-        if (same) {  // fused passes: |w_k|^2 with (w_k, r), then r -= alpha w_k with |r|^2
-          reduce_norm_dot(st, g, Wk, r, R, ND, &gs);
+        if (k > 0) reduce_multidot(st, g, W, vstride, k, Wk, R, nullptr, &gs);  // A, T from (W_j, w_k)
+        if (same) {
+          // fused passes: the orthogonalisation of w_k with |w_k|^2 and (w_k, r), then
+          // r -= alpha w_k with |r|^2
+          if (k > 0) lincomb_norm_dot(st, g, W, vstride, k, A, m, Wk, r, R, gs);
+          else reduce_norm_dot(st, g, Wk, r, R, ND, &gs);
           axpy_norm2(st, g, NEGA, Wk, r, R, rn2);
-        } else if (fused_mixed_ok(Wk, r)) {
-          reduce_norm_dot_mixed(st, g, Wk, r, R, ND, &gs);
-          axpy_norm2_mixed(st, g, NEGA, Wk, r, R, rn2);
         } else {
-          reduce_norm2(st, g, Wk, R, nw1);
-          scatter_col(st, nw1, k, m, nr, NW);
-          reduce_dot_mixed(st, g, Wk, r, R, D1);
-          gcr_alpha(st, D1, NW, k, m, nr, active, ALPHA, NEGA);
-          launch_axpy_mixed(st, g, NEGA, Wk, r, +1);
-          reduce_norm2(st, g, r, R, rn2);
+          if (k > 0) launch_lincomb(st, g, W, vstride, k, A, m, Wk, -1);
+          if (fused_mixed_ok(Wk, r)) {
+            reduce_norm_dot_mixed(st, g, Wk, r, R, ND, &gs);
+            axpy_norm2_mixed(st, g, NEGA, Wk, r, R, rn2);
+          } else {
+            reduce_norm2(st, g, Wk, R, nw1);
+            scatter_col(st, nw1, k, m, nr, NW);
+            reduce_dot_mixed(st, g, Wk, r, R, D1);
+            gcr_alpha(st, D1, NW, k, m, nr, active, ALPHA, NEGA);
+            launch_axpy_mixed(st, g, NEGA, Wk, r, +1);
+            reduce_norm2(st, g, r, R, rn2);
+          }
         }
       }
       // Residual norms go to pinned host memory behind an event; the check of
@@ -2117,21 +2120,31 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
   const bool prof = c->prof;
   c->prof = false;
   const int reps = c->V >= (1 << 20) ? 10 : 30;
-  // Stencil forms are timed on two launch shapes the solvers make (right-hand sides per
-  // launch: 16 and 64 below 2^20 sites, where one right-hand side is dominated by launch
-  // latency; 1 and 8 from there up). After a warm-up round, each form keeps its best time
-  // over three interleaved rounds, so that clock changes during tuning favour no form. The pick is
+  // Stencil forms are timed on two launch shapes the solvers make: one gauge field with
+  // 16 right-hand sides (1 from 2^20 sites up, where one right-hand side is not bound by
+  // launch latency), and the other loaded gauge fields as the proposals of one launch
+  // (as the batched estimator launches them) with 128 right-hand sides in all (8 from
+  // 2^20 sites up). After a warm-up round, each form keeps its best time over three
+  // interleaved rounds, so that clock changes during tuning favour no form. The pick is
   // the form whose worst slowdown against the fastest form of a shape is smallest: a form
   // that is fast on one shape and slow on the other loses to one that is good on both.
-  const int shapes[2] = {c->V >= (1 << 20) ? 1 : 16, c->V >= (1 << 20) ? 8 : 64};
+  const bool big = c->V >= (1 << 20);
   for (int pr = 0; pr < 3; ++pr) {
     Prec P = Prec(pr);
     if (P != P_F64 && !c->slots[slot].su3) continue;
-    Links L = links_of(c, &slot, 1, P == P_F64 ? LK_F64 : LK_F32C12);
+    // the proposals: every other loaded slot (the slot itself when there is none)
+    std::vector<int> props;
+    for (int i = 0; i < 64 && int(props.size()) < MAXPROP; ++i)
+      if (i != slot && c->slots[i].loaded && (P == P_F64 || c->slots[i].su3)) props.push_back(i);
+    if (props.empty()) props.push_back(slot);
+    const int fmt = P == P_F64 ? LK_F64 : LK_F32C12;
     double tv[8][2];
     for (auto& row : tv) row[0] = row[1] = 1e30;
     for (int si = 0; si < 2; ++si) {
-      FieldBatch in = field(c, "tune_in", P, 1, shapes[si]), out = field(c, "tune_out", P, 1, shapes[si]);
+      const int np = si == 0 ? 1 : int(props.size());
+      const int nrhs = si == 0 ? (big ? 1 : 16) : std::max(1, (big ? 8 : 128) / np);
+      Links L = links_of(c, si == 0 ? &slot : props.data(), np, fmt);
+      FieldBatch in = field(c, "tune_in", P, np, nrhs), out = field(c, "tune_out", P, np, nrhs);
       launch_zero(c->st, in, c->Vh);
       const int r = si == 0 ? reps : std::max(3, reps / 4);
       for (int round = 0; round < 4; ++round)  // round 0 only warms up (clocks, first launches)
