@@ -409,6 +409,24 @@ def main():
     s_plain = dtp / args.plain_steps / nest
     log(f"plain f64: {1e3 * dtp / args.plain_steps:.2f} ms/step, solver {stp[-1]}")
 
+    # the same mixed step with the noise and Delta in (pageable) host memory: the library
+    # stages the noise over PCIe and returns Delta to the host in every call
+    host_buffers = None
+    try:
+        noise_h = noise.cpu().numpy()
+        delta_h = np.empty((nprop, nest // nprop), np.float64)
+        slots = list(range(1, 1 + nprop))
+        ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise_h, fast, delta=delta_h)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise_h, fast, delta=delta_h)
+        dth = time.perf_counter() - t0
+        host_buffers = {"s_per_estimate": dth / args.steps / nest, "ms_per_step": 1e3 * dth / args.steps,
+                        "max_abs_delta_diff": float(np.abs(delta_h - d_fast).max())}
+        log(f"host buffers: {host_buffers}")
+    except Exception as e:  # reported, not hidden
+        host_buffers = {"error": repr(e)}
+
     learned = None
     if not args.no_learned:
         try:
@@ -474,6 +492,8 @@ def main():
         "plain_f64_s_per_estimate": s_plain,
         "speedup_vs_plain_f64": s_plain / value,
         "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
+        # PCIe-inclusive: the same step with the noise and Delta in pageable host memory
+        "host_buffers": host_buffers,
         # ln mean_j exp(-Delta_pj) per proposal, from the same noise in both modes
         "log_ratio_estimate": {"fast": [round(float(v), 10) for v in psms.log_ratio_estimate(d_fast)],
                                "plain": [round(float(v), 10) for v in psms.log_ratio_estimate(d_plain)]},

@@ -2129,6 +2129,14 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
   // the form whose worst slowdown against the fastest form of a shape is smallest: a form
   // that is fast on one shape and slow on the other loses to one that is good on both.
   const bool big = c->V >= (1 << 20);
+  // Gaussian inputs (zeros draw less power, which can change clocks and so the ranking)
+  auto fill = [&](const FieldBatch& in) {
+    const size_t fd = size_t(c->V) * 24;
+    const int nf = in.nprop * in.nrhs;
+    double* raw = dscratch<double>(c, "tune_raw", fd * nf);
+    launch_gaussian(c->st, raw, fd / 2, nf, 0x74756e65ULL, 0);
+    launch_pack(c->st, c->g, raw, in);
+  };
   for (int pr = 0; pr < 3; ++pr) {
     Prec P = Prec(pr);
     if (P != P_F64 && !c->slots[slot].su3) continue;
@@ -2145,7 +2153,7 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
       const int nrhs = si == 0 ? (big ? 1 : 16) : std::max(1, (big ? 8 : 128) / np);
       Links L = links_of(c, si == 0 ? &slot : props.data(), np, fmt);
       FieldBatch in = field(c, "tune_in", P, np, nrhs), out = field(c, "tune_out", P, np, nrhs);
-      launch_zero(c->st, in, c->Vh);
+      fill(in);
       const int r = si == 0 ? reps : std::max(3, reps / 4);
       for (int round = 0; round < 4; ++round)  // round 0 only warms up (clocks, first launches)
         for (int v = 0; v <= 7; ++v) {
@@ -2174,7 +2182,7 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     if (P != P_F64 && !c->slots[slot].su3) continue;
     Links L = links_of(c, &slot, 1, P == P_F64 ? LK_F64 : LK_F32C12);
     FieldBatch in = field(c, "tune_in", P, 1, 8), out = field(c, "tune_out", P, 1, 8);
-    launch_zero(c->st, in, c->Vh);
+    fill(in);
     int* nr = pr == 0 ? &c->nr_f64 : &c->nr_low;
     double tn[3] = {1e30, 1e30, 1e30};
     const int cands[3] = {1, 2, 4};
@@ -2190,6 +2198,7 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
   }
   drop_buf(c, "tune_in");
   drop_buf(c, "tune_out");
+  drop_buf(c, "tune_raw");
   c->prof = prof;
   c->tuned_from = "autotune";
   if (cache_path) {
