@@ -276,9 +276,11 @@ def batched_leg(psms, workload: str, steps: int, rhs_chunk: int):
     import torch
 
     _, ctx, w, noise, delta, nprop = setup(workload)
-    ctx.autotune(0, None)
+    tune = ctx.autotune(0, None)
     nest = nprop * noise.shape[0]
-    out = {"workload": workload, "estimates_per_step": nest, "rhs_chunk": rhs_chunk}
+    out = {"workload": workload, "estimates_per_step": nest, "rhs_chunk": rhs_chunk,
+           "tuning": {k: tune[k] for k in ("dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64",
+                                            "nr_low")}}
     d = {}
     for mode in ("mixed_bf16", "plain"):
         prm = mode_params(psms, mode, w["tol"], workload)

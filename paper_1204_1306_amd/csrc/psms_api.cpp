@@ -2146,13 +2146,17 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
       if (i != slot && c->slots[i].loaded && (P == P_F64 || c->slots[i].su3)) props.push_back(i);
     if (props.empty()) props.push_back(slot);
     const int fmt = P == P_F64 ? LK_F64 : LK_F32C12;
-    double tv[8][2];
-    for (auto& row : tv) row[0] = row[1] = 1e30;
-    for (int si = 0; si < 2; ++si) {
+    // BF16 inputs also meet FP32 outputs (a different kernel under the same form number):
+    // a third measurement, the batched shape into FP32
+    const int nsh = P == P_BF16 ? 3 : 2;
+    double tv[8][3];
+    for (auto& row : tv) row[0] = row[1] = row[2] = 1e30;
+    for (int si = 0; si < nsh; ++si) {
       const int np = si == 0 ? 1 : int(props.size());
       const int nrhs = si == 0 ? (big ? 1 : 16) : std::max(1, (big ? 8 : 128) / np);
       Links L = links_of(c, si == 0 ? &slot : props.data(), np, fmt);
-      FieldBatch in = field(c, "tune_in", P, np, nrhs), out = field(c, "tune_out", P, np, nrhs);
+      FieldBatch in = field(c, "tune_in", P, np, nrhs);
+      FieldBatch out = field(c, "tune_out", si == 2 ? P_F32 : P, np, nrhs);
       fill(in);
       const int r = si == 0 ? reps : std::max(3, reps / 4);
       for (int round = 0; round < 4; ++round)  // round 0 only warms up (clocks, first launches)
@@ -2162,13 +2166,14 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
           if (round > 0) tv[v][si] = std::min(tv[v][si], t);
         }
     }
-    double fastest[2] = {1e30, 1e30};
+    double fastest[3] = {1e30, 1e30, 1e30};
     for (int v = 0; v <= 7; ++v)
-      for (int si = 0; si < 2; ++si) fastest[si] = std::min(fastest[si], tv[v][si]);
+      for (int si = 0; si < nsh; ++si) fastest[si] = std::min(fastest[si], tv[v][si]);
     int best = 0;
     double worst_best = 1e30;
     for (int v = 0; v <= 7; ++v) {
-      const double worst = std::max(tv[v][0] / fastest[0], tv[v][1] / fastest[1]);
+      double worst = 0;
+      for (int si = 0; si < nsh; ++si) worst = std::max(worst, tv[v][si] / fastest[si]);
       if (worst < worst_best) {
         worst_best = worst;
         best = v;
