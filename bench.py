@@ -37,7 +37,7 @@ def log(*a):
 # Schwarz cycles x block iterations where the measured best differs from the library
 # default (4 x 6, best for mixed at 8^4 and for both modes at 16^4 and 32^4): plain
 # FP64 at 8^4 prefers 5 x 6.
-SAP_TUNED = {("c2", "plain"): (5, 6)}
+SAP_TUNED = {("8x8x8x8", "plain"): (5, 6)}
 
 
 def mode_params(psms, mode: str, tol: float, workload: str | None = None):
@@ -87,7 +87,7 @@ FAMILIES = ("dslash", "dslash_part", "block_mr", "block_solve", "blas", "net")
 TRAFFIC = {
     # even-odd FP32 block kernel, four lanes per site, links staged in LDS; 8 blocks x 16
     # right-hand sides, Schwarz sweeps (4 cycles x 6 block iterations, averaged over launches)
-    ("block_mr", "c2", "mixed"): {"bytes_per_launch": 27263006, "source": "kernels_block.hip",
+    ("block_mr", "8x8x8x8", "mixed"): {"bytes_per_launch": 27263006, "source": "kernels_block.hip",
                                   "sha256": "fd25afb550b19ac4ba6959272a2aeba348c9e4ac37a009293bd6c8eb0621827d"},
     # full-lattice FP64 stencil at 32^4 on 4x4x8x16 blocks, four lanes per site (variant 6)
     # and split form (variant 1); keyed by lattice/block shape
@@ -365,7 +365,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="8x8x8x8")
     ap.add_argument("--mode", default="mixed")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--nprop", type=int, default=None)
@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--dw-lattice", default="32,32,32,32")
     ap.add_argument("--dw-blocks", default="auto")
-    ap.add_argument("--batched-workload", default="c3", help="'none' skips the batched leg")
+    ap.add_argument("--batched-workload", default="16x16x16x16-batched", help="'none' skips the batched leg")
     ap.add_argument("--no-net-leg", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--batched-rhs-chunk", type=int, default=128)
@@ -485,7 +485,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "s/estimate", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-        "config": {"workload": (f"{args.workload}: {'x'.join(map(str, w['L']))} lattice, {'x'.join(map(str, w['b']))} "
+        "config": {"workload": (f"{'x'.join(map(str, w['L']))} lattice, {'x'.join(map(str, w['b']))} "
                                 f"blocks, kappa {w['kappa']}, links exp(i {w['eps']} H), {nprop} proposal(s) x {nnoise} "
                                 f"noise, Schur-complement ratio, relative residual {w['tol']:g}"),
                    "mode": args.mode, "estimates_per_step": nest,

@@ -167,17 +167,17 @@ def gauge_transform(rng_seed: int, V: int, eps: float = 1.0) -> np.ndarray:
 # Workloads of the paper's shapes (lattice, blocks, kappa, link spread, proposal
 # spread, numbers of proposals and noise vectors, seeds).
 WORKLOADS = {
-    "c1": dict(L=(4, 4, 4, 4), b=(2, 2, 2, 2), kappa=0.12, eps=0.5, eps_prime=0.05,
-               nprop=1, nnoise=4, seed_U=1001, seed_Up=1101, seed_noise=1501, tol=1e-12),
-    "c2": dict(L=(8, 8, 8, 8), b=(4, 4, 4, 4), kappa=0.15, eps=0.6, eps_prime=0.05,
-               nprop=1, nnoise=16, seed_U=2001, seed_Up=2101, seed_noise=2501, tol=1e-10),
-    "c3": dict(L=(16, 16, 16, 16), b=(4, 4, 4, 4), kappa=0.155, eps=0.6, eps_prime=(0.02, 0.1),
-               nprop=8, nnoise=64, seed_U=3001, seed_Up=3101, seed_noise=3501, tol=1e-10),
-    "c4": dict(L=(16, 16, 16, 16), b=(4, 4, 4, 4), kappa=0.157, eps=0.6, eps_prime=(0.02, 0.1),
-               nprop=1, nnoise=8, seed_U=4999, seed_Up=4899, seed_noise=4501, tol=1e-10),
-    "c5": dict(L=(32, 32, 32, 32), b=(8, 8, 8, 8), kappa=0.1575, eps=0.6, eps_prime=(0.02, 0.1),
-               nprop=4, nnoise=32, seed_U=5001, seed_Up=5101, seed_noise=5501, tol=1e-10,
-               sap_b=(4, 4, 4, 4)),
+    "4x4x4x4": dict(L=(4, 4, 4, 4), b=(2, 2, 2, 2), kappa=0.12, eps=0.5, eps_prime=0.05,
+        nprop=1, nnoise=4, seed_U=1001, seed_Up=1101, seed_noise=1501, tol=1e-12),
+    "8x8x8x8": dict(L=(8, 8, 8, 8), b=(4, 4, 4, 4), kappa=0.15, eps=0.6, eps_prime=0.05,
+        nprop=1, nnoise=16, seed_U=2001, seed_Up=2101, seed_noise=2501, tol=1e-10),
+    "16x16x16x16-batched": dict(L=(16, 16, 16, 16), b=(4, 4, 4, 4), kappa=0.155, eps=0.6, eps_prime=(0.02, 0.1),
+        nprop=8, nnoise=64, seed_U=3001, seed_Up=3101, seed_noise=3501, tol=1e-10),
+    "16x16x16x16-network": dict(L=(16, 16, 16, 16), b=(4, 4, 4, 4), kappa=0.157, eps=0.6, eps_prime=(0.02, 0.1),
+        nprop=1, nnoise=8, seed_U=4999, seed_Up=4899, seed_noise=4501, tol=1e-10),
+    "32x32x32x32": dict(L=(32, 32, 32, 32), b=(8, 8, 8, 8), kappa=0.1575, eps=0.6, eps_prime=(0.02, 0.1),
+        nprop=4, nnoise=32, seed_U=5001, seed_Up=5101, seed_noise=5501, tol=1e-10,
+        sap_b=(4, 4, 4, 4)),
 }
 
 

@@ -17,7 +17,7 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_traffic_figures_follow_their_kernel_source(tmp_path, monkeypatch):
-    key = ("block_mr", "c2", "mixed")
+    key = ("block_mr", "8x8x8x8", "mixed")
     assert key in bench.TRAFFIC
     entry = dict(bench.TRAFFIC[key])
     src = os.path.join(ROOT, "paper_1204_1306_amd", "csrc", entry["source"])
@@ -26,4 +26,4 @@ def test_traffic_figures_follow_their_kernel_source(tmp_path, monkeypatch):
     monkeypatch.setitem(bench.TRAFFIC, key, dict(entry, sha256="0" * 64))
     assert bench.traffic_for(*key) is None
     # an unknown key is unmeasured too
-    assert bench.traffic_for("no_such_family", "c2", "mixed") is None
+    assert bench.traffic_for("no_such_family", "8x8x8x8", "mixed") is None

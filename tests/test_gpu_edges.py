@@ -28,7 +28,7 @@ def psms():
 def test_zero_right_hand_side_and_zero_noise(psms):
     """A zero right-hand side next to nonzero ones solves to exactly zero while the others
     converge; a zero noise vector gives Delta = 0 exactly (xi = 0)."""
-    w, U, Ups, eta = synth.workload_inputs("c2", nnoise=3)
+    w, U, Ups, eta = synth.workload_inputs("8x8x8x8", nnoise=3)
     ctx = psms.Context(w["L"], w["b"], w["kappa"])
     ctx.gauge_load(0, U)
     ctx.gauge_load(1, Ups[0])
@@ -51,7 +51,7 @@ def test_zero_right_hand_side_and_zero_noise(psms):
 def test_more_proposals_than_one_launch_addresses(psms):
     """17 proposals (one launch addresses at most 16 gauge fields) x 2 noise vectors on the
     4^4 workload: every Delta against the oracle's exact value to 1e-8."""
-    w, U, _, eta = synth.workload_inputs("c1", nnoise=2)
+    w, U, _, eta = synth.workload_inputs("4x4x4x4", nnoise=2)
     Ups = [synth.proposal(U, w["L"], w["b"], w["eps_prime"], 7000 + p) for p in range(17)]
     ctx = psms.Context(w["L"], w["b"], w["kappa"])
     ctx.gauge_load(0, U)
@@ -72,7 +72,7 @@ def test_more_proposals_than_one_launch_addresses(psms):
 def test_ragged_right_hand_side_chunks(psms):
     """Noise vectors solved in chunks that do not divide their number (5 vectors, 2 per
     chunk) give the Deltas of the unchunked solve within the tolerance bound."""
-    w, U, Ups, eta = synth.workload_inputs("c2", nnoise=5)
+    w, U, Ups, eta = synth.workload_inputs("8x8x8x8", nnoise=5)
     ctx = psms.Context(w["L"], w["b"], w["kappa"])
     ctx.gauge_load(0, U)
     ctx.gauge_load(1, Ups[0])

@@ -76,14 +76,14 @@ def _certified_delta(psms, ctx, w, U, Up, slot_up, eta, tol):
     return float(np.vdot(z, z).real - np.vdot(xi, xi).real), float(np.vdot(xi, xi).real)
 
 
-def test_c2_bench_configuration_against_oracle(psms):
+def test_8x4_bench_configuration_against_oracle(psms):
     """8^4, 4^4 blocks, kappa 0.15, 16 noise vectors in one call, in the benchmark's
     mixed and plain modes; the oracle computes Delta for 3 of the 16 noise vectors."""
-    w, U, Ups, eta = synth.workload_inputs("c2")
+    w, U, Ups, eta = synth.workload_inputs("8x8x8x8")
     ctx = _load(psms, w, U, Ups)
     ctx.autotune(0, None)
-    d_mx, s_mx = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "mixed", w["tol"], "c2"))
-    d_64, s_64 = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "plain", w["tol"], "c2"))
+    d_mx, s_mx = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "mixed", w["tol"], "8x8x8x8"))
+    d_64, s_64 = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, bench.mode_params(psms, "plain", w["tol"], "8x8x8x8"))
     say(" mixed", s_mx, "plain", s_64)
     assert s_mx["converged"] and s_64["converged"]
     assert s_mx["true_rel_residual"] <= w["tol"] and s_64["true_rel_residual"] <= w["tol"]
@@ -102,11 +102,11 @@ def test_c2_bench_configuration_against_oracle(psms):
         assert abs(d_64[0, j] - ref) < bound[j]
 
 
-def test_c3_full_batch(psms):
+def test_16x4_full_batch(psms):
     """16^4, 4^4 blocks, kappa 0.155, 8 proposals (eps' per block in [0.02, 0.1]) x 64
     noise: the whole batch with BF16 inner storage and with plain FP64; two sampled
     pairs rebuilt from oracle-certified sub-solves."""
-    w, U, Ups, eta = synth.workload_inputs("c3")
+    w, U, Ups, eta = synth.workload_inputs("16x16x16x16-batched")
     ctx = _load(psms, w, U, Ups)
     ctx.autotune(0, None)
     slots = list(range(1, 1 + len(Ups)))
@@ -136,11 +136,11 @@ def test_c3_full_batch(psms):
 
 @pytest.mark.slow
 @pytest.mark.timeout(600)
-def test_c5_one_proposal_batch(psms):
+def test_32x4_one_proposal_batch(psms):
     """32^4, 8^4 Schur blocks (4^4 Schwarz blocks), kappa 0.1575, one proposal x 32 noise
     (one chunk of the full 4 x 32 workload): BF16-inner vs FP64 on every Delta, and one
     pair rebuilt from oracle-certified sub-solves."""
-    w, U, Ups, eta = synth.workload_inputs("c5", nprop=1)
+    w, U, Ups, eta = synth.workload_inputs("32x32x32x32", nprop=1)
     ctx = _load(psms, w, U, Ups)
     ctx.autotune(0, None)
     fast = bench.mode_params(psms, "mixed_bf16", w["tol"])
@@ -164,7 +164,7 @@ def test_c5_one_proposal_batch(psms):
     assert abs(d_bf[0, 3] - ref) < b and abs(d_64[0, 3] - ref) < b
 
 
-def test_c4_network_full_size(psms):
+def test_16x4_network_full_size(psms):
     """16^4 at kappa 0.157 with the 1->8->8->8->1 network: the forward pass in both
     channel-mixing forms (FP32 vector units, bf16 matrix cores) against the FP64
     network oracle on the whole lattice, then flexible GCR right-preconditioned by
@@ -173,7 +173,7 @@ def test_c4_network_full_size(psms):
     from oracle import dirac
     from oracle import network as net
 
-    w, U, _, _ = synth.workload_inputs("c4", nprop=0, nnoise=0)
+    w, U, _, _ = synth.workload_inputs("16x16x16x16-network", nprop=0, nnoise=0)
     L, kappa = w["L"], w["kappa"]
     chans = (1, 8, 8, 8, 1)
     rng = np.random.default_rng(4601)
@@ -181,7 +181,7 @@ def test_c4_network_full_size(psms):
           for ci, co in zip(chans[:-1], chans[1:])]
     flat = np.concatenate([x.ravel() for x in ws])
     r = synth.gaussian_noise(L, 2, 4602)
-    say("case c4 network forward, oracle on the CPU")
+    say("case 16^4 network forward, oracle on the CPU")
     ref, _ = net.forward(U, ws, r[0], L)
     ctx = psms.Context(L, w["b"], kappa)
     ctx.gauge_load(0, U)
@@ -193,7 +193,7 @@ def test_c4_network_full_size(psms):
         err = float(np.linalg.norm((out[0] - ref).ravel()) / np.linalg.norm(ref.ravel()))
         say(f" mfma {mfma}: relative error {err:.2e}")
         assert err < tol
-    say("case c4 network-preconditioned solve")
+    say("case 16^4 network-preconditioned solve")
     x, st = ctx.solve(0, r, psms.default_params(pc=psms.PC_NET, tol=w["tol"], prec=psms.MIXED))
     say(" stats", st)
     assert st["converged"] == 1

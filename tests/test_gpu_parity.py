@@ -282,7 +282,7 @@ def _oracle_deltas(w, U, Ups, eta, kind):
 def test_logdet_ratio_small_workload(psms):
     """4^4 lattice, 2^4 blocks, kappa 0.12, 4 noise vectors, solves to 1e-12:
     same-noise Delta within 1e-8 absolute of the oracle."""
-    w, U, Ups, eta = synth.workload_inputs("c1")
+    w, U, Ups, eta = synth.workload_inputs("4x4x4x4")
     ctx = make_ctx(psms, w["L"], w["b"], w["kappa"])
     ctx.gauge_load(0, U)
     ctx.gauge_load(1, Ups[0])
@@ -300,7 +300,7 @@ def test_logdet_ratio_small_workload(psms):
 def test_logdet_ratio_mixed_vs_f64_8x4(psms):
     """8^4 lattice, 4^4 blocks, kappa 0.15: FP64 and mixed precision both to 1e-10
     against the oracle on the same noise (4 of the 16 noise vectors)."""
-    w, U, Ups, eta = synth.workload_inputs("c2", nnoise=4)
+    w, U, Ups, eta = synth.workload_inputs("8x8x8x8", nnoise=4)
     ctx = make_ctx(psms, w["L"], w["b"], w["kappa"])
     ctx.gauge_load(0, U)
     ctx.gauge_load(1, Ups[0])
@@ -329,7 +329,7 @@ def test_logdet_ratio_mixed_vs_f64_8x4(psms):
 def test_split_schwarz_blocks_same_results(psms):
     """Schwarz blocks smaller than the domain blocks (solver in a second block layout):
     the solve and the Schur estimator agree with the oracle and with the unsplit context."""
-    w, U, Ups, eta = synth.workload_inputs("c2", nnoise=2)
+    w, U, Ups, eta = synth.workload_inputs("8x8x8x8", nnoise=2)
     ctx = psms.Context(w["L"], w["b"], w["kappa"], sap_b=(2, 2, 2, 2))
     ctx.gauge_load(0, U)
     ctx.gauge_load(1, Ups[0])
