@@ -1,5 +1,5 @@
 """GPU edge cases of the estimator path: zero fields, more proposals than one launch
-addresses, ragged right-hand-side chunks. Oracle comparisons on the 4^4 workload,
+addresses, ragged right-hand-side chunks; the autotuner's cache file. Oracle comparisons on the 4^4 workload,
 whose Deltas the oracle computes exactly by dense LU."""
 import sys
 
@@ -84,3 +84,41 @@ def test_ragged_right_hand_side_chunks(psms):
     g = schur.Geometry(w["L"], w["b"])
     xi2 = np.array([np.vdot(g.project(e), g.project(e)).real for e in eta])
     assert np.all(np.abs(full[0] - chunked[0]) < 2 * xi2 * 1e-10 * 50)
+
+
+def test_autotune_cache_round_trip(psms, tmp_path):
+    """psms_autotune with a cache file: a timed run appends one entry for this device and
+    geometry; a second context on the same geometry then takes the last entry for that key
+    (here one edited to values the timing would not all pick) without timing, and the
+    operator still matches the oracle under those values."""
+    import json
+    import time
+
+    w, U, _, _ = synth.workload_inputs("8x8x8x8", nprop=0, nnoise=0)
+    path = str(tmp_path / "tune.jsonl")
+    ctx = psms.Context(w["L"], w["b"], w["kappa"])
+    ctx.gauge_load(0, U)
+    first = ctx.autotune(0, path)
+    ctx.close()
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1
+    entry = json.loads(lines[0])
+    for k in psms.Context.TUNING_KEYS:
+        assert entry[k] == first[k], k
+    edited = dict(entry, dslash_variant_f64=3, nr_low=4)
+    with open(path, "a") as f:
+        f.write(json.dumps(edited) + "\n")
+    ctx = psms.Context(w["L"], w["b"], w["kappa"])
+    ctx.gauge_load(0, U)
+    t0 = time.perf_counter()
+    got = ctx.autotune(0, path)
+    dt = time.perf_counter() - t0
+    say(" cached tuning", got, f"in {dt * 1e3:.1f} ms")
+    assert got["dslash_variant_f64"] == 3 and got["nr_low"] == 4
+    assert len(open(path).read().splitlines()) == 2  # read, nothing appended
+    psi = synth.gaussian_noise(w["L"], 2, 77)
+    out = ctx.apply_dw(0, psi)
+    for k in range(2):
+        ref = dirac.apply_D(U, psi[k], w["kappa"], w["L"])
+        assert np.linalg.norm(out[k] - ref) / np.linalg.norm(ref) < 1e-13
+    ctx.close()
