@@ -87,13 +87,13 @@ FAMILIES = ("dslash", "dslash_part", "block_mr", "block_solve", "blas", "net")
 TRAFFIC = {
     # even-odd FP32 block kernel, four lanes per site, links staged in LDS; 8 blocks x 16
     # right-hand sides, Schwarz sweeps (4 cycles x 6 block iterations, averaged over launches)
-    ("block_mr", "8x8x8x8", "mixed"): {"bytes_per_launch": 27263006, "source": "kernels_block.hip",
-                                  "sha256": "fd25afb550b19ac4ba6959272a2aeba348c9e4ac37a009293bd6c8eb0621827d"},
+    ("block_mr", "8x8x8x8", "mixed"): {"bytes_per_launch": 27262877, "source": "kernels_block.hip",
+                                  "sha256": "3d1ecb116bacd732d136ac32d3a26135b09d40adacb7f9b296ca9c1871b2326e"},
     # full-lattice FP64 stencil at 32^4 on 4x4x8x16 blocks, four lanes per site (variant 6)
     # and split form (variant 1); keyed by lattice/block shape
-    ("dslash_f64_v6", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1344825603, "source": "kernels_dirac.hip",
+    ("dslash_f64_v6", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1344951765, "source": "kernels_dirac.hip",
                                               "sha256": "32ebb8c2ff28342c88e02bd90d75fecdc897061fa4ce60d96888daf6719d5d8f"},
-    ("dslash_f64_v1", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1322715868, "source": "kernels_dirac.hip",
+    ("dslash_f64_v1", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1322713898, "source": "kernels_dirac.hip",
                                               "sha256": "32ebb8c2ff28342c88e02bd90d75fecdc897061fa4ce60d96888daf6719d5d8f"},
 }
 

@@ -991,6 +991,11 @@ __global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
   zero(xv);
   if (h == 0) S::load(rin + size_t(fp) * S::NC * Vh, Vh, s, acc);
   else if (!a.x_assign) S::load(x + size_t(fp) * S::NC * Vh, Vh, s, xv);
+  // the site tables head the chain of dependent reads of the face update: read them
+  // before the link staging so that their latency overlaps it
+  SiteInfo so, se;
+  site_info(g, 1, s, so);
+  site_info(g, 0, s, se);
   if constexpr (LL) {  // link (parity gp, site q, mu) -> planes mu * 5 + e, kappa U
     for (int i = t; i < 4 * 2 * H; i += NT) {
       const int mu = i / (2 * H), xq = i - mu * 2 * H, gp = xq / H;
@@ -1009,9 +1014,6 @@ __global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
   // in-block neighbours of this lane's hops: nA for the odd site j, nB for the even
   // site j (-1 when the hop leaves the block); gA, gB their indices in the field
   int nA[4], nB[4], gA[4], gB[4];
-  SiteInfo so, se;
-  site_info(g, 1, s, so);
-  site_info(g, 0, s, se);
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     Nbr n = neighbour(g, so, mu, h == 0 ? +1 : -1);
