@@ -2151,9 +2151,12 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     const int nsh = P == P_BF16 ? 3 : 2;
     double tv[8][3];
     for (auto& row : tv) row[0] = row[1] = row[2] = 1e30;
+    // each tuning buffer (input, output, Gaussian staging) is kept within 2 GiB
+    const size_t cap = std::max<size_t>(1, (size_t(2) << 30) / (size_t(c->V) * 24 * sizeof(double)));
     for (int si = 0; si < nsh; ++si) {
-      const int np = si == 0 ? 1 : int(props.size());
-      const int nrhs = si == 0 ? (big ? 1 : 16) : std::max(1, (big ? 8 : 128) / np);
+      const int np = si == 0 ? 1 : int(std::min<size_t>(props.size(), cap));
+      const int nrhs = int(std::min<size_t>(si == 0 ? (big ? 1 : 16) : std::max(1, (big ? 8 : 128) / np),
+                                            std::max<size_t>(1, cap / np)));
       Links L = links_of(c, si == 0 ? &slot : props.data(), np, fmt);
       FieldBatch in = field(c, "tune_in", P, np, nrhs);
       FieldBatch out = field(c, "tune_out", si == 2 ? P_F32 : P, np, nrhs);
