@@ -364,3 +364,73 @@ def test_inputs_are_su3_and_noise_normalised():
     changed = np.any(np.abs(Up - U) > 1e-15, axis=(2, 3))
     _, intra = synth.intra_block_link_sets((4, 4, 4, 4), (2, 2, 2, 2))
     assert np.array_equal(changed, intra)
+
+
+def test_interpolated_fields_endpoints_and_gamma5_hermiticity():
+    """eq. gfparam with g = 1: U_0 = U and U_N = U' exactly; the intermediate links are not
+    SU(3), yet D built with their Hermitian conjugates stays gamma5-Hermitian (Sec. 4.3), so
+    its determinant is real."""
+    L = (2, 2, 2, 2)
+    U = synth.gauge_field(L, 0.5, 40)
+    Up = synth.proposal(U, L, (2, 2, 2, 2), 0.3, 41)
+    N = 3
+    assert np.array_equal(estimator.interpolated_field(U, Up, N, 0), U)
+    assert np.array_equal(estimator.interpolated_field(U, Up, N, N), Up)
+    U1 = estimator.interpolated_field(U, Up, N, 1)
+    uu = np.einsum("...ij,...kj->...ik", U1, U1.conj())
+    assert np.abs(uu - np.eye(3)).max() > 1e-4  # not unitary
+    A = dirac.dirac_matrix(U1, 0.12, L).toarray()
+    g5 = np.kron(np.eye(A.shape[0] // 12), np.kron(np.diag([1, 1, -1, -1]), np.eye(3)))
+    H = g5 @ A
+    assert np.abs(H - H.conj().T).max() < 1e-13
+    sign, _ = np.linalg.slogdet(A)
+    assert abs(sign.imag) < 1e-10
+
+
+def test_interpolated_estimator_factorises():
+    """N interpolation steps (eqs. param, Mparam, staccN): prod_i det(M_i^dagger M_i) equals
+    det(M^dagger M) of the one-step M; the oracle's Delta equals the dense quadratic forms
+    sum_i xi_i^dagger (M_i^dagger M_i - 1) xi_i; and over independent noise per factor,
+    mean e^-Delta tends to det(M^dagger M)^-1 (computed from the one-step M alone) while
+    the variance of Delta falls below the one-step variance (the noise reduction of the
+    method)."""
+    L, b = (2, 2, 2, 2), (1, 1, 1, 1)
+    U = synth.gauge_field(L, 0.5, 50)
+    Up = synth.proposal(U, L, (2, 2, 2, 2), 0.12, 51)
+    kappa, N = 0.12, 3
+    M = _dense_M_full(L, U, Up, kappa)
+    lam = np.linalg.eigvalsh(M.conj().T @ M)
+    e_exp, _, var1 = estimator.exact_moments(lam)
+    Ms = [_dense_M_full(L, estimator.interpolated_field(U, Up, N, i), estimator.interpolated_field(U, Up, N, i + 1),
+                        kappa) for i in range(N)]
+    logdet = sum(np.linalg.slogdet(Mi.conj().T @ Mi)[1] for Mi in Ms)
+    assert logdet == pytest.approx(np.linalg.slogdet(M.conj().T @ M)[1], rel=1e-10, abs=1e-10)
+    varN = sum(estimator.exact_moments(np.linalg.eigvalsh(Mi.conj().T @ Mi))[2] for Mi in Ms)
+    assert varN < var1 / 2
+    g = schur.Geometry(L, b)
+    etas = synth.gaussian_noise(L, N, 52)
+    q = sum(float((np.vdot(Mi @ e.reshape(-1), Mi @ e.reshape(-1)) - np.vdot(e.reshape(-1), e.reshape(-1))).real)
+            for Mi, e in zip(Ms, etas))
+    assert estimator.delta_interpolated(g, U, Up, kappa, etas, op="full") == pytest.approx(q, rel=1e-10, abs=1e-10)
+    n = 20000
+    d = np.zeros(n)
+    for i, Mi in enumerate(Ms):
+        eta = synth.gaussian_noise(L, n, 60 + i).reshape(n, -1)
+        d += np.sum(np.abs(eta @ Mi.T) ** 2, axis=1) - np.sum(np.abs(eta) ** 2, axis=1)
+    se = np.std(np.exp(-d)) / np.sqrt(n)
+    assert abs(np.mean(np.exp(-d)) - e_exp) < 5 * se
+    assert np.var(d) == pytest.approx(varN, rel=0.06)
+
+
+def test_interpolated_estimator_one_step_is_the_estimator():
+    """N = 1 is the one-step estimator, FULL and SCHUR."""
+    L, b = (4, 4, 4, 4), (2, 2, 2, 2)
+    U = synth.gauge_field(L, 0.5, 70)
+    Up = synth.proposal(U, L, b, 0.05, 71)
+    g = schur.Geometry(L, b)
+    ops = schur.Operator(g, U, 0.12), schur.Operator(g, Up, 0.12)
+    e = synth.gaussian_noise(L, 1, 72)
+    assert estimator.delta_interpolated(g, U, Up, 0.12, e, op="full") == pytest.approx(
+        estimator.delta_full(*ops, e[0]), rel=1e-12, abs=1e-12)
+    assert estimator.delta_interpolated(g, U, Up, 0.12, e, op="schur") == pytest.approx(
+        estimator.delta_schur(*ops, e[0]), rel=1e-12, abs=1e-12)
