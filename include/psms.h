@@ -153,7 +153,15 @@ psms_status psms_apply_schur_inv(psms_ctx* ctx, int slot, const double* in, doub
  * noise field eta_j: delta[p*nnoise + j] = |M xi_j|^2 - |xi_j|^2 with
  *   op FULL : M = D(U')^-1 D(U),                 xi_j = eta_j;
  *   op SCHUR: M = (1 - PQ(U'))^-1 (1 - PQ(U)),   xi_j = P eta_j.
- * noise holds nnoise fields with density exp(-|eta|^2); n_interp must be 1.
+ * noise holds nnoise fields with density exp(-|eta|^2).
+ * n_interp = N > 1: gauge-field interpolation (Sec. 4.3) with the intermediate fields
+ * U_i = ((N - i) U + i U') / N of eq. gfparam (no relative gauge fixing, g = 1) and
+ * delta[p*nnoise + j] = sum_i (|M_i xi_ij|^2 - |xi_ij|^2), M_i = D(U_{i+1})^-1 D(U_i)
+ * (eq. Mparam; the Schur complements for SCHUR), eq. staccN. noise then holds N groups
+ * of nnoise fields, group i (fields i*nnoise .. i*nnoise + nnoise - 1) for factor i.
+ * The intermediate fields are not SU(3), so N > 1 needs prec PSMS_F64 (else
+ * PSMS_EINVAL); they use two free gauge slots (PSMS_EINVAL when fewer are free), which
+ * are free again on return.
  * SCHUR: the full solve inside (1 - PQ(U'))^-1 starts from the exact solution of the
  * same system with U, a by-product of applying (1 - PQ(U)); tol still refers to |b|.
  * delta may be host or device memory (nprop*nnoise doubles). */

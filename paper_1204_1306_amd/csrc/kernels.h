@@ -126,6 +126,9 @@ void lincomb_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& basis, siz
 void axpy_norm2(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
                 double* out);
 
+// out = wx x + wy y over n doubles (intermediate link fields of the interpolation)
+void launch_lerp(hipStream_t st, const double* x, const double* y, double wx, double wy, double* out, size_t n);
+
 // --- block solver (Schwarz / Dirichlet block inverses, minimal residual)
 struct BlockMRParams {
   int colour;

@@ -164,6 +164,20 @@ void launch_keep_colour(hipStream_t st, const Geo& g, const FieldBatch& y, int k
   DISPATCH_PREC(y.prec, keep_go, st, g, y, keep_colour);
 }
 
+// ----------------------------------------------------------------- interpolation
+// out[i] = wx x[i] + wy y[i] for i < n: intermediate link fields, entry by entry
+__global__ void k_lerp(const double* __restrict__ x, const double* __restrict__ y, double wx, double wy,
+                       double* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    out[i] = wx * x[i] + wy * y[i];
+}
+void launch_lerp(hipStream_t st, const double* x, const double* y, double wx, double wy, double* out, size_t n) {
+  if (n == 0) return;
+  const size_t g = (n + 255) / 256;
+  const unsigned nwg = unsigned(g < 65536 ? g : 65536);
+  hipLaunchKernelGGL(k_lerp, dim3(nwg), dim3(256), 0, st, x, y, wx, wy, out, n);
+}
+
 // ----------------------------------------------------------------- linear combination
 // y += sign * sum_j c[r][j] X_j
 template <Prec P>

@@ -1679,24 +1679,18 @@ psms_status psms_apply_schur_inv(psms_ctx* c, int slot, const double* in, double
   return PSMS_OK;
 }
 
-psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise,
-                              int nnoise, int n_interp, const psms_solve_params* pp, double* delta, psms_solve_stats* stats) {
-  API_BEGIN(c)
-  check_params(pp);
-  REQUIRE(op == PSMS_OP_FULL || op == PSMS_OP_SCHUR, "unknown operator");
-  REQUIRE(n_interp == 1, "only one interpolation step (n_interp = 1) is supported");
-  REQUIRE(nprop >= 1 && nnoise >= 1 && slot_Up && noise && delta, "bad sizes or null pointers");
-  auto t0 = std::chrono::steady_clock::now();
+// One estimator step: hdelta[p*nnoise + j] = |M xi_j|^2 - |xi_j|^2 for the fields in
+// slot_U and slot_Up[p] (eq. stacc, eq. Deltaistoch); solver outcomes go into agg.
+static void logdet_core(psms_ctx* c, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise, int nnoise,
+                        const psms_solve_params* pp, std::vector<double>& hdelta, FullSolveOut& agg) {
   const size_t fd = size_t(c->V) * 24;
   const double* dn = stage_in(c, noise, fd * nnoise, "stage_noise");
-  std::vector<double> hdelta(size_t(nprop) * nnoise, 0.0);
+  hdelta.assign(size_t(nprop) * nnoise, 0.0);
   Links LU = links_of(c, &slot_U, 1, LK_F64);
   // chunking: noise vectors per batch and proposals per batch
   int pchunk = std::min(nprop, MAXPROP);
   int jchunk = pp->rhs_chunk > 0 ? std::max(1, pp->rhs_chunk / pchunk) : nnoise;
   jchunk = std::min(jchunk, nnoise);
-  FullSolveOut agg;
-  agg.converged = true;
   for (int j0 = 0; j0 < nnoise; j0 += jchunk) {
     const int nj = std::min(jchunk, nnoise - j0);
     // xi_j (and phi_j for SCHUR), computed once with U and shared by all proposals
@@ -1751,6 +1745,70 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
       for (int p = 0; p < npp; ++p)
         for (int j = 0; j < nj; ++j) hdelta[size_t(p0 + p) * nnoise + j0 + j] = hy[size_t(p) * nj + j] - hx[j];
     }
+  }
+}
+
+// The field U_i of eq. gfparam (g = 1) for the fields in slots s0 and s1, into slot dst:
+// FP64 links only (not SU(3) in general), in every layout the context holds.
+static void interp_slot(psms_ctx* c, int dst, int s0, int s1, int N, int i) {
+  Slot& d = c->slots[dst];
+  const Slot& a = c->slots[s0];
+  const Slot& b = c->slots[s1];
+  const size_t n = size_t(c->V) * 4 * 18;  // doubles of one FP64 link field
+  const double wa = double(N - i) / N, wb = double(i) / N;
+  if (!d.f64) d.f64 = dev_alloc(c, n * sizeof(double));
+  launch_lerp(c->st, (const double*)a.f64, (const double*)b.f64, wa, wb, (double*)d.f64, n);
+  if (c->split) {
+    if (!d.f64_s) d.f64_s = dev_alloc(c, n * sizeof(double));
+    launch_lerp(c->st, (const double*)a.f64_s, (const double*)b.f64_s, wa, wb, (double*)d.f64_s, n);
+  }
+  d.loaded = true;
+  d.su3 = false;
+}
+
+psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise,
+                              int nnoise, int n_interp, const psms_solve_params* pp, double* delta, psms_solve_stats* stats) {
+  API_BEGIN(c)
+  check_params(pp);
+  REQUIRE(op == PSMS_OP_FULL || op == PSMS_OP_SCHUR, "unknown operator");
+  REQUIRE(n_interp >= 1 && n_interp <= 1024, "n_interp must be in [1, 1024]");
+  REQUIRE(n_interp == 1 || pp->prec == PSMS_F64,
+          "intermediate fields are not SU(3): n_interp > 1 needs prec PSMS_F64");
+  REQUIRE(nprop >= 1 && nnoise >= 1 && slot_Up && noise && delta, "bad sizes or null pointers");
+  REQUIRE(slot_U >= 0 && slot_U < 64 && c->slots[slot_U].loaded, "gauge slot not loaded");
+  for (int p = 0; p < nprop; ++p)
+    REQUIRE(slot_Up[p] >= 0 && slot_Up[p] < 64 && c->slots[slot_Up[p]].loaded, "gauge slot not loaded");
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> hdelta;
+  FullSolveOut agg;
+  agg.converged = true;
+  if (n_interp == 1) {
+    logdet_core(c, op, slot_U, slot_Up, nprop, noise, nnoise, pp, hdelta, agg);
+  } else {
+    // eq. staccN: per proposal, the sum over the N factors M_i = D(U_{i+1})^-1 D(U_i) of
+    // eq. Mparam, factor i with noise fields i*nnoise .. (i+1)*nnoise - 1; the
+    // intermediate fields go into two free slots, released afterwards
+    int fr[2] = {-1, -1};
+    for (int k = 63, n = 0; k >= 0 && n < 2; --k)
+      if (!c->slots[k].loaded) fr[n++] = k;
+    REQUIRE(fr[1] >= 0, "n_interp > 1 needs two free gauge slots");
+    struct Release {
+      psms_ctx* c;
+      int a, b;
+      ~Release() { c->slots[a].loaded = c->slots[b].loaded = false; }
+    } release{c, fr[0], fr[1]};
+    const size_t fd = size_t(c->V) * 24;
+    hdelta.assign(size_t(nprop) * nnoise, 0.0);
+    std::vector<double> step;
+    for (int p = 0; p < nprop; ++p)
+      for (int i = 0; i < n_interp; ++i) {
+        const int a = i == 0 ? slot_U : fr[0];
+        const int b = i + 1 == n_interp ? slot_Up[p] : fr[1];
+        if (i > 0) interp_slot(c, fr[0], slot_U, slot_Up[p], n_interp, i);
+        if (i + 1 < n_interp) interp_slot(c, fr[1], slot_U, slot_Up[p], n_interp, i + 1);
+        logdet_core(c, op, a, &b, 1, noise + size_t(i) * nnoise * fd, nnoise, pp, step, agg);
+        for (int j = 0; j < nnoise; ++j) hdelta[size_t(p) * nnoise + j] += step[j];
+      }
   }
   if (is_device_ptr(delta)) {
     HIPCHK(hipMemcpyAsync(delta, hdelta.data(), hdelta.size() * sizeof(double), hipMemcpyHostToDevice, c->st));

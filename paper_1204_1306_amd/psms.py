@@ -284,18 +284,23 @@ class Context:
         return out, st.as_dict()
 
     def logdet_ratio(self, op: int, slot_U: int, slots_Up, noise, params: SolveParams | None = None, delta=None,
-                     check: bool = True):
-        """Delta[p, j] for proposals slots_Up and noise fields; returns (delta, stats)."""
+                     check: bool = True, n_interp: int = 1):
+        """Delta[p, j] for proposals slots_Up and noise fields; returns (delta, stats).
+        With n_interp > 1 the noise holds n_interp groups of nnoise fields, group i for
+        interpolation factor i."""
         p = params or default_params()
         nprop = len(slots_Up)
-        nnoise = self._nrhs(noise)
+        nfield = self._nrhs(noise)
+        if n_interp < 1 or nfield % n_interp:
+            raise ValueError("the noise must hold n_interp groups of equally many fields")
+        nnoise = nfield // n_interp
         slots = (C.c_int * nprop)(*slots_Up)
         if delta is None:
             delta = np.empty((nprop, nnoise), np.float64)
         dptr = C.c_void_p(delta.data_ptr()) if _is_torch(delta) else C.c_void_p(delta.ctypes.data)
         st = SolveStats()
-        s = self._lib.psms_logdet_ratio(self._h, op, slot_U, slots, nprop, _ptr(noise), nnoise, 1, C.byref(p), dptr,
-                                        C.byref(st))
+        s = self._lib.psms_logdet_ratio(self._h, op, slot_U, slots, nprop, _ptr(noise), nnoise, int(n_interp), C.byref(p),
+                                        dptr, C.byref(st))
         if check:
             self._check(s)
         return delta, st.as_dict()

@@ -297,6 +297,36 @@ def test_logdet_ratio_small_workload(psms):
         assert abs(lhat[0] - estimator.log_ratio_estimate(ref[0])) < 1e-8
 
 
+def test_logdet_ratio_interpolated(psms):
+    """Gauge-field interpolation (Sec. 4.3, eqs. gfparam, Mparam, staccN) with N = 3 on the
+    4^4 workload, two proposals: same-noise Delta (sum over the three factors, each with its
+    own noise group) within 1e-8 absolute of the oracle, SCHUR and FULL. Mixed precision is
+    refused (the intermediate fields are not SU(3)), and the two slots the call borrows are
+    free again afterwards."""
+    w, U, Ups, _ = synth.workload_inputs("4x4x4x4", nprop=2)
+    N, nn = 3, 2
+    eta = synth.gaussian_noise(w["L"], N * nn, 4711)
+    ctx = make_ctx(psms, w["L"], w["b"], w["kappa"])
+    ctx.gauge_load(0, U)
+    ctx.gauge_load(1, Ups[0])
+    ctx.gauge_load(2, Ups[1])
+    prm = psms.default_params(tol=1e-12, max_iter=5000)
+    g = schur.Geometry(w["L"], w["b"])
+    for op, kind in ((psms.OP_SCHUR, "schur"), (psms.OP_FULL, "full")):
+        say("case interpolated", kind, "N", N)
+        d, st = ctx.logdet_ratio(op, 0, [1, 2], eta, prm, n_interp=N)
+        assert d.shape == (2, nn)
+        for p in range(2):
+            for j in range(nn):
+                ref = estimator.delta_interpolated(g, U, Ups[p], w["kappa"], [eta[i * nn + j] for i in range(N)], op=kind)
+                say(f"  p {p} j {j}: {d[p, j]:.12f} oracle {ref:.12f}")
+                assert abs(d[p, j] - ref) < 1e-8
+    with pytest.raises(psms.PsmsError):
+        ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10, prec=psms.MIXED), n_interp=N)
+    ctx.gauge_load(62, U)  # a borrowed slot, loadable again
+    ctx.gauge_load(63, U)
+
+
 def test_logdet_ratio_mixed_vs_f64_8x4(psms):
     """8^4 lattice, 4^4 blocks, kappa 0.15: FP64 and mixed precision both to 1e-10
     against the oracle on the same noise (4 of the 16 noise vectors)."""
