@@ -296,6 +296,35 @@ def batched_leg(psms, workload: str, steps: int, rhs_chunk: int):
     return out
 
 
+def interpolation_leg(psms, ctx, w, nprop, steps: int, ns=(1, 2, 4)):
+    """The estimator with gauge-field interpolation (N factors, FP64): seconds per
+    estimate and the spread of Delta over the noise fields, which the method reduces
+    about as 1/sqrt(N). Each factor draws its own seeded noise."""
+    import torch
+
+    from paper_1204_1306_amd import synth
+
+    prm = mode_params(psms, "plain", w["tol"])
+    slots = list(range(1, 1 + nprop))
+    nn = w["nnoise"]
+    out = {}
+    for n in ns:
+        eta = torch.from_numpy(synth.gaussian_noise(w["L"], n * nn, 9100 + n)).to("cuda")
+        delta = torch.empty((nprop, nn), dtype=torch.float64, device="cuda")
+        ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, eta, prm, delta=delta, n_interp=n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, eta, prm, delta=delta, n_interp=n)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        d = delta.cpu().numpy()
+        out[f"n{n}"] = {"s_per_estimate": dt / (nprop * nn), "ms_per_step": 1e3 * dt,
+                        "delta_std": float(d.std()), "delta_mean": float(d.mean()),
+                        "inner_iters": st["inner_iters"]}
+    return out
+
+
 def cpu_baseline(workload: str, budget_s: float = 20.0):
     """The CPU oracle on a bounded sample of the workload: one Schur estimate (one
     proposal, one noise vector). The Dirichlet block solves are timed on two blocks per
@@ -379,6 +408,7 @@ def main():
     ap.add_argument("--dw-blocks", default="auto")
     ap.add_argument("--batched-workload", default="16x16x16x16-batched", help="'none' skips the batched leg")
     ap.add_argument("--no-net-leg", action="store_true")
+    ap.add_argument("--no-interp-leg", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--batched-rhs-chunk", type=int, default=128)
     args = ap.parse_args()
@@ -428,6 +458,14 @@ def main():
         log(f"host buffers: {host_buffers}")
     except Exception as e:  # reported, not hidden
         host_buffers = {"error": repr(e)}
+
+    interp = None
+    if not args.no_interp_leg:
+        try:
+            interp = interpolation_leg(psms, ctx, w, nprop, max(1, args.plain_steps // 2))
+            log(f"interpolation: {interp}")
+        except Exception as e:  # reported, not hidden
+            interp = {"error": repr(e)}
 
     learned = None
     if not args.no_learned:
@@ -496,6 +534,8 @@ def main():
         "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
         # PCIe-inclusive: the same step with the noise and Delta in pageable host memory
         "host_buffers": host_buffers,
+        # gauge-field interpolation with N factors (FP64): cost and spread of Delta
+        "interpolation": interp,
         # ln mean_j exp(-Delta_pj) per proposal, from the same noise in both modes
         "log_ratio_estimate": {"fast": [round(float(v), 10) for v in psms.log_ratio_estimate(d_fast)],
                                "plain": [round(float(v), 10) for v in psms.log_ratio_estimate(d_plain)]},

@@ -261,7 +261,8 @@ psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);
  * the proposals of one launch (up to the proposals one launch addresses, SU(3) slots only
  * for the reduced-precision forms; `slot` itself when there is no other) with 128
  * right-hand sides in all (8 from 2^20 sites up), on Gaussian inputs; BF16 forms also
- * into FP32 outputs at the second shape. The
+ * into FP32 outputs at the second shape. Forms whose kernels spill registers to scratch
+ * are skipped while any form does not. The
  * form kept is the one whose worst slowdown against the fastest form of either shape is
  * smallest. For the right-hand-side blocking the fastest is kept. If cache_path names a
  * JSON-lines file holding an entry for this GPU architecture and geometry, that entry is

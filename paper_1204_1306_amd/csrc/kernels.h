@@ -56,6 +56,10 @@ struct DslashParams {
 };
 
 // out = cdiag * in + chop * H_sel in (+ out), on the selected parities/blocks.
+// Scratch bytes per lane (register spills) of the kernel that stencil form v runs for
+// input storage `in` and output storage `out` (F64 and F32 forms map to themselves;
+// BF16 input to BF16 or F32 output); 0 when the runtime does not say.
+size_t dslash_variant_scratch(Prec in, Prec out, int v);
 void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& in,
                    const FieldBatch& out, const DslashParams& dp, int nr_pref);
 

@@ -475,6 +475,35 @@ static void dslash_sel(hipStream_t st, const DslashArgs& a, int nprop, int sel, 
   else dslash_nr<SI, SO, LK, T, HOP_CROSS>(st, a, nprop, nr);
 }
 
+// The kernel that stencil form v launches for these storages (as dslash_variant does)
+template <class SI, class SO, class LK, class T>
+static const void* variant_kernel(int v) {
+  switch (v) {
+    case 7: return reinterpret_cast<const void*>(&k_dslash_block<SI, SO, LK, T, 1>);
+    case 1: return reinterpret_cast<const void*>(&k_dslash_split<SI, SO, LK, T, 1>);
+    case 2: return reinterpret_cast<const void*>(&k_dslash<SI, SO, LK, T, HOP_ALL, 1, 4>);
+    case 3: return reinterpret_cast<const void*>(&k_dslash_split<SI, SO, LK, T, 4>);
+    case 4: return reinterpret_cast<const void*>(&k_dslash<SI, SO, LK, T, HOP_ALL, 1, 6>);
+    case 5: return reinterpret_cast<const void*>(&k_dslash_split<SI, SO, LK, T, 6>);
+    case 6: return reinterpret_cast<const void*>(&k_dslash_quad<SI, SO, LK, T, 2>);
+    default: return reinterpret_cast<const void*>(&k_dslash<SI, SO, LK, T, HOP_ALL, 1, 1>);
+  }
+}
+
+size_t dslash_variant_scratch(Prec in, Prec out, int v) {
+  const void* f;
+  if (in == P_F64) f = variant_kernel<StF64, StF64, LkF64, double>(v);
+  else if (in == P_F32) f = variant_kernel<StF32, StF32, LkF32C12, float>(v);
+  else if (out == P_BF16) f = variant_kernel<StBF16, StBF16, LkF32C12, float>(v);
+  else f = variant_kernel<StBF16, StF32, LkF32C12, float>(v);
+  hipFuncAttributes attr;
+  if (hipFuncGetAttributes(&attr, f) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return attr.localSizeBytes;
+}
+
 void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& in,
                    const FieldBatch& out, const DslashParams& dp, int nr_pref) {
   DslashArgs a;

@@ -2204,6 +2204,13 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
       if (i != slot && c->slots[i].loaded && (P == P_F64 || c->slots[i].su3)) props.push_back(i);
     if (props.empty()) props.push_back(slot);
     const int fmt = P == P_F64 ? LK_F64 : LK_F32C12;
+    // Forms whose kernels spill registers to scratch are not timed while any form does not:
+    // their cost depends on what else occupies the caches, so an isolated timing misleads.
+    bool spills[8], any_clean = false;
+    for (int v = 0; v <= 7; ++v) {
+      spills[v] = dslash_variant_scratch(P, P, v) > 0 || (P == P_BF16 && dslash_variant_scratch(P, P_F32, v) > 0);
+      any_clean |= !spills[v];
+    }
     // BF16 inputs also meet FP32 outputs (a different kernel under the same form number):
     // a third measurement, the batched shape into FP32
     const int nsh = P == P_BF16 ? 3 : 2;
@@ -2222,6 +2229,7 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
       const int r = si == 0 ? reps : std::max(3, reps / 4);
       for (int round = 0; round < 4; ++round)  // round 0 only warms up (clocks, first launches)
         for (int v = 0; v <= 7; ++v) {
+          if (any_clean && spills[v]) continue;
           c->variant[pr] = v;
           const double t = time_dslash(c, L, in, out, r);
           if (round > 0) tv[v][si] = std::min(tv[v][si], t);
@@ -2230,9 +2238,10 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     double fastest[3] = {1e30, 1e30, 1e30};
     for (int v = 0; v <= 7; ++v)
       for (int si = 0; si < nsh; ++si) fastest[si] = std::min(fastest[si], tv[v][si]);
-    int best = 0;
+    int best = -1;
     double worst_best = 1e30;
     for (int v = 0; v <= 7; ++v) {
+      if (any_clean && spills[v]) continue;
       double worst = 0;
       for (int si = 0; si < nsh; ++si) worst = std::max(worst, tv[v][si] / fastest[si]);
       if (worst < worst_best) {
@@ -2240,7 +2249,7 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
         best = v;
       }
     }
-    c->variant[pr] = best;
+    c->variant[pr] = best < 0 ? 0 : best;
   }
   // right-hand sides per thread for batched launches (8 right-hand sides)
   for (int pr = 0; pr < 2; ++pr) {
