@@ -87,14 +87,14 @@ FAMILIES = ("dslash", "dslash_part", "block_mr", "block_solve", "blas", "net")
 TRAFFIC = {
     # even-odd FP32 block kernel, four lanes per site, links staged in LDS; 8 blocks x 16
     # right-hand sides, Schwarz sweeps (4 cycles x 6 block iterations, averaged over launches)
-    ("block_mr", "8x8x8x8", "mixed"): {"bytes_per_launch": 27262877, "source": "kernels_block.hip",
+    ("block_mr", "8x8x8x8", "mixed"): {"bytes_per_launch": 27262906, "source": "kernels_block.hip",
                                   "sha256": "3d1ecb116bacd732d136ac32d3a26135b09d40adacb7f9b296ca9c1871b2326e"},
     # full-lattice FP64 stencil at 32^4 on 4x4x8x16 blocks, four lanes per site (variant 6)
     # and split form (variant 1); keyed by lattice/block shape
-    ("dslash_f64_v6", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1344951765, "source": "kernels_dirac.hip",
-                                              "sha256": "32ebb8c2ff28342c88e02bd90d75fecdc897061fa4ce60d96888daf6719d5d8f"},
-    ("dslash_f64_v1", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1322713898, "source": "kernels_dirac.hip",
-                                              "sha256": "32ebb8c2ff28342c88e02bd90d75fecdc897061fa4ce60d96888daf6719d5d8f"},
+    ("dslash_f64_v6", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1351452507, "source": "kernels_dirac.hip",
+                                              "sha256": "972445184e6d1e397207f9b942531f8af75d7f6d8ce2c60c172ca9605582bc3b"},
+    ("dslash_f64_v1", "32x32x32x32/4x4x8x16", "dw"): {"bytes_per_launch": 1322265086, "source": "kernels_dirac.hip",
+                                              "sha256": "972445184e6d1e397207f9b942531f8af75d7f6d8ce2c60c172ca9605582bc3b"},
 }
 
 
