@@ -327,6 +327,30 @@ def test_logdet_ratio_interpolated(psms):
     ctx.gauge_load(63, U)
 
 
+def test_logdet_ratio_interpolated_split_schwarz_blocks(psms):
+    """The interpolated estimator (N = 2) in a context whose Schwarz blocks (2^4) differ from
+    its domain blocks (4^4), so the intermediate fields are formed in both link layouts:
+    the same Deltas as the unsplit context, within the bound the solve tolerance implies."""
+    w, U, Ups, _ = synth.workload_inputs("8x8x8x8", nprop=1)
+    N, nn = 2, 2
+    eta = synth.gaussian_noise(w["L"], N * nn, 4801)
+    prm = psms.default_params(tol=1e-10)
+    out = []
+    for sap_b in (None, (2, 2, 2, 2)):
+        say("case interpolated, Schwarz blocks", sap_b)
+        ctx = psms.Context(w["L"], w["b"], w["kappa"], sap_b=sap_b)
+        ctx.gauge_load(0, U)
+        ctx.gauge_load(1, Ups[0])
+        d, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, prm, n_interp=N)
+        say("  delta", d.ravel(), st)
+        assert st["converged"] == 1
+        out.append(d)
+        ctx.close()
+    g = schur.Geometry(w["L"], w["b"])
+    xi2 = sum(np.linalg.norm(g.project(e)) ** 2 for e in eta) / nn
+    assert np.abs(out[0] - out[1]).max() < 2 * xi2 * 1e-10 * 50
+
+
 def test_logdet_ratio_mixed_vs_f64_8x4(psms):
     """8^4 lattice, 4^4 blocks, kappa 0.15: FP64 and mixed precision both to 1e-10
     against the oracle on the same noise (4 of the 16 noise vectors)."""
