@@ -145,18 +145,6 @@ void* buf(psms_ctx* c, const std::string& name, size_t bytes) {
   return b.p;
 }
 
-// Frees a named buffer (after a one-off use such as tuning).
-void drop_buf(psms_ctx* c, const std::string& name) {
-  auto it = c->bufs.find(name);
-  if (it == c->bufs.end()) return;
-  if (it->second.p) {
-    HIPCHK(hipStreamSynchronize(c->st));
-    HIPCHK(hipFree(it->second.p));
-    c->held -= it->second.n;
-  }
-  c->bufs.erase(it);
-}
-
 FieldBatch field(psms_ctx* c, const std::string& name, Prec prec, int nprop, int nrhs, int copies = 1) {
   size_t bytes = bytes_per_field(prec, c->Vh) * size_t(nprop) * nrhs * copies;
   return FieldBatch{buf(c, name, bytes), prec, nprop, nrhs};
@@ -2175,7 +2163,25 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     }
   }
   REQUIRE(slot >= 0 && slot < 64 && c->slots[slot].loaded, "autotune needs a loaded gauge slot");
-  const bool prof = c->prof;
+  // kernel timing off while tuning; the setting and the tuning buffers are restored and
+  // freed on every way out
+  struct Restore {
+    psms_ctx* c;
+    bool prof;
+    ~Restore() {
+      c->prof = prof;
+      for (const char* b : {"tune_in", "tune_out", "tune_raw"}) {
+        auto it = c->bufs.find(b);
+        if (it == c->bufs.end()) continue;
+        if (it->second.p) {
+          (void)hipStreamSynchronize(c->st);
+          (void)hipFree(it->second.p);
+          c->held -= it->second.n;
+        }
+        c->bufs.erase(it);
+      }
+    }
+  } restore{c, c->prof};
   c->prof = false;
   const int reps = c->V >= (1 << 20) ? 10 : 30;
   // Stencil forms are timed on two launch shapes the solvers make: one gauge field with
@@ -2271,10 +2277,6 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
       if (tn[i] < tn[best]) best = i;
     *nr = cands[best];
   }
-  drop_buf(c, "tune_in");
-  drop_buf(c, "tune_out");
-  drop_buf(c, "tune_raw");
-  c->prof = prof;
   c->tuned_from = "autotune";
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "a")) {
