@@ -225,7 +225,7 @@ struct NetMfmaArgs {
   int cin, cout;  // channels of this launch
 };
 
-__global__ void __launch_bounds__(256) k_net_layer_mfma(NetMfmaArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_net_layer_mfma(NetMfmaArgs a) {
   // the staged input tile (bf16) and the output tile (FP32) share one LDS buffer:
   // the output is written only after the last MFMA has read the inputs
   constexpr size_t kB = sizeof(short) * 3 * NET_NS * NET_KPAD, kC = sizeof(float) * 8 * NET_MAXC * NET_CPAD;
