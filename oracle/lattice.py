@@ -58,15 +58,22 @@ def parity(L) -> np.ndarray:
     return coords(L).sum(axis=1) % 2
 
 
-def projector_matrices(L, b) -> np.ndarray:
-    """Per-site 4x4 spin matrices of P, shape [V, 4, 4] (colour identity implied)."""
+def projector_matrices(L, b, outer=None) -> np.ndarray:
+    """Per-site 4x4 spin matrices of P, shape [V, 4, 4] (colour identity implied).
+
+    With ``outer`` (recursive domain decomposition, eq. ddrec): the operator is the
+    Dirichlet operator of the outer blocks ``x // outer``, so a neighbour across an outer
+    face is no neighbour, and P counts only the out-of-block neighbours that stay in the
+    site's outer block."""
     V = volume(L)
     bid = block_id(L, b)
     black = is_black(L, b)
+    oid = block_id(L, outer) if outer is not None else np.zeros(V, int)
     out_nb = np.zeros((V, 4, 2), bool)  # [site, mu, (forward, backward)] outside own block
     for mu in range(4):
-        out_nb[:, mu, 0] = bid[neighbour(L, mu, +1)] != bid
-        out_nb[:, mu, 1] = bid[neighbour(L, mu, -1)] != bid
+        for k, sign in enumerate((+1, -1)):
+            nb = neighbour(L, mu, sign)
+            out_nb[:, mu, k] = (bid[nb] != bid) & (oid[nb] == oid)
     n_out = out_nb.reshape(V, 8).sum(axis=1)
     P = np.zeros((V, 4, 4), np.complex128)
     for mu in range(4):

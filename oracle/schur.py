@@ -22,15 +22,20 @@ from .solvers import DenseLU, cgne
 
 
 class Geometry:
-    def __init__(self, L, b, antiperiodic: bool = True):
+    """Blocks ``b`` of the Schur complement; with ``outer``, the projector of the
+    Dirichlet operator of the outer blocks (recursive decomposition, eq. ddrec), whose
+    links across outer faces the caller removes (``recursive.cut_links``)."""
+
+    def __init__(self, L, b, antiperiodic: bool = True, outer=None):
         self.L = tuple(int(v) for v in L)
         self.b = tuple(int(v) for v in b)
+        self.outer = tuple(int(v) for v in outer) if outer is not None else None
         self.antiperiodic = antiperiodic
         self.V = lattice.volume(self.L)
         self.black = lattice.is_black(self.L, self.b)
         self.white = ~self.black
         self.block = lattice.block_id(self.L, self.b)
-        self.Pm = lattice.projector_matrices(self.L, self.b)
+        self.Pm = lattice.projector_matrices(self.L, self.b, self.outer)
 
     def dofs(self, site_mask: np.ndarray) -> np.ndarray:
         """Flat dof indices (12 x + 3 s + c) of the sites in the mask."""
