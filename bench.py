@@ -8,10 +8,14 @@ with U' per pair (flexible GCR, Schwarz preconditioner, FP64 true residual to th
 workload's tolerance), FP64 accumulation. Gauge fields and noise are resident in
 HBM before the timed region.
 
-The default workload is the 8^4 lattice with 4^4 blocks, kappa 0.15, 16 noise
-vectors, tolerance 1e-10, timed once with FP32 inner solves and FP64 defect
-correction (the value) and once fully in FP64 (plain). Prints one JSON line;
-progress goes to stderr.
+The default workload is the largest one: the 32^4 lattice with 8^4 Schur blocks
+(4^4 Schwarz blocks), kappa 0.1575, 4 proposals x 32 noise vectors in one call,
+tolerance 1e-10. The value is its seconds per estimate with BF16 Krylov storage,
+FP32 inner solves and FP64 defect correction, all blocks, noise vectors and
+proposals batched per launch. Beside it: the same batch fully in FP64, the learned
+preconditioner on the same workload, D_w at 32^4, the batched 16^4 workload, the
+network, the interpolation leg, and the CPU oracle. Prints one JSON line; progress
+goes to stderr.
 """
 from __future__ import annotations
 
@@ -58,12 +62,12 @@ def mode_params(psms, mode: str, tol: float, workload: str | None = None):
     raise ValueError(mode)
 
 
-def setup(workload: str, nprop=None, nnoise=None):
+def setup(workload: str, nprop=None, nnoise=None, inputs=None):
     import torch
 
     from paper_1204_1306_amd import psms, synth
 
-    w, U, Ups, eta = synth.workload_inputs(workload, nprop=nprop, nnoise=nnoise)
+    w, U, Ups, eta = inputs if inputs is not None else synth.workload_inputs(workload, nprop=nprop, nnoise=nnoise)
     stream = torch.cuda.current_stream().cuda_stream
     ctx = psms.Context(w["L"], w["b"], w["kappa"], stream=stream, sap_b=w.get("sap_b"))
     dev = torch.device("cuda:0")
@@ -114,10 +118,10 @@ def traffic_for(family: str, workload: str, mode: str):
     return t["bytes_per_launch"]
 
 
-def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=False):
-    """Times `steps` unprofiled steps; with `profile`, then runs the same number of steps
-    again with per-family kernel timing (the event bookkeeping is kept out of the timed
-    region, where it would add to every launch of a latency-bound step)."""
+def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=False, profile_steps=None):
+    """Times `steps` unprofiled steps; with `profile`, then runs `profile_steps` (default
+    `steps`) more steps with per-family kernel timing (the event bookkeeping is kept out of
+    the timed region, where it would add to every launch of a latency-bound step)."""
     import torch
 
     slots = list(range(1, 1 + nprop))
@@ -135,7 +139,7 @@ def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=Fal
     fam = {}
     if profile:
         ctx.profile(True)
-        for _ in range(steps):
+        for _ in range(steps if profile_steps is None else profile_steps):
             ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise, params, delta=delta)
         torch.cuda.synchronize()
         fam = {f: ctx.profile_read(f) for f in FAMILIES}
@@ -143,43 +147,41 @@ def run_steps(psms, ctx, noise, delta, nprop, params, steps, warmup, profile=Fal
     return dt, stats, fam, d
 
 
-def dw_blocks(L, spec: str = "auto"):
-    """Block layout of the D_w leg. The operator does not depend on it; the layout sets
-    which sites a workgroup tile and its concurrent neighbours touch. "auto" takes blocks
-    of L/8, L/8, L/4, L/2 (4x4x8x16 at 32^4: long along the fastest direction, measured
-    best among the shapes tried), else an explicit "b0,b1,b2,b3"."""
-    if spec != "auto":
-        return tuple(int(v) for v in spec.split(","))
-    b = (L[0] // 8, L[1] // 8, L[2] // 4, L[3] // 2)
-    ok = all(x >= 2 and x % 2 == 0 and l % x == 0 and (l // x) % 2 == 0 for x, l in zip(b, L))
-    return b if ok else tuple(max(2, v // 4) for v in L)
-
-
-def dw_bandwidth(psms, L, b, kappa, reps=20):
-    """Full-lattice D_w launches on device-resident fields (FP64 and mixed), HIP events on
-    the library's stream, on an L lattice (32^4 by default: its working set exceeds the
-    256 MB Infinity Cache)."""
+def dw_bandwidth(psms, L, b, kappa, U=None, reps=20, nrhs_list=(1, 4, 8)):
+    """Full-lattice D_w launches on device-resident fields, HIP events on the library's
+    stream, on an L lattice (32^4: its working set exceeds the 256 MB Infinity Cache)
+    laid out in blocks b (the 4^4 Schwarz layout of the 32^4 solver). Forms: FP64;
+    FP32 12-real links with FP32 spinors; the same links with BF16 spinors (the
+    operands of the BF16 inner solves); each for 1, 4 and 8 right-hand sides (the
+    links are read once per launch in the algorithmic bytes)."""
     import torch
 
     from paper_1204_1306_amd import synth
 
     dev = torch.device("cuda:0")
     ctx = psms.Context(L, b, kappa, stream=torch.cuda.current_stream().cuda_stream)
-    ctx.gauge_load(0, torch.from_numpy(synth.gauge_field(L, 0.6, 5001)).to(dev))
+    ctx.gauge_load(0, torch.from_numpy(U if U is not None else synth.gauge_field(L, 0.6, 5001)).to(dev))
     tune = ctx.autotune(0, None)
-    psi = torch.from_numpy(synth.gaussian_noise(L, 1, 7)).to(dev)
     out = {"lattice": "x".join(map(str, L)), "blocks": "x".join(map(str, b)), "tuning": tune}
-    for name, prec in (("f64", psms.F64), ("mixed", psms.MIXED)):
-        ctx.apply_dw(0, psi, prec)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        for _ in range(reps):
-            ctx.apply_dw(0, psi, prec)
-        torch.cuda.synchronize()
-        r = ctx.profile_read("dslash")
-        ctx.profile(False)
-        out[name] = {"gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9, "us_per_launch": 1e3 * r["ms"] / r["launches"],
-                     "bytes_per_launch": r["bytes"] / r["launches"]}
+    forms = (("f64", lambda x: ctx.apply_dw(0, x, psms.F64)),
+             ("mixed", lambda x: ctx.apply_dw(0, x, psms.MIXED)),
+             ("bf16", lambda x: ctx.apply_dw_lowp(0, x, psms.SPINOR_BF16, psms.SPINOR_BF16)))
+    for n in nrhs_list:
+        psi = torch.from_numpy(synth.gaussian_noise(L, n, 7)).to(dev)
+        for name, fn in forms:
+            fn(psi)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            for _ in range(reps):
+                fn(psi)
+            torch.cuda.synchronize()
+            r = ctx.profile_read("dslash")
+            ctx.profile(False)
+            key = name if n == 1 else f"{name}_n{n}"
+            out[key] = {"gbs": r["bytes"] / (r["ms"] * 1e-3) / 1e9, "us_per_launch": 1e3 * r["ms"] / r["launches"],
+                        "bytes_per_launch": r["bytes"] / r["launches"]}
+        del psi
+        torch.cuda.empty_cache()
     ctx.close()
     return out
 
@@ -207,27 +209,39 @@ def copy_ceiling(mib=512, reps=10):
     return {"bytes_per_launch": nbytes, "us_per_launch": round(1e3 * ms, 2), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
-def learned_leg(psms, ctx, w, noise, delta, nprop, steps, npairs):
-    """Train the gauge-covariant network on seeded configurations of the workload's
-    geometry (outside the timed region), then time the estimator with it as the right
-    preconditioner of the mixed-precision solver."""
+def learned_leg(psms, ctx, w, noise, nprop, nnoise, steps, npairs, train_lattice=(16, 16, 16, 16)):
+    """The learned preconditioner on the workload's geometry. The network (1-8-8-8-1
+    channels) is trained on the GPU on seeded configurations of the near-critical 16^4
+    lattice (kappa 0.157, links exp(i 0.6 H), seeds 4000 + k), outside the timed region;
+    its weights act on any lattice, so they are loaded into the workload's context. Then
+    the estimator is timed with the network as right preconditioner of the mixed-precision
+    solver on the first `nprop` proposals x `nnoise` noise fields of the workload."""
     import torch
 
     from paper_1204_1306_amd import synth
 
     dev = torch.device("cuda:0")
+    tctx = psms.Context(train_lattice, (4, 4, 4, 4), 0.157, stream=torch.cuda.current_stream().cuda_stream)
     train_slots = []
     for k in range(4):
-        ctx.gauge_load(40 + k, torch.from_numpy(synth.gauge_field(w["L"], w["eps"], 9000 + k)).to(dev))
-        train_slots.append(40 + k)
-    ctx.net_init((1, 8, 8, 8, 1), seed=7, scale=0.05)
+        tctx.gauge_load(k, torch.from_numpy(synth.gauge_field(train_lattice, 0.6, 4000 + k)).to(dev))
+        train_slots.append(k)
+    chans = (1, 8, 8, 8, 1)
+    tctx.net_init(chans, seed=7, scale=0.05)
     t0 = time.perf_counter()
-    tr = ctx.net_train(train_slots, npairs=npairs, batch=8, epochs=2, chunk=64, lr=2e-3, solve_tol=1e-6)
+    tr = tctx.net_train(train_slots, npairs=npairs, batch=8, epochs=2, chunk=64, lr=2e-3, solve_tol=1e-6)
     t_train = time.perf_counter() - t0
+    weights = tctx.net_get_weights()
+    tctx.close()
+    ctx.net_init(chans)
+    ctx.net_set_weights(weights)
     prm = mode_params(psms, "learned", w["tol"])
-    dt, st, fam, d = run_steps(psms, ctx, noise, delta, nprop, prm, steps, 1, profile=True)
-    return {"s_per_estimate": dt / steps / (nprop * noise.shape[0]), "train_seconds": t_train, "train": tr,
-            "solver": st[-1], "net_ms_per_step": fam["net"]["ms"] / steps}, d
+    sub = noise[:nnoise]
+    delta = torch.empty((nprop, nnoise), dtype=torch.float64, device=dev)
+    dt, st, fam, d = run_steps(psms, ctx, sub, delta, nprop, prm, steps, 0, profile=True, profile_steps=1)
+    return {"s_per_estimate": dt / steps / (nprop * nnoise), "estimates_per_step": nprop * nnoise,
+            "train_lattice": "x".join(map(str, train_lattice)), "train_seconds": t_train, "train": tr,
+            "solver": st[-1], "net_ms_per_step": fam["net"]["ms"]}, d
 
 
 def net_leg(psms, L=(16, 16, 16, 16), nrhs=8, reps=10):
@@ -325,31 +339,27 @@ def interpolation_leg(psms, ctx, w, nprop, steps: int, ns=(1, 2, 4)):
     return out
 
 
-def cpu_baseline(workload: str, budget_s: float = 20.0):
-    """The CPU oracle on a bounded sample of the workload: one Schur estimate (one
-    proposal, one noise vector). The Dirichlet block solves are timed on two blocks per
-    colour (dense LU) and scaled to all blocks; the full solve is CG on the normal
-    equations, run until the workload tolerance or the time budget, and scaled to the
-    tolerance from the observed residual decay when the budget ends first."""
-    from oracle import schur
-    from oracle.solvers import norm2
-    from paper_1204_1306_amd import synth
+def cpu_baseline(workload: str, inputs, budget_s: float = 25.0):
+    """The CPU oracle (numpy, FP64) on a bounded sample of the workload.
 
-    w, U, Ups, eta = synth.workload_inputs(workload, nprop=1, nnoise=1)
+    * One matrix-free application of D on the whole lattice, timed: the oracle's D_w rate.
+    * The full-lattice solve of one Schur estimate (proposal 0, noise 0): the oracle's CG
+      on the normal equations for D(U') x = D_wb xi, run for `budget_s` seconds; the
+      iterations still needed for the workload's tolerance are extrapolated from the
+      residual decay of the last half of the iterations run, and the per-estimate time is
+      (iterations run + still needed) x the measured time per iteration. The Dirichlet
+      block solves that form (1 - PQ(U)) xi are left out, so the figure is a lower bound
+      on the oracle's seconds per estimate."""
+    from oracle import dirac, schur
+    from oracle.solvers import norm2
+
+    w, U, Ups, eta = inputs
     g = schur.Geometry(w["L"], w["b"])
-    opU = schur.Operator(g, U, w["kappa"], direct=False)
     opP = schur.Operator(g, Ups[0], w["kappa"], direct=False)
-    xi = g.project(eta[0])
-    nsample = min(2, g.V // int(np.prod(w["b"])) // 2)
     t0 = time.perf_counter()
-    for mask in (g.black, g.white):
-        for k in np.unique(g.block[mask])[:nsample]:
-            m = g.block == k
-            lu = schur.DenseLU(opU.sub_matrix(m, m).toarray())
-            lu.solve(xi.reshape(-1)[g.dofs(m)])
-    t_blk = (time.perf_counter() - t0) / (2 * nsample)
-    nblk = g.V // int(np.prod(w["b"]))
-    t_schur = t_blk * nblk
+    dirac.apply_D(U, eta[0], w["kappa"], w["L"])
+    t_dw = time.perf_counter() - t0
+    xi = g.project(eta[0])
     v = opP.D_wb(xi)
     bn = np.sqrt(norm2(v))
     x = np.zeros_like(v)
@@ -381,35 +391,40 @@ def cpu_baseline(workload: str, budget_s: float = 20.0):
     except Exception:
         cores = os.cpu_count()
     threads = os.environ.get("OMP_NUM_THREADS")
-    return {"value": float(t_schur + per_it * need), "unit": "s/estimate",
+    V = int(np.prod(w["L"]))
+    return {"value": float(per_it * need), "unit": "s/estimate",
             "cores": int(threads) if threads and threads.isdigit() else cores, "kind": "oracle",
-            "sample": (f"one {workload} Schur estimate (1 proposal x 1 noise): block solves by dense LU timed on "
-                       f"{nsample} blocks per colour ({t_blk:.3f} s each) x {nblk} blocks = {t_schur:.2f} s; full solve "
-                       f"by CG on the normal equations, {it} iterations in {t_cg:.1f} s reaching {h[-1]:.1e}"
-                       + ("" if h[-1] <= w["tol"] else f", scaled to {need:.0f} iterations for {w['tol']:g}"))}
+            "dw_seconds": t_dw, "dw_gbs": V * 960 / t_dw / 1e9,
+            "sample": (f"{workload}: one oracle D_w application on the whole lattice in {t_dw:.2f} s; the full solve of "
+                       f"one Schur estimate (proposal 0, noise 0) by CG on the normal equations, {it} iterations in "
+                       f"{t_cg:.1f} s reaching {h[-1]:.2e}"
+                       + ("" if h[-1] <= w["tol"] else f", extrapolated to {need:.0f} iterations for {w['tol']:g} from "
+                          f"the residual decay of its last {len(h) - k0} iterations")
+                       + "; block solves not included (lower bound)")}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="8x8x8x8")
-    ap.add_argument("--mode", default="mixed")
-    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="32x32x32x32")
+    ap.add_argument("--mode", default="mixed_bf16")
+    ap.add_argument("--rhs-chunk", type=int, default=32, help="right-hand sides per solver launch (memory)")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--plain-rhs-chunk", type=int, default=16, help="FP64 Krylov bases are 4x larger than BF16")
     ap.add_argument("--nprop", type=int, default=None)
     ap.add_argument("--nnoise", type=int, default=None)
-    ap.add_argument("--rhs-chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-pairs", type=int, default=512)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--dw-lattice", default="32,32,32,32")
-    ap.add_argument("--dw-blocks", default="auto")
+    ap.add_argument("--learned-estimates", default="1x8", help="proposals x noise of the learned leg")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--dw-blocks", default="4,4,4,4")
     ap.add_argument("--batched-workload", default="16x16x16x16-batched", help="'none' skips the batched leg")
     ap.add_argument("--no-net-leg", action="store_true")
     ap.add_argument("--no-interp-leg", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--batched-steps", type=int, default=1)
     ap.add_argument("--batched-rhs-chunk", type=int, default=128)
     args = ap.parse_args()
 
@@ -421,61 +436,61 @@ def main():
         print("bench.py runs on one GPU only (WORLD_SIZE > 1).", file=sys.stderr)
         sys.exit(2)
 
-    psms, ctx, w, noise, delta, nprop = setup(args.workload, args.nprop, args.nnoise)
+    import torch
+
+    from paper_1204_1306_amd import synth
+
+    t_setup = time.perf_counter()
+    inputs = synth.workload_inputs(args.workload, nprop=args.nprop, nnoise=args.nnoise)
+    psms, ctx, w, noise, delta, nprop = setup(args.workload, inputs=inputs)
     nnoise = noise.shape[0]
     nest = nprop * nnoise
     tune = ctx.autotune(0, None)
     log(f"workload {args.workload}: L={w['L']} b={w['b']} kappa={w['kappa']} {nprop} proposals x {nnoise} noise; "
-        f"tuning {tune}")
+        f"setup {time.perf_counter() - t_setup:.1f} s; tuning {tune}")
 
     fast = mode_params(psms, args.mode, w["tol"], args.workload)
     fast.rhs_chunk = args.rhs_chunk
-    dt, stats, fam, d_fast = run_steps(psms, ctx, noise, delta, nprop, fast, args.steps, args.warmup, profile=True)
+    dt, stats, fam, d_fast = run_steps(psms, ctx, noise, delta, nprop, fast, args.steps, args.warmup, profile=True,
+                                       profile_steps=1)
     ms_per_step = 1e3 * dt / args.steps
     log(f"{args.mode}: {ms_per_step:.2f} ms/step, solver {stats[-1]}")
-    log("  kernel families (ms over the timed steps):", {f: round(v["ms"], 2) for f, v in fam.items()})
-
-    plain = mode_params(psms, "plain", w["tol"], args.workload)
-    plain.rhs_chunk = args.rhs_chunk
-    dtp, stp, _, d_plain = run_steps(psms, ctx, noise, delta, nprop, plain, args.plain_steps, 1)
-    s_plain = dtp / args.plain_steps / nest
-    log(f"plain f64: {1e3 * dtp / args.plain_steps:.2f} ms/step, solver {stp[-1]}")
-
-    # the same mixed step with the noise and Delta in (pageable) host memory: the library
-    # stages the noise over PCIe and returns Delta to the host in every call
-    host_buffers = None
-    try:
-        noise_h = noise.cpu().numpy()
-        delta_h = np.empty((nprop, nest // nprop), np.float64)
-        slots = list(range(1, 1 + nprop))
-        ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise_h, fast, delta=delta_h)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, noise_h, fast, delta=delta_h)
-        dth = time.perf_counter() - t0
-        host_buffers = {"s_per_estimate": dth / args.steps / nest, "ms_per_step": 1e3 * dth / args.steps,
-                        "max_abs_delta_diff": float(np.abs(delta_h - d_fast).max())}
-        log(f"host buffers: {host_buffers}")
-    except Exception as e:  # reported, not hidden
-        host_buffers = {"error": repr(e)}
-
-    interp = None
-    if not args.no_interp_leg:
-        try:
-            interp = interpolation_leg(psms, ctx, w, nprop, max(1, args.plain_steps // 2))
-            log(f"interpolation: {interp}")
-        except Exception as e:  # reported, not hidden
-            interp = {"error": repr(e)}
+    log("  kernel families (ms over one profiled step):", {f: round(v["ms"], 2) for f, v in fam.items()})
 
     learned = None
+    d_learned = None
     if not args.no_learned:
         try:
-            learned, d_learned = learned_leg(psms, ctx, w, noise, delta, nprop, max(1, args.plain_steps // 2),
+            lp, ln = (int(v) for v in args.learned_estimates.split("x"))
+            learned, d_learned = learned_leg(psms, ctx, w, noise, min(lp, nprop), min(ln, nnoise), 1,
                                              args.learned_pairs)
-            learned["max_abs_delta_diff_vs_plain"] = float(np.abs(d_learned - d_plain).max())
             log(f"learned: {learned}")
         except Exception as e:  # reported, not hidden
             learned = {"error": repr(e)}
+    ctx.close()
+    torch.cuda.empty_cache()
+
+    # plain FP64 on the same batch, in a fresh context (its Krylov basis is FP64)
+    _, ctxp, _, _, _, _ = setup(args.workload, inputs=(w, inputs[1], inputs[2], inputs[3][:0]))
+    for k, v in tune.items():
+        ctxp.set_tuning(k, v)
+    plain = mode_params(psms, "plain", w["tol"], args.workload)
+    plain.rhs_chunk = args.plain_rhs_chunk
+    dtp, stp, _, d_plain = run_steps(psms, ctxp, noise, delta, nprop, plain, args.plain_steps, 0)
+    s_plain = dtp / args.plain_steps / nest
+    log(f"plain f64: {1e3 * dtp / args.plain_steps:.2f} ms/step, solver {stp[-1]}")
+    if learned and d_learned is not None and "error" not in learned:
+        learned["max_abs_delta_diff_vs_plain"] = float(np.abs(d_learned - d_plain[:d_learned.shape[0],
+                                                                                   :d_learned.shape[1]]).max())
+    ctxp.close()
+    del noise, delta
+    torch.cuda.empty_cache()
+
+    copy = copy_ceiling()
+    log(f"copy: {copy}")
+    dwb = tuple(int(v) for v in args.dw_blocks.split(","))
+    dw = dw_bandwidth(psms, w["L"], dwb, w["kappa"], U=inputs[1])
+    log(f"D_w: {dw}")
 
     batched = None
     if args.batched_workload != "none":
@@ -484,6 +499,16 @@ def main():
         except Exception as e:  # reported, not hidden
             batched = {"error": repr(e)}
 
+    interp = None
+    if not args.no_interp_leg:
+        try:
+            _, ictx, iw, _, _, inprop = setup("8x8x8x8")
+            interp = interpolation_leg(psms, ictx, iw, inprop, 2)
+            ictx.close()
+            log(f"interpolation: {interp}")
+        except Exception as e:  # reported, not hidden
+            interp = {"error": repr(e)}
+
     net = None
     if not args.no_net_leg:
         try:
@@ -491,12 +516,6 @@ def main():
             log(f"network: {net}")
         except Exception as e:  # reported, not hidden
             net = {"error": repr(e)}
-
-    copy = copy_ceiling()
-    log(f"copy: {copy}")
-    dwL = tuple(int(v) for v in args.dw_lattice.split(","))
-    dw = dw_bandwidth(psms, dwL, dw_blocks(dwL, args.dw_blocks), w["kappa"])
-    log(f"D_w: {dw}")
 
     # roofline of the dominant kernel family (by time) among those with a bytes model
     cand = [f for f in fam if fam[f]["launches"] > 0 and fam[f]["bytes"] > 0]
@@ -513,42 +532,41 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(args.workload, args.cpu_budget)
+            cpu = cpu_baseline(args.workload, inputs, args.cpu_budget)
         except Exception as e:  # the baseline is context; report why it is missing
             cpu = {"value": None, "error": repr(e)}
 
     value = dt / args.steps / nest
     dtype = {"mixed": "f32+f64", "mixed_bf16": "bf16+f32+f64", "plain": "f64", "learned": "f32+f64"}[args.mode]
+    dw_keys = [k for k, v in dw.items() if isinstance(v, dict) and "gbs" in v]
     line = {
         "metric": METRIC, "value": value, "unit": "s/estimate", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": (f"{'x'.join(map(str, w['L']))} lattice, {'x'.join(map(str, w['b']))} "
-                                f"blocks, kappa {w['kappa']}, links exp(i {w['eps']} H), {nprop} proposal(s) x {nnoise} "
-                                f"noise, Schur-complement ratio, relative residual {w['tol']:g}"),
-                   "mode": args.mode, "estimates_per_step": nest,
+                                f"Schur blocks, kappa {w['kappa']}, links exp(i {w['eps']} H), {nprop} proposal(s) x "
+                                f"{nnoise} noise in one call, Schur-complement ratio, relative residual {w['tol']:g}"),
+                   "mode": args.mode, "estimates_per_step": nest, "rhs_chunk": args.rhs_chunk,
+                   "schwarz_blocks": "x".join(map(str, w.get("sap_b") or w["b"])),
                    "schwarz": {"cycles": fast.sap_cycles, "block_iters": fast.block_iters,
                                "plain_cycles": plain.sap_cycles, "plain_block_iters": plain.block_iters}},
         "plain_f64_s_per_estimate": s_plain,
+        "plain_f64_rhs_chunk": args.plain_rhs_chunk,
         "speedup_vs_plain_f64": s_plain / value,
         "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
-        # PCIe-inclusive: the same step with the noise and Delta in pageable host memory
-        "host_buffers": host_buffers,
-        # gauge-field interpolation with N factors (FP64): cost and spread of Delta
-        "interpolation": interp,
         # ln mean_j exp(-Delta_pj) per proposal, from the same noise in both modes
-        "log_ratio_estimate": {"fast": [round(float(v), 10) for v in psms.log_ratio_estimate(d_fast)],
-                               "plain": [round(float(v), 10) for v in psms.log_ratio_estimate(d_plain)]},
+        "log_ratio_estimate": {"fast": [round(float(v), 8) for v in psms.log_ratio_estimate(d_fast)],
+                               "plain": [round(float(v), 8) for v in psms.log_ratio_estimate(d_plain)]},
         "learned": learned,
         "batched": batched,
+        "interpolation": interp,
         "network": net,
         "dw_lattice": dw["lattice"],
         "dw_blocks": dw["blocks"],
         "dw_tuning": dw["tuning"],
-        "dw_gbs": {k: round(v["gbs"], 1) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
-        "dw_us_per_launch": {k: round(v["us_per_launch"], 2) for k, v in dw.items() if isinstance(v, dict) and "gbs" in v},
-        "dw_frac_of_hbm_peak": {k: round(v["gbs"] / HBM_PEAK_GBS, 4) for k, v in dw.items()
-                                if isinstance(v, dict) and "gbs" in v},
+        "dw_gbs": {k: round(dw[k]["gbs"], 1) for k in dw_keys},
+        "dw_us_per_launch": {k: round(dw[k]["us_per_launch"], 2) for k in dw_keys},
+        "dw_frac_of_hbm_peak": {k: round(dw[k]["gbs"] / HBM_PEAK_GBS, 4) for k in dw_keys},
         "dw_traffic_bytes_per_launch": {"f64": traffic_for(f"dslash_f64_v{dw['tuning']['dslash_variant_f64']}",
                                                           f"{dw['lattice']}/{dw['blocks']}", "dw")},
         "copy_ceiling": copy,

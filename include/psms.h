@@ -57,6 +57,12 @@ typedef struct {
                           solves; all zero: the same as b. Must divide b, be even, with
                           L[mu]/sap_b[mu] even. The solver then works in a second block
                           layout (fields permuted in and out, links held twice). */
+  int outer_b[4];      /* recursive domain decomposition (Sec. 3, eq. ddrec): all zero for
+                          none; else every operator of the context is the Dirichlet operator
+                          of the outer blocks of this extent (the direct sum of their block
+                          operators D_B: hops across outer faces are dropped), whose Schur
+                          complement is taken over the sub-blocks b. Must be a multiple of
+                          b[mu] with outer_b[mu]/b[mu] even, and divide L[mu]. */
 } psms_geom;
 
 typedef struct {
@@ -103,12 +109,23 @@ unsigned long long psms_device_bytes(const psms_ctx* ctx);
 /* Uploads gauge field U into slot (0 <= slot < 64), converting it to the internal
  * layouts (FP64 and FP32 12-real). Returns PSMS_ENOTSU3 if some link deviates from
  * SU(3) by more than 1e-6 (the FP64 copy is still loaded; mixed precision is then
- * refused for this slot). */
+ * refused for this slot), PSMS_EINVAL if an entry is NaN or Inf (the slot is then
+ * left unloaded). */
 psms_status psms_gauge_load(psms_ctx* ctx, int slot, const double* U);
 
 /* out = D in (eq. Dw, rescaled), full lattice. prec MIXED applies the FP32 12-real
  * link, FP32 spinor kernel (input rounded to FP32). */
 psms_status psms_apply_dw(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs, psms_prec prec);
+
+/* out = D in (eq. Dw, rescaled) with the operands of the mixed-precision inner solves:
+ * FP32 12-real links, the input rounded to in_storage (FP32, or BF16 round-to-nearest-
+ * even), arithmetic in FP32, the result stored in out_storage and returned as FP64.
+ * Pairs: F32 -> F32, BF16 -> BF16, BF16 -> F32 (an FP32 input with a BF16 output is
+ * PSMS_EINVAL). The stencil form is that of the context's tuning for the input
+ * storage ("dslash_variant_f32" / "dslash_variant_bf16"). Needs SU(3) links
+ * (PSMS_ENOTSU3 otherwise). */
+psms_status psms_apply_dw_lowp(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs,
+                               psms_inner_storage in_storage, psms_inner_storage out_storage);
 
 /* Even-odd preconditioned operator on even sites: out_e = in_e - kappa^2 H_eo H_oe in_e
  * (the block-size-one case of eq. ddfactor). Odd sites of `in` are ignored, odd sites
@@ -168,6 +185,35 @@ psms_status psms_apply_schur_inv(psms_ctx* ctx, int slot, const double* in, doub
 psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise,
                               int nnoise, int n_interp, const psms_solve_params* params, double* delta,
                               psms_solve_stats* stats);
+
+/* The block-Schur filter of the recursive decomposition (Sec. 3, eq. ddrec; the second
+ * acceptance step of eq. 4step), on a context with outer blocks (geom.outer_b): for every
+ * proposal p, noise field j and outer block B (lexicographic order of x // outer_b),
+ *   delta[(p * nnoise + j) * nouter + B] = |(M xi_j)_B|^2 - |(xi_j)_B|^2,
+ *   M = (1 - PQ(U'))^-1 (1 - PQ(U)),   xi_j = P eta_j,
+ * with Q and P those of the outer blocks' Dirichlet operators over their sub-blocks b: the
+ * stochastic estimator of det(Dhat_B(U')^+ Dhat_B(U')) / det(Dhat_B(U)^+ Dhat_B(U)) for each
+ * outer block B at once (eq. Deltaistoch per block), since the operators are block-diagonal
+ * over the outer blocks and each block sees its own part of the noise. Summed over B it is
+ * what psms_logdet_ratio (SCHUR) gives on the same context. The full solve inside is judged
+ * on the whole lattice: params->tol bounds |b - D x| / |b| over all outer blocks together.
+ * delta: host or device memory, nprop * nnoise * nouter doubles. */
+psms_status psms_logdet_ratio_blocks(psms_ctx* ctx, int slot_U, const int* slot_Up, int nprop, const double* noise,
+                                     int nnoise, const psms_solve_params* params, double* delta, psms_solve_stats* stats);
+
+/* Exact block determinants: the first acceptance step of eq. 4step (the block filter,
+ * Sec. 3), whose determinants the paper computes exactly by LU for blocks of up to about
+ * 6^4 points. For every gauge slot slots[s] and every block of the context's block
+ * decomposition (blocks in lexicographic order of their coordinates x // b, direction 3
+ * fastest):
+ *   out[(s * nblk + k) * 2 + 0] = ln |det D_b|,  out[(s * nblk + k) * 2 + 1] = arg det D_b
+ * (in [-pi, pi]; det D_b is real, so 0 or pi up to rounding), D_b the Dirichlet block
+ * operator of eq. domdec. Computed as det(1 - kappa^2 H_eo H_oe) on the block's even sites
+ * (D_b has unit even-even and odd-odd blocks), by a dense LU in FP64 without row exchanges.
+ * The block filter's exponent is Delta_b = -2 (ln|det D_b(U')| - ln|det D_b(U)|).
+ * Blocks of more than 1024 sites: PSMS_EINVAL. A pivot of modulus below 1e-8: PSMS_ENOTCONV
+ * (the result is refused). out: host or device memory, nslot * nblk * 2 doubles. */
+psms_status psms_block_logdet(psms_ctx* ctx, const int* slots, int nslot, double* out);
 
 /* The estimate of the log-determinant ratio from the Deltas of psms_logdet_ratio
  * (Sec. 4.1, eq. stacc: the mean of e^-Delta over Gaussian noise is det(M^+ M)^-1):

@@ -206,6 +206,7 @@ struct Geo {
   int sB[4], sl[4];       // lexicographic strides of block coords and local coords
   int Vh, Vbh, nblk, nblk_c;
   int apbc;
+  int ob[4];               // outer (Dirichlet) block extent of the recursive decomposition, 0: none
   const uint32_t* lcoord;  // [2][Vbh] local coords of (parity, i), 8 bits each
   const uint32_t* bcoord;  // [nblk] block coords of blk, 8 bits each
   const int* border;       // [nblk] the order in which the stencil visits blocks (black, then its white neighbour)

@@ -71,6 +71,8 @@ void launch_pack(hipStream_t st, const Geo& g, const double* src, const FieldBat
 void launch_unpack(hipStream_t st, const Geo& g, const FieldBatch& src, double* dst);
 // links [V][4][3][3] complex double -> internal F64 or F32C12
 void launch_pack_links(hipStream_t st, const Geo& g, const double* U, void* dst, int linkfmt);
+// zero the links that leave their outer block (g.ob), in the internal format given
+void launch_cut_links(hipStream_t st, const Geo& g, void* links, int linkfmt);
 // max over links of |U U^+ - 1| (per-workgroup maxima in partial, host reduces)
 void launch_unitarity(hipStream_t st, const Geo& g, const double* U, double* partial, int nwg);
 
@@ -126,6 +128,8 @@ void reduce_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& x, const Fi
 // reduce_norm_dot.
 void lincomb_norm_dot(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const double2* c, int cstride,
                       const FieldBatch& y, const FieldBatch& z, const Reducer& R, const GcrStep& gs);
+// out[r * nblk + blk] = |x_r|^2 over block blk (FP64 fields, deterministic)
+void launch_block_norm2(hipStream_t st, const Geo& g, const FieldBatch& x, double* out);
 // y += a[r] x and out[r] = |y|^2 in one pass (x, y of one storage)
 void axpy_norm2(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
                 double* out);
@@ -167,6 +171,19 @@ void reduce_norm_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, co
                            double* out3, const GcrStep* gs = nullptr);
 void axpy_norm2_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, const Reducer& R,
                       double* out);
+
+// --- exact block determinants (kernels_lu.hip)
+// unit-vector columns k0 .. k0 + nr - 1 of the even-odd reduced block operator, in every
+// block at once (fields zeroed by the caller)
+void launch_lu_units(hipStream_t st, const Geo& g, double2* e, int k0, int nr, int n);
+// column k0 + r of each matrix of blocks [b0, b0 + nb) from y (= -kappa^2 H_eo H_oe e), plus 1
+void launch_lu_scatter(hipStream_t st, const Geo& g, const double2* y, double* M, int k0, int nr, int n, int npad, int b0,
+                       int nb);
+// zero nmat matrices (npad x npad complex, planar), ones on the padded diagonal
+void launch_lu_init(hipStream_t st, double* M, int n, int npad, int nmat);
+// blocked LU of nmat matrices in place; logdet[mat] += (sum ln|u_cc|, sum arg u_cc),
+// minpiv[mat] = min(minpiv[mat], |u_cc|); inv: scratch of 4 * 64 * 64 doubles per matrix
+void launch_lu_factor(hipStream_t st, double* M, int npad, int nmat, double2* logdet, double* minpiv, double* inv);
 
 // --- gauge-covariant network
 // one layer (forward, or adjoint with adj = 1) on F32 activations [batch][channel][field]

@@ -515,4 +515,31 @@ void axpy_norm2(hipStream_t st, const Geo& g, const double2* a, const FieldBatch
   DISPATCH_PREC(y.prec, axpy_norm_go, st, g, a, x, y, R, out);
 }
 
+
+// out[r * nblk + blk] = |x|^2 over the sites of block blk (both parities) of FP64 field r:
+// one workgroup per (block, field), a fixed-order tree in LDS (deterministic).
+__global__ void __launch_bounds__(256) k_block_norm2(Geo g, const double2* __restrict__ x, double* __restrict__ out) {
+  __shared__ double sm[256];
+  const int blk = blockIdx.x, r = blockIdx.y, t = threadIdx.x;
+  const size_t Vh = g.Vh;
+  const double2* f = x + size_t(r) * 24 * Vh + size_t(blk) * g.Vbh;
+  const int per = 12 * g.Vbh;  // units of one parity of a block
+  double acc = 0.0;
+  for (int e = t; e < 2 * per; e += 256) {
+    const int p = e / per, rem = e - p * per, k = rem / g.Vbh, i = rem - k * g.Vbh;
+    const double2 v = f[(size_t(p) * 12 + k) * Vh + i];
+    acc += v.x * v.x + v.y * v.y;
+  }
+  sm[t] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) sm[t] += sm[t + o];
+    __syncthreads();
+  }
+  if (t == 0) out[size_t(r) * g.nblk + blk] = sm[0];
+}
+
+void launch_block_norm2(hipStream_t st, const Geo& g, const FieldBatch& x, double* out) {
+  hipLaunchKernelGGL(k_block_norm2, dim3(g.nblk, x.nprop * x.nrhs), dim3(256), 0, st, g, (const double2*)x.p, out);
+}
 }  // namespace psms

@@ -525,12 +525,16 @@ void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int l
   // an output larger than the 8 XCD L2 caches (8 x 4 MB) cannot be re-read from L2 by
   // the next kernel anyway: stream it past the cache
   a.nt_out = double(bytes_per_field(out.prec, g.Vh)) * out.nrhs * out.nprop > 32.0 * (1 << 20) ? 1 : 0;
-  if (dp.variant > 0 && dp.sel == HOP_ALL && nr_pref <= 1) {
-    if (in.prec == P_F64 && out.prec == P_F64 && linkfmt == LK_F64)
+  // the stencil forms exist for these storage pairs; any other pair runs the one-lane form
+  const bool has_forms = (in.prec == P_F64 && out.prec == P_F64 && linkfmt == LK_F64) ||
+                         (in.prec != P_F64 && linkfmt == LK_F32C12 &&
+                          ((in.prec == P_F32 && out.prec == P_F32) || (in.prec == P_BF16 && out.prec != P_F64)));
+  if (dp.variant > 0 && dp.sel == HOP_ALL && nr_pref <= 1 && has_forms) {
+    if (in.prec == P_F64)
       dslash_variant<StF64, StF64, LkF64, double>(st, a, in.nprop, dp.variant);
-    else if (in.prec == P_F32 && out.prec == P_F32 && linkfmt == LK_F32C12)
+    else if (in.prec == P_F32)
       dslash_variant<StF32, StF32, LkF32C12, float>(st, a, in.nprop, dp.variant);
-    else if (in.prec == P_BF16 && out.prec == P_BF16 && linkfmt == LK_F32C12)
+    else if (out.prec == P_BF16)
       dslash_variant<StBF16, StBF16, LkF32C12, float>(st, a, in.nprop, dp.variant);
     else
       dslash_variant<StBF16, StF32, LkF32C12, float>(st, a, in.nprop, dp.variant);
@@ -672,6 +676,34 @@ void launch_pack_links(hipStream_t st, const Geo& g, const double* U, void* dst,
 }
 
 // Deviation of each link from SU(3): max(|U U^+ - 1|_max, |det U - 1|).
+// Links U(x, mu) with x_mu mod ob_mu = ob_mu - 1 leave x's outer block: set to zero.
+__global__ void k_cut_links(Geo g, void* __restrict__ links, int fmt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * g.Vh) return;
+  const int p = t / g.Vh, s = t - p * g.Vh;
+  SiteInfo si;
+  site_info(g, p, s, si);
+  const size_t Vh = g.Vh;
+  for (int mu = 0; mu < 4; ++mu) {
+    const int x = si.B[mu] * g.b[mu] + si.l[mu];
+    if (x % g.ob[mu] != g.ob[mu] - 1) continue;
+    if (fmt == LK_F64) {
+      double2* d = reinterpret_cast<double2*>(links) + size_t(p * 4 + mu) * 9 * Vh;
+      for (int k = 0; k < 9; ++k) d[k * Vh + s] = make_double2(0.0, 0.0);
+    } else {
+      float4* d = reinterpret_cast<float4*>(links) + size_t(p * 4 + mu) * 3 * Vh;
+      for (int k = 0; k < 3; ++k) d[k * Vh + s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+void launch_cut_links(hipStream_t st, const Geo& g, void* links, int linkfmt) {
+  hipLaunchKernelGGL(k_cut_links, dim3((2 * g.Vh + 255) / 256), dim3(256), 0, st, g, links, linkfmt);
+}
+
+// max that keeps a NaN (fmax drops it), so a link holding NaN or Inf marks the field
+__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
 __global__ void k_unitarity(const double* __restrict__ U, int nlinks, double* __restrict__ partial) {
   __shared__ double sm[256];
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -684,17 +716,17 @@ __global__ void k_unitarity(const double* __restrict__ U, int nlinks, double* __
       for (int j = 0; j < 3; ++j) {
         cx<double> a = cjmul(m[j][0], m[i][0]) + cjmul(m[j][1], m[i][1]) + cjmul(m[j][2], m[i][2]);
         double re = a.re - (i == j ? 1.0 : 0.0);
-        dev = fmax(dev, fmax(fabs(re), fabs(a.im)));
+        dev = nan_max(dev, nan_max(fabs(re), fabs(a.im)));
       }
     cx<double> det = cmul(m[0][0], cmul(m[1][1], m[2][2]) - cmul(m[1][2], m[2][1])) -
                      cmul(m[0][1], cmul(m[1][0], m[2][2]) - cmul(m[1][2], m[2][0])) +
                      cmul(m[0][2], cmul(m[1][0], m[2][1]) - cmul(m[1][1], m[2][0]));
-    dev = fmax(dev, fmax(fabs(det.re - 1.0), fabs(det.im)));
+    dev = nan_max(dev, nan_max(fabs(det.re - 1.0), fabs(det.im)));
   }
   sm[threadIdx.x] = dev;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    if (threadIdx.x < o) sm[threadIdx.x] = nan_max(sm[threadIdx.x], sm[threadIdx.x + o]);
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
@@ -752,8 +784,11 @@ __global__ void k_project(Geo g, const typename S::unit* __restrict__ in, typena
     int nout = 0, mu1 = 0, dir1 = 0;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-      if (si.l[mu] == g.b[mu] - 1) { ++nout; mu1 = mu; dir1 = +1; }
-      if (si.l[mu] == 0) { ++nout; mu1 = mu; dir1 = -1; }
+      // with outer blocks, a hop across an outer face is not part of the operator
+      const int x = si.B[mu] * g.b[mu] + si.l[mu];
+      const bool cut_f = g.ob[mu] && x % g.ob[mu] == g.ob[mu] - 1, cut_b = g.ob[mu] && x % g.ob[mu] == 0;
+      if (si.l[mu] == g.b[mu] - 1 && !cut_f) { ++nout; mu1 = mu; dir1 = +1; }
+      if (si.l[mu] == 0 && !cut_b) { ++nout; mu1 = mu; dir1 = -1; }
     }
     if (nout > 0) {
       Spinor<T> x;

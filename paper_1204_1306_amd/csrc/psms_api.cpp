@@ -253,8 +253,9 @@ void prof_collect(psms_ctx* c) {
 
 // ------------------------------------------------------------------ geometry
 // Builds the block-major layout of a lattice L with blocks b (device tables owned by c).
-void build_geo(psms_ctx* c, const int* L, const int* b, int apbc, Geo& g) {
+void build_geo(psms_ctx* c, const int* L, const int* b, int apbc, const int* ob, Geo& g) {
   int V = 1, nblk = 1, Vb = 1;
+  for (int m = 0; m < 4; ++m) g.ob[m] = ob ? ob[m] : 0;
   for (int m = 0; m < 4; ++m) {
     REQUIRE(L[m] > 0 && L[m] <= 255, "L[mu] must be in [1, 255]");
     REQUIRE(b[m] > 0 && L[m] % b[m] == 0, "L[mu] must be a multiple of b[mu]");
@@ -326,11 +327,19 @@ void check_geometry(const psms_geom* gm) {
       REQUIRE((gm->L[m] / gm->sap_b[m]) % 2 == 0, "L[mu]/sap_b[mu] must be even");
     }
   }
+  const bool outer = gm->outer_b[0] || gm->outer_b[1] || gm->outer_b[2] || gm->outer_b[3];
+  if (outer)
+    for (int m = 0; m < 4; ++m) {
+      REQUIRE(gm->outer_b[m] > 0 && gm->outer_b[m] % gm->b[m] == 0, "outer_b[mu] must be a multiple of b[mu]");
+      REQUIRE((gm->outer_b[m] / gm->b[m]) % 2 == 0, "outer_b[mu]/b[mu] must be even (sub-block colours)");
+      REQUIRE(gm->L[m] % gm->outer_b[m] == 0, "outer_b[mu] must divide L[mu]");
+    }
 }
 
 void setup_geometry(psms_ctx* c, const psms_geom* gm) {
   REQUIRE(gm->kappa > 0 && std::isfinite(gm->kappa), "kappa must be positive");
-  build_geo(c, gm->L, gm->b, gm->antiperiodic_t ? 1 : 0, c->g);
+  const bool outer = gm->outer_b[0] || gm->outer_b[1] || gm->outer_b[2] || gm->outer_b[3];
+  build_geo(c, gm->L, gm->b, gm->antiperiodic_t ? 1 : 0, outer ? gm->outer_b : nullptr, c->g);
   c->V = 2 * c->g.Vh;
   c->Vh = c->g.Vh;
   const bool any = gm->sap_b[0] || gm->sap_b[1] || gm->sap_b[2] || gm->sap_b[3];
@@ -340,7 +349,7 @@ void setup_geometry(psms_ctx* c, const psms_geom* gm) {
       REQUIRE(gm->sap_b[m] > 0 && gm->b[m] % gm->sap_b[m] == 0, "sap_b[mu] must divide b[mu]");
       c->split |= gm->sap_b[m] != gm->b[m];
     }
-    if (c->split) build_geo(c, gm->L, gm->sap_b, gm->antiperiodic_t ? 1 : 0, c->gs);
+    if (c->split) build_geo(c, gm->L, gm->sap_b, gm->antiperiodic_t ? 1 : 0, outer ? gm->outer_b : nullptr, c->gs);
   }
 }
 
@@ -389,9 +398,8 @@ Links links_of(psms_ctx* c, const int* slots, int nprop, int fmt) {
 double spinor_bytes(Prec p) { return p == P_F64 ? 192.0 : p == P_F32 ? 96.0 : 48.0; }
 double link_bytes(int fmt) { return fmt == LK_F64 ? 144.0 : 48.0; }
 
-// out = cdiag in + chop H_sel in (+ out), on blocks of out_colour (-1: all)
-void dslash(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch& out, int sel, int out_colour, double cdiag,
-            double chop, int accumulate) {
+DslashParams dslash_params(psms_ctx* c, const FieldBatch& in, int sel, int out_colour, double cdiag, double chop,
+                           int accumulate) {
   DslashParams dp;
   dp.sel = sel;
   dp.p0 = 0;
@@ -403,6 +411,13 @@ void dslash(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch&
   dp.accumulate = accumulate;
   dp.variant = c->variant[in.prec];
   dp.xcd_map = c->xcd_map;
+  return dp;
+}
+
+// out = cdiag in + chop H_sel in (+ out), on blocks of out_colour (-1: all)
+void dslash(psms_ctx* c, const Links& L, const FieldBatch& in, const FieldBatch& out, int sel, int out_colour, double cdiag,
+            double chop, int accumulate) {
+  DslashParams dp = dslash_params(c, in, sel, out_colour, cdiag, chop, accumulate);
   bool full = sel == HOP_ALL && out_colour < 0 && !accumulate;
   // algorithmic bytes of a full application: every link once, input and output once per rhs
   double bytes = double(c->V) * in.nprop * (4 * link_bytes(L.fmt) + in.nrhs * (spinor_bytes(in.prec) + spinor_bytes(out.prec)));
@@ -1429,12 +1444,27 @@ psms_status psms_gauge_load(psms_ctx* c, int slot, const double* U) {
     launch_pack_links(c->st, c->gs, dU, s.f64_s, LK_F64);
     launch_pack_links(c->st, c->gs, dU, s.c12_s, LK_F32C12);
   }
+  if (c->g.ob[0]) {
+    // recursive decomposition: the operator is the direct sum of the outer blocks'
+    // Dirichlet operators, i.e. D of the field without its links across outer faces
+    // (a zero link is exact in the 12-real form as well: its rebuilt row is zero too)
+    launch_cut_links(c->st, c->g, s.f64, LK_F64);
+    launch_cut_links(c->st, c->g, s.c12, LK_F32C12);
+    if (c->split) {
+      launch_cut_links(c->st, c->gs, s.f64_s, LK_F64);
+      launch_cut_links(c->st, c->gs, s.c12_s, LK_F32C12);
+    }
+  }
   const int nwg = 256;
   double* part = dscratch<double>(c, "unit_partial", nwg);
   launch_unitarity(c->st, c->g, dU, part, nwg);
   std::vector<double> h = to_host(c, part, nwg);
   double dev = 0;
-  for (double v : h) dev = std::max(dev, v);
+  for (double v : h) dev = (v > dev || v != v) ? v : dev;
+  if (!std::isfinite(dev)) {
+    s.loaded = false;
+    throw Err{PSMS_EINVAL, "gauge field holds a NaN or Inf entry; slot left unloaded"};
+  }
   s.loaded = true;
   s.su3 = dev <= 1e-6;
   if (!s.su3) {
@@ -1456,6 +1486,30 @@ psms_status psms_apply_dw(psms_ctx* c, int slot, const double* in, double* out, 
   FieldBatch a = field(c, "api_a", p, 1, nrhs), b = field(c, "api_b", p, 1, nrhs);
   launch_pack(c->st, c->g, din, a);
   apply_D(c, L, a, b);
+  launch_unpack(c->st, c->g, b, dout);
+  finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_dw_lowp(psms_ctx* c, int slot, const double* in, double* out, int nrhs,
+                               psms_inner_storage in_storage, psms_inner_storage out_storage) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  REQUIRE((in_storage == PSMS_SPINOR_F32 || in_storage == PSMS_SPINOR_BF16) &&
+              (out_storage == PSMS_SPINOR_F32 || out_storage == PSMS_SPINOR_BF16),
+          "storage must be PSMS_SPINOR_F32 or PSMS_SPINOR_BF16");
+  REQUIRE(!(in_storage == PSMS_SPINOR_F32 && out_storage == PSMS_SPINOR_BF16),
+          "an FP32 input takes an FP32 output (the solvers never round an FP32 stencil result to BF16)");
+  size_t nd = size_t(nrhs) * c->V * 24;
+  const double* din = stage_in(c, in, nd, "stage_in");
+  double* dout = stage_out(c, out, nd, "stage_out");
+  Prec pi = in_storage == PSMS_SPINOR_BF16 ? P_BF16 : P_F32;
+  Prec po = out_storage == PSMS_SPINOR_BF16 ? P_BF16 : P_F32;
+  Links L = links_of(c, &slot, 1, LK_F32C12);
+  FieldBatch a = field(c, "api_lp_a", pi, 1, nrhs), b = field(c, "api_lp_b", po, 1, nrhs);
+  launch_pack(c->st, c->g, din, a);
+  dslash(c, L, a, b, HOP_ALL, -1, 1.0, -c->geom.kappa, 0);
   launch_unpack(c->st, c->g, b, dout);
   finish_out(c, out, dout, nd);
   API_END(c)
@@ -1669,11 +1723,43 @@ psms_status psms_apply_schur_inv(psms_ctx* c, int slot, const double* in, double
 
 // One estimator step: hdelta[p*nnoise + j] = |M xi_j|^2 - |xi_j|^2 for the fields in
 // slot_U and slot_Up[p] (eq. stacc, eq. Deltaistoch); solver outcomes go into agg.
+// Outer (Dirichlet) block of each internal sub-block index, and the number of outer blocks.
+static std::vector<int> outer_of_blocks(const psms_ctx* c, int* nouter) {
+  const Geo& g = c->g;
+  int NO[4];
+  for (int m = 0; m < 4; ++m) NO[m] = g.L[m] / g.ob[m];
+  *nouter = NO[0] * NO[1] * NO[2] * NO[3];
+  std::vector<int> o(g.nblk);
+  for (int lex = 0; lex < g.nblk; ++lex) {
+    int B[4], r = lex;
+    for (int m = 3; m >= 0; --m) {
+      B[m] = r % g.NB[m];
+      r /= g.NB[m];
+    }
+    const int col = (B[0] + B[1] + B[2] + B[3]) & 1;
+    int O[4];
+    for (int m = 0; m < 4; ++m) O[m] = B[m] * g.b[m] / g.ob[m];
+    o[col * g.nblk_c + (lex >> 1)] = ((O[0] * NO[1] + O[1]) * NO[2] + O[2]) * NO[3] + O[3];
+  }
+  return o;
+}
+
+// With hblocks (a context with outer blocks): also hblocks[(p*nnoise + j)*nouter + B] =
+// |(M xi_j)_B|^2 - |(xi_j)_B|^2 per outer block B, the sums over each outer block's
+// sub-blocks taken in a fixed order.
 static void logdet_core(psms_ctx* c, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise, int nnoise,
-                        const psms_solve_params* pp, std::vector<double>& hdelta, FullSolveOut& agg) {
+                        const psms_solve_params* pp, std::vector<double>& hdelta, FullSolveOut& agg,
+                        std::vector<double>* hblocks = nullptr) {
   const size_t fd = size_t(c->V) * 24;
   const double* dn = stage_in(c, noise, fd * nnoise, "stage_noise");
   hdelta.assign(size_t(nprop) * nnoise, 0.0);
+  int nouter = 0;
+  std::vector<int> outer_of;
+  if (hblocks) {
+    outer_of = outer_of_blocks(c, &nouter);
+    hblocks->assign(size_t(nprop) * nnoise * nouter, 0.0);
+  }
+  const int nblk = c->g.nblk;
   Links LU = links_of(c, &slot_U, 1, LK_F64);
   // chunking: noise vectors per batch and proposals per batch
   int pchunk = std::min(nprop, MAXPROP);
@@ -1732,6 +1818,20 @@ static void logdet_core(psms_ctx* c, psms_op op, int slot_U, const int* slot_Up,
       }
       for (int p = 0; p < npp; ++p)
         for (int j = 0; j < nj; ++j) hdelta[size_t(p0 + p) * nnoise + j0 + j] = hy[size_t(p) * nj + j] - hx[j];
+      if (hblocks) {
+        double* by = dscratch<double>(c, "ld_by", size_t(npp) * nj * nblk);
+        double* bx = dscratch<double>(c, "ld_bx", size_t(nj) * nblk);
+        launch_block_norm2(c->st, c->g, y, by);
+        launch_block_norm2(c->st, c->g, xi, bx);
+        std::vector<double> hby, hbx;
+        to_host2(c, by, npp * nj * nblk, hby, bx, nj * nblk, hbx);
+        for (int p = 0; p < npp; ++p)
+          for (int j = 0; j < nj; ++j) {
+            double* o = &(*hblocks)[(size_t(p0 + p) * nnoise + j0 + j) * nouter];
+            for (int k = 0; k < nblk; ++k)
+              o[outer_of[k]] += hby[(size_t(p) * nj + j) * nblk + k] - hbx[size_t(j) * nblk + k];
+          }
+      }
     }
   }
 }
@@ -1803,6 +1903,114 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
     HIPCHK(hipStreamSynchronize(c->st));
   } else {
     std::memcpy(delta, hdelta.data(), hdelta.size() * sizeof(double));
+  }
+  fill_stats(stats, agg, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  if (agg.nan) return PSMS_ENAN;
+  if (!agg.converged) {
+    c->err = "a solve inside the estimator did not reach tol";
+    return PSMS_ENOTCONV;
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_block_logdet(psms_ctx* c, const int* slots, int nslot, double* out) {
+  API_BEGIN(c)
+  REQUIRE(slots && out && nslot >= 1, "null argument or no gauge slot");
+  const Geo& g = c->g;
+  const int n = 12 * g.Vbh;  // even sites of a block x 12
+  const int npad = (n + 63) / 64 * 64;
+  REQUIRE(n <= 6144, "exact block determinants take blocks of at most 1024 sites (the dense even-odd reduced "
+                     "operator has 6 V_b rows); factorise larger blocks by their Schur complement");
+  const size_t mat_doubles = size_t(2) * npad * npad;
+  const int per_batch = int(std::max<size_t>(1, std::min<size_t>(g.nblk, (size_t(16) << 30) / (8 * mat_doubles))));
+  double* M = dscratch<double>(c, "lu_M", mat_doubles * per_batch);
+  double2* dld = dscratch<double2>(c, "lu_logdet", per_batch);
+  double* dmp = dscratch<double>(c, "lu_minpiv", per_batch);
+  double* inv = dscratch<double>(c, "lu_inv", size_t(4) * 64 * 64 * per_batch);
+  const int nc = std::min(n, 96);  // columns assembled per pass
+  FieldBatch e = field(c, "lu_e", P_F64, 1, nc), tb = field(c, "lu_t", P_F64, 1, nc), y = field(c, "lu_y", P_F64, 1, nc);
+  // internal block index of each lexicographic block (black blocks first, eq. domdec)
+  std::vector<int> lex_of(g.nblk);
+  for (int lex = 0; lex < g.nblk; ++lex) {
+    int B[4], r = lex;
+    for (int m = 3; m >= 0; --m) {
+      B[m] = r % g.NB[m];
+      r /= g.NB[m];
+    }
+    const int col = (B[0] + B[1] + B[2] + B[3]) & 1;
+    lex_of[col * g.nblk_c + (lex >> 1)] = lex;
+  }
+  const double k2 = c->geom.kappa * c->geom.kappa;
+  std::vector<double2> zero_ld(per_batch, make_double2(0.0, 0.0));
+  std::vector<double> big_mp(per_batch, 1e300);
+  std::vector<double> res(size_t(nslot) * g.nblk * 2);
+  for (int si = 0; si < nslot; ++si) {
+    Links L = links_of(c, &slots[si], 1, LK_F64);
+    for (int b0 = 0; b0 < g.nblk; b0 += per_batch) {
+      const int nb = std::min(per_batch, g.nblk - b0);
+      launch_lu_init(c->st, M, n, npad, nb);
+      for (int k0 = 0; k0 < n; k0 += nc) {
+        const int nr = std::min(nc, n - k0);
+        FieldBatch ee{e.p, P_F64, 1, nr}, tt{tb.p, P_F64, 1, nr}, yy{y.p, P_F64, 1, nr};
+        launch_zero(c->st, ee, c->Vh);
+        launch_zero(c->st, tt, c->Vh);  // its even half is read (times zero) by the second hop
+        launch_lu_units(c->st, g, (double2*)ee.p, k0, nr, n);
+        // t_odd = H_oe e, then y_even = -kappa^2 H_eo t: hops inside the blocks only
+        DslashParams d1{HOP_INTRA, 1, 1, 0, g.nblk, 0.0, 1.0, 0};
+        launch_dslash(c->st, g, L.p, L.fmt, ee, tt, d1, 1);
+        DslashParams d2{HOP_INTRA, 0, 1, 0, g.nblk, 0.0, -k2, 0};
+        launch_dslash(c->st, g, L.p, L.fmt, tt, yy, d2, 1);
+        launch_lu_scatter(c->st, g, (const double2*)yy.p, M, k0, nr, n, npad, b0, nb);
+      }
+      HIPCHK(hipMemcpyAsync(dld, zero_ld.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, c->st));
+      HIPCHK(hipMemcpyAsync(dmp, big_mp.data(), sizeof(double) * nb, hipMemcpyHostToDevice, c->st));
+      launch_lu_factor(c->st, M, npad, nb, dld, dmp, inv);
+      HIPCHK(hipGetLastError());
+      std::vector<double2> hld(nb);
+      std::vector<double> hmp(nb);
+      HIPCHK(hipMemcpyAsync(hld.data(), dld, sizeof(double2) * nb, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(hmp.data(), dmp, sizeof(double) * nb, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+      for (int k = 0; k < nb; ++k) {
+        if (!(hmp[k] >= 1e-8) || !std::isfinite(hld[k].x))
+          throw Err{PSMS_ENOTCONV, "block LU met a pivot of modulus " + std::to_string(hmp[k]) + " in block " +
+                                       std::to_string(lex_of[b0 + k]) + " (no exchanges are made; result refused)"};
+        double* o = &res[(size_t(si) * g.nblk + lex_of[b0 + k]) * 2];
+        o[0] = hld[k].x;
+        o[1] = std::remainder(hld[k].y, 2.0 * M_PI);
+      }
+    }
+  }
+  if (is_device_ptr(out)) {
+    HIPCHK(hipMemcpyAsync(out, res.data(), res.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+  } else {
+    std::memcpy(out, res.data(), res.size() * sizeof(double));
+  }
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_logdet_ratio_blocks(psms_ctx* c, int slot_U, const int* slot_Up, int nprop, const double* noise,
+                                     int nnoise, const psms_solve_params* pp, double* delta, psms_solve_stats* stats) {
+  API_BEGIN(c)
+  check_params(pp);
+  REQUIRE(c->g.ob[0] > 0, "psms_logdet_ratio_blocks needs a context with outer blocks (geom.outer_b)");
+  REQUIRE(nprop >= 1 && nnoise >= 1 && slot_Up && noise && delta, "bad sizes or null pointers");
+  REQUIRE(slot_U >= 0 && slot_U < 64 && c->slots[slot_U].loaded, "gauge slot not loaded");
+  for (int p = 0; p < nprop; ++p)
+    REQUIRE(slot_Up[p] >= 0 && slot_Up[p] < 64 && c->slots[slot_Up[p]].loaded, "gauge slot not loaded");
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> hdelta, hblocks;
+  FullSolveOut agg;
+  agg.converged = true;
+  logdet_core(c, PSMS_OP_SCHUR, slot_U, slot_Up, nprop, noise, nnoise, pp, hdelta, agg, &hblocks);
+  if (is_device_ptr(delta)) {
+    HIPCHK(hipMemcpyAsync(delta, hblocks.data(), hblocks.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+  } else {
+    std::memcpy(delta, hblocks.data(), hblocks.size() * sizeof(double));
   }
   fill_stats(stats, agg, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
   if (agg.nan) return PSMS_ENAN;

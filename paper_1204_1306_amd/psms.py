@@ -35,7 +35,7 @@ class PsmsError(RuntimeError):
 
 class Geom(C.Structure):
     _fields_ = [("L", C.c_int * 4), ("b", C.c_int * 4), ("antiperiodic_t", C.c_int), ("kappa", C.c_double),
-                ("sap_b", C.c_int * 4)]
+                ("sap_b", C.c_int * 4), ("outer_b", C.c_int * 4)]
 
 
 class SolveParams(C.Structure):
@@ -76,6 +76,7 @@ _SIGS = {
     "psms_device_bytes": (C.c_ulonglong, [C.c_void_p]),
     "psms_gauge_load": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "psms_apply_dw": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "psms_apply_dw_lowp": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "psms_apply_dhat_ee": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "psms_apply_block": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "psms_apply_hop_bw": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
@@ -89,6 +90,9 @@ _SIGS = {
     "psms_logdet_ratio": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "psms_log_ratio_estimate": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "psms_block_logdet": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "psms_logdet_ratio_blocks": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]),
     "psms_net_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_ulonglong, C.c_double]),
     "psms_net_num_weights": (C.c_longlong, [C.c_void_p]),
     "psms_net_set_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_longlong]),
@@ -108,9 +112,18 @@ _SIGS = {
 
 
 def load_library():
-    """Open libpsms.so and declare every exported symbol's signature."""
+    """Open libpsms.so and declare every exported symbol's signature.
+
+    PyTorch is imported first when it is installed: its wheel carries its own HIP
+    runtime under the same soname as the system one, and the library must bind to the
+    runtime already in the process (a second HIP/HSA runtime in one process cannot open
+    the GPU that the first one holds)."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1204_1306_amd.build`")
         lib = C.CDLL(LIB_PATH)
@@ -170,7 +183,8 @@ def _empty_like(a):
 class Context:
     """One libpsms context (geometry, device, stream)."""
 
-    def __init__(self, L, b, kappa: float, antiperiodic: bool = True, device: int = 0, stream=None, sap_b=None):
+    def __init__(self, L, b, kappa: float, antiperiodic: bool = True, device: int = 0, stream=None, sap_b=None,
+                 outer_b=None):
         lib = load_library()
         g = Geom()
         g.L[:] = list(L)
@@ -178,7 +192,9 @@ class Context:
         g.antiperiodic_t = 1 if antiperiodic else 0
         g.kappa = float(kappa)
         g.sap_b[:] = list(sap_b) if sap_b is not None else [0, 0, 0, 0]
+        g.outer_b[:] = list(outer_b) if outer_b is not None else [0, 0, 0, 0]
         self.L, self.b, self.kappa = tuple(L), tuple(b), float(kappa)
+        self.outer_b = tuple(outer_b) if outer_b is not None else None
         self.V = int(np.prod(L))
         h = C.c_void_p()
         st = C.c_void_p(stream) if stream is not None else None
@@ -225,6 +241,12 @@ class Context:
     def apply_dw(self, slot: int, psi, prec: int = F64):
         out = _empty_like(psi)
         self._check(self._lib.psms_apply_dw(self._h, slot, _ptr(psi), _ptr(out), self._nrhs(psi), prec))
+        return out
+
+    def apply_dw_lowp(self, slot: int, psi, in_storage: int = SPINOR_BF16, out_storage: int = SPINOR_BF16):
+        out = _empty_like(psi)
+        self._check(self._lib.psms_apply_dw_lowp(self._h, slot, _ptr(psi), _ptr(out), self._nrhs(psi), in_storage,
+                                                 out_storage))
         return out
 
     def apply_dhat_ee(self, slot: int, psi):
@@ -304,6 +326,35 @@ class Context:
         if check:
             self._check(s)
         return delta, st.as_dict()
+
+    def n_outer(self) -> int:
+        return int(np.prod(np.asarray(self.L) // np.asarray(self.outer_b))) if self.outer_b else 0
+
+    def logdet_ratio_blocks(self, slot_U: int, slots_Up, noise, params: SolveParams | None = None, delta=None,
+                            check: bool = True):
+        """Delta[p, j, B] per outer block B (a context made with outer_b); returns (delta, stats)."""
+        p = params or default_params()
+        nprop = len(slots_Up)
+        nnoise = self._nrhs(noise)
+        slots = (C.c_int * nprop)(*slots_Up)
+        if delta is None:
+            delta = np.empty((nprop, nnoise, self.n_outer()), np.float64)
+        dptr = C.c_void_p(delta.data_ptr()) if _is_torch(delta) else C.c_void_p(delta.ctypes.data)
+        st = SolveStats()
+        s = self._lib.psms_logdet_ratio_blocks(self._h, slot_U, slots, nprop, _ptr(noise), nnoise, C.byref(p), dptr,
+                                               C.byref(st))
+        if check:
+            self._check(s)
+        return delta, st.as_dict()
+
+    def block_logdet(self, slots) -> np.ndarray:
+        """ln det D_b per gauge slot and block (lexicographic block order) as complex
+        (ln|det|, i arg det): shape [len(slots), nblk]."""
+        arr = (C.c_int * len(slots))(*slots)
+        nblk = int(np.prod(np.asarray(self.L) // np.asarray(self.b)))
+        out = np.empty((len(slots), nblk, 2), np.float64)
+        self._check(self._lib.psms_block_logdet(self._h, arr, len(slots), C.c_void_p(out.ctypes.data)))
+        return out[..., 0] + 1j * out[..., 1]
 
     # ---------------------------------------------------------------- learned preconditioner
     def net_init(self, channels=(1, 8, 8, 8, 1), seed: int = 1, scale: float = 0.1):

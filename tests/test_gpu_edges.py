@@ -71,19 +71,19 @@ def test_more_proposals_than_one_launch_addresses(psms):
 
 def test_ragged_right_hand_side_chunks(psms):
     """Noise vectors solved in chunks that do not divide their number (5 vectors, 2 per
-    chunk) give the Deltas of the unchunked solve within the tolerance bound."""
+    chunk) give the Deltas of the unchunked solve: both solve to 1e-12, where each Delta is
+    within 1e-8 of the exact value at this size, so they agree to 2e-8."""
     w, U, Ups, eta = synth.workload_inputs("8x8x8x8", nnoise=5)
     ctx = psms.Context(w["L"], w["b"], w["kappa"])
     ctx.gauge_load(0, U)
     ctx.gauge_load(1, Ups[0])
-    full, _ = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10))
-    prm = psms.default_params(tol=1e-10)
+    full, _ = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-12, max_iter=5000))
+    prm = psms.default_params(tol=1e-12, max_iter=5000)
     prm.rhs_chunk = 2
     chunked, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, prm)
-    say(" full", full, "chunked", chunked, st)
-    g = schur.Geometry(w["L"], w["b"])
-    xi2 = np.array([np.vdot(g.project(e), g.project(e)).real for e in eta])
-    assert np.all(np.abs(full[0] - chunked[0]) < 2 * xi2 * 1e-10 * 50)
+    diff = float(np.abs(full[0] - chunked[0]).max())
+    say(" full", full, "chunked", chunked, st, f"max diff {diff:.2e} (bound 2e-8)")
+    assert diff < 2e-8
 
 
 def test_autotune_cache_round_trip(psms, tmp_path):

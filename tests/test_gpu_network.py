@@ -113,6 +113,45 @@ def test_net_loss_and_gradient_parity(psms, mfma):
     assert rel(g, flat(ref_g)) < (1e-4 if mfma == 0 else 5e-2)
 
 
+def test_net_three_wave_form_agrees_with_two_wave_form(psms):
+    """Launches of >= 4096 workgroups run the matrix-core layer built for three waves per
+    SIMD; smaller ones the unconstrained form. At 16^4 (1024 workgroups per field) four
+    fields cross the threshold and two do not. Both forms take the same MFMA steps in the
+    same order, so the forward results agree to FP32 rounding (1e-6), the loss and its
+    gradient over four pairs equal the sums over two + two pairs (the gradient's site
+    reduction is split differently: 1e-5), and the three-wave forward matches the FP64
+    oracle within the bf16 tolerance."""
+    chans = (1, 8, 8, 8, 1)
+    L, b = (16, 16, 16, 16), (4, 4, 4, 4)
+    U = synth.gauge_field(L, 0.6, 4999)
+    r = synth.gaussian_noise(L, 4, 4702)
+    e = synth.gaussian_noise(L, 4, 4703)
+    ws = rand_weights(4701, chans)
+    ctx = psms.Context(L, b, 0.157)
+    ctx.set_tuning("net_mfma", 1)
+    ctx.gauge_load(0, U)
+    ctx.net_init(chans)
+    ctx.net_set_weights(flat(ws))
+    say("case net three-wave form: forward")
+    out4 = ctx.net_apply(0, r)
+    out2 = ctx.net_apply(0, r[:2])
+    d = rel(out4[:2], out2)
+    say(f"  |N4 - N2| / |N2| = {d:.2e}")
+    assert d < 1e-6
+    ref, _ = net.forward(U, ws, r[3], L)
+    err = rel(out4[3], ref)
+    say(f"  three-wave form against the FP64 oracle: {err:.2e} (bound {TOL[1]})")
+    assert err < TOL[1]
+    say("case net three-wave form: loss and gradient")
+    l4, g4 = ctx.net_loss_grad(0, r, e)
+    la, ga = ctx.net_loss_grad(0, r[:2], e[:2])
+    lb, gb = ctx.net_loss_grad(0, r[2:], e[2:])
+    say(f"  loss {l4} vs {la + lb}; gradient {rel(g4, ga + gb):.2e}")
+    assert l4 == pytest.approx(la + lb, rel=1e-6)
+    assert rel(g4, ga + gb) < 1e-5
+    ctx.close()
+
+
 def test_net_training_reduces_loss_and_checkpoints(psms, tmp_path):
     L, b = (8, 8, 8, 8), (4, 4, 4, 4)
     kappa = 0.15
@@ -175,12 +214,25 @@ def test_trained_network_gains_over_untrained_and_no_preconditioner(psms):
             assert np.linalg.norm(res) / np.linalg.norm(bvec[k]) <= 1.01e-10
         return st["inner_iters"]
 
+    import time
+
+    t0 = time.perf_counter()
+    n_sap = run(psms.PC_SAP)
+    t_sap = time.perf_counter() - t0
     n_none = run(psms.PC_NONE)
     ctx.net_init((1, 8, 8, 8, 1), seed=7, scale=0.05)
     n_untrained = run(psms.PC_NET)
     tr = ctx.net_train([10, 11, 12, 13], npairs=512, batch=8, epochs=2, chunk=64, lr=2e-3, solve_tol=1e-6)
+    t0 = time.perf_counter()
     n_trained = run(psms.PC_NET)
-    say(f" iterations: none {n_none}, untrained network {n_untrained}, trained network {n_trained}; train {tr}")
+    t_net = time.perf_counter() - t0
+    say(f" iterations: none {n_none}, untrained network {n_untrained}, trained network {n_trained} ({t_net:.3f} s), "
+        f"Schwarz {n_sap} ({t_sap:.3f} s); train {tr}")
     assert tr["final_loss"] < 0.5 * tr["first_loss"]
     assert n_trained <= 0.5 * n_untrained
     assert n_trained < n_none
+    # against the method without the network (Schwarz-preconditioned GCR) the trained
+    # network loses: it reaches 4 sites, a Schwarz block solve couples a whole block
+    if not (n_trained < n_sap and t_net < t_sap):
+        pytest.xfail(f"trained network {n_trained} iterations / {t_net:.3f} s against Schwarz {n_sap} / "
+                     f"{t_sap:.3f} s")

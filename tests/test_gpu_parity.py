@@ -330,11 +330,13 @@ def test_logdet_ratio_interpolated(psms):
 def test_logdet_ratio_interpolated_split_schwarz_blocks(psms):
     """The interpolated estimator (N = 2) in a context whose Schwarz blocks (2^4) differ from
     its domain blocks (4^4), so the intermediate fields are formed in both link layouts:
-    the same Deltas as the unsplit context, within the bound the solve tolerance implies."""
+    the same Deltas as the unsplit context. Both solve to 1e-12, where each Delta is
+    within 1e-8 of the exact value (the 8^4 estimator tests against the oracle), so the
+    two agree to 2e-8."""
     w, U, Ups, _ = synth.workload_inputs("8x8x8x8", nprop=1)
     N, nn = 2, 2
     eta = synth.gaussian_noise(w["L"], N * nn, 4801)
-    prm = psms.default_params(tol=1e-10)
+    prm = psms.default_params(tol=1e-12, max_iter=5000)
     out = []
     for sap_b in (None, (2, 2, 2, 2)):
         say("case interpolated, Schwarz blocks", sap_b)
@@ -346,38 +348,41 @@ def test_logdet_ratio_interpolated_split_schwarz_blocks(psms):
         assert st["converged"] == 1
         out.append(d)
         ctx.close()
-    g = schur.Geometry(w["L"], w["b"])
-    xi2 = sum(np.linalg.norm(g.project(e)) ** 2 for e in eta) / nn
-    assert np.abs(out[0] - out[1]).max() < 2 * xi2 * 1e-10 * 50
+    diff = float(np.abs(out[0] - out[1]).max())
+    say(f"  max |split - unsplit| = {diff:.2e} (bound 2e-8)")
+    assert diff < 2e-8
 
 
 def test_logdet_ratio_mixed_vs_f64_8x4(psms):
-    """8^4 lattice, 4^4 blocks, kappa 0.15: FP64 and mixed precision both to 1e-10
-    against the oracle on the same noise (4 of the 16 noise vectors)."""
+    """8^4 lattice, 4^4 blocks, kappa 0.15: FP64, mixed precision (FP32 and BF16 inner
+    storage) and FP32 block passes, all solving to 1e-12, against the oracle (1e-14) on the
+    same noise: same-noise Delta within 1e-8 absolute (the stated tolerance)."""
     w, U, Ups, eta = synth.workload_inputs("8x8x8x8", nnoise=4)
     ctx = make_ctx(psms, w["L"], w["b"], w["kappa"])
     ctx.gauge_load(0, U)
     ctx.gauge_load(1, Ups[0])
     ref = _oracle_deltas(w, U, Ups, eta[:2], "schur")
-    d64, s64 = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10))
-    dmx, smx = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10, prec=psms.MIXED))
-    say(" d64", d64.ravel(), s64)
-    say(" dmx", dmx.ravel(), smx)
     say(" ref", ref.ravel())
-    # |dDelta| <~ 2 |y| |M dphi| with relative solve error ~ cond * 1e-10
-    xi2 = np.array([np.linalg.norm(schur.Geometry(w["L"], w["b"]).project(e)) ** 2 for e in eta[:2]])
-    bound = 2 * xi2 * 1e-10 * 50
-    assert np.all(np.abs(d64[0, :2] - ref[0]) < bound)
-    assert np.all(np.abs(dmx[0, :2] - ref[0]) < bound)
-    assert np.abs(d64 - dmx).max() < bound.max()
+    runs = {"f64": dict(), "mixed": dict(prec=psms.MIXED),
+            "bf16": dict(prec=psms.MIXED, inner_storage=psms.SPINOR_BF16, inner_tol=1e-2, restart=32)}
+    out = {}
+    for name, kw in runs.items():
+        d, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-12, max_iter=5000, **kw))
+        err = float(np.abs(d[0, :2] - ref[0]).max())
+        say(f" {name}: {d.ravel()} {st}; max |gpu - oracle| = {err:.2e} (bound 1e-8)")
+        assert st["converged"] == 1 and err < 1e-8
+        out[name] = d
+    assert np.abs(out["f64"] - out["mixed"]).max() < 2e-8
+    assert np.abs(out["f64"] - out["bf16"]).max() < 2e-8
     # the block inverses to tolerance as FP32 passes inside FP64 defect correction
     ctx.set_tuning("block_tol_prec", 1)
-    dp, sp = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10, prec=psms.MIXED))
+    dp, sp = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-12, max_iter=5000,
+                                                                              prec=psms.MIXED))
     ctx.set_tuning("block_tol_prec", 0)
-    say(" dp32", dp.ravel(), sp)
-    assert sp["converged"] == 1
-    assert np.all(np.abs(dp[0, :2] - ref[0]) < bound)
-    assert np.abs(dp - d64).max() < bound.max()
+    err = float(np.abs(dp[0, :2] - ref[0]).max())
+    say(f" dp32 {dp.ravel()} {sp}; max |gpu - oracle| = {err:.2e}")
+    assert sp["converged"] == 1 and err < 1e-8
+    assert np.abs(dp - out["f64"]).max() < 2e-8
 
 
 def test_split_schwarz_blocks_same_results(psms):
@@ -391,8 +396,8 @@ def test_split_schwarz_blocks_same_results(psms):
     x, st = ctx.solve(0, bvec, psms.default_params(tol=1e-11, prec=psms.MIXED))
     res = bvec - dirac.apply_D(U, x, w["kappa"], w["L"])
     assert np.linalg.norm(res) / np.linalg.norm(bvec) <= 1.01e-11
-    d_split, _ = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-11))
+    d_split, _ = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-12, max_iter=5000))
     ref = _oracle_deltas(w, U, Ups, eta, "schur")
-    say(" split", d_split.ravel(), "oracle", ref.ravel())
-    xi2 = np.array([np.linalg.norm(schur.Geometry(w["L"], w["b"]).project(e)) ** 2 for e in eta])
-    assert np.all(np.abs(d_split[0] - ref[0]) < 2 * xi2 * 1e-11 * 50)
+    err = float(np.abs(d_split[0] - ref[0]).max())
+    say(" split", d_split.ravel(), "oracle", ref.ravel(), f"max diff {err:.2e} (bound 1e-8)")
+    assert err < 1e-8
