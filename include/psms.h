@@ -127,6 +127,18 @@ psms_status psms_apply_dw(psms_ctx* ctx, int slot, const double* in, double* out
 psms_status psms_apply_dw_lowp(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs,
                                psms_inner_storage in_storage, psms_inner_storage out_storage);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): psms_apply_dw without any
+ * allocation and without synchronising. `in` and `out` must be device memory of the
+ * context's device (PSMS_EINVAL otherwise); the work is only enqueued on the
+ * context's stream. The two internal-layout fields live in a fixed device array of
+ * 64 MiB that the library holds on every device it runs on until the process ends:
+ * nrhs fields need 2 x nrhs x V x 192 bytes (F64) or 96 bytes (MIXED), and a larger
+ * request is PSMS_EINVAL. All calls on one device share that array: calls that overlap
+ * on one device (other streams, other threads, other contexts) race and must be
+ * serialised by the caller. Results equal those of psms_apply_dw. */
+psms_status psms_apply_dw_noalloc(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs, psms_prec prec);
+
 /* Even-odd preconditioned operator on even sites: out_e = in_e - kappa^2 H_eo H_oe in_e
  * (the block-size-one case of eq. ddfactor). Odd sites of `in` are ignored, odd sites
  * of `out` are set to zero. */

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -63,6 +64,12 @@ const char* fam_names[NFAM] = {"dslash", "dslash_part", "block_mr", "block_solve
 
 }  // namespace
 
+// Scratch of psms_apply_dw_noalloc: the two internal-layout fields of one call. Each
+// device holds its own copy at its own address (hipGetSymbolAddress, taken once per
+// device when a context is created there); host code uses only that address.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 struct psms_ctx {
   psms_geom geom;
   Geo g;
@@ -114,6 +121,7 @@ struct psms_ctx {
     bool packed = false;                 // fragments match the FP32 weights
   } net;
   int net_mfma = 1;  // channel mixing on the matrix cores (bf16) or on the vector units (FP32)
+  void* noalloc_scratch = nullptr;  // this device's address of `scratch`
 };
 
 namespace {
@@ -1374,6 +1382,19 @@ const char* psms_status_string(psms_status s) {
   return "unknown status";
 }
 
+// Device address of `scratch` on `device` (current), looked up once per device.
+static void* noalloc_scratch_address(int device) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  addr[device] = p;
+  return p;
+}
+
 psms_status psms_create(const psms_geom* geom, int device, void* hip_stream, psms_ctx** out) {
   if (!geom || !out) return PSMS_EINVAL;
   *out = nullptr;
@@ -1389,6 +1410,7 @@ psms_status psms_create(const psms_geom* geom, int device, void* hip_stream, psm
     c->device = device;
     HIPCHK(hipSetDevice(device));
     c->st = reinterpret_cast<hipStream_t>(hip_stream);
+    c->noalloc_scratch = noalloc_scratch_address(device);
     setup_geometry(c, geom);
   } catch (const Err& e) {
     psms_status s = e.st;
@@ -1512,6 +1534,42 @@ psms_status psms_apply_dw_lowp(psms_ctx* c, int slot, const double* in, double* 
   dslash(c, L, a, b, HOP_ALL, -1, 1.0, -c->geom.kappa, 0);
   launch_unpack(c->st, c->g, b, dout);
   finish_out(c, out, dout, nd);
+  API_END(c)
+  return PSMS_OK;
+}
+
+psms_status psms_apply_dw_noalloc(psms_ctx* c, int slot, const double* in, double* out, int nrhs, psms_prec prec) {
+  API_BEGIN(c)
+  check_rhs(nrhs);
+  REQUIRE(in && out, "null field pointer");
+  REQUIRE(prec == PSMS_F64 || prec == PSMS_MIXED, "prec must be PSMS_F64 or PSMS_MIXED");
+  for (const void* p : {(const void*)in, (const void*)out}) {
+    hipPointerAttribute_t attr;
+    bool dev = hipPointerGetAttributes(&attr, p) == hipSuccess &&
+               (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged) && attr.device == c->device;
+    if (!dev) (void)hipGetLastError();
+    REQUIRE(dev, "psms_apply_dw_noalloc takes device memory of the context's device only (host buffers would need "
+                 "staging buffers)");
+  }
+  Prec p = prec == PSMS_F64 ? P_F64 : P_F32;
+  const size_t one = bytes_per_field(p, c->Vh) * size_t(nrhs);  // one batch of fields
+  const size_t off = (one + 255) & ~size_t(255);                  // the output batch starts 256-aligned
+  const size_t need = off + one;
+  if (need > kNoAllocScratchBytes)
+    throw Err{PSMS_EINVAL, "psms_apply_dw_noalloc: " + std::to_string(nrhs) + " fields need " + std::to_string(need) +
+                               " bytes of scratch, more than its " + std::to_string(kNoAllocScratchBytes) +
+                               "; pass fewer right-hand sides per call"};
+  REQUIRE(c->noalloc_scratch != nullptr, "no scratch address for this device");
+  Links L = links_of(c, &slot, 1, prec == PSMS_F64 ? LK_F64 : LK_F32C12);
+  unsigned char* base = static_cast<unsigned char*>(c->noalloc_scratch);
+  FieldBatch a{base, p, 1, nrhs}, b{base + off, p, 1, nrhs};
+  // pack writes every unit of a and the full-lattice stencil every unit of b, so
+  // nothing left by an earlier call is read
+  launch_pack(c->st, c->g, in, a);
+  DslashParams dp = dslash_params(c, a, HOP_ALL, -1, 1.0, -c->geom.kappa, 0);
+  launch_dslash(c->st, c->g, L.p, L.fmt, a, b, dp, p == P_F64 ? c->nr_f64 : c->nr_low);
+  launch_unpack(c->st, c->g, b, out);
+  HIPCHK(hipGetLastError());
   API_END(c)
   return PSMS_OK;
 }

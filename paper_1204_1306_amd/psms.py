@@ -77,6 +77,7 @@ _SIGS = {
     "psms_gauge_load": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "psms_apply_dw": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
     "psms_apply_dw_lowp": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "psms_apply_dw_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
     "psms_apply_dhat_ee": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "psms_apply_block": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "psms_apply_hop_bw": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
@@ -248,6 +249,13 @@ class Context:
         self._check(self._lib.psms_apply_dw_lowp(self._h, slot, _ptr(psi), _ptr(out), self._nrhs(psi), in_storage,
                                                  out_storage))
         return out
+
+    def apply_dw_noalloc(self, slot: int, psi, out, prec: int = F64, check: bool = True) -> int:
+        """psms_apply_dw_noalloc into the caller's `out` (device tensors only); returns the status."""
+        s = self._lib.psms_apply_dw_noalloc(self._h, slot, _ptr(psi), _ptr(out), self._nrhs(psi), prec)
+        if check:
+            self._check(s)
+        return s
 
     def apply_dhat_ee(self, slot: int, psi):
         out = _empty_like(psi)
