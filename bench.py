@@ -311,31 +311,45 @@ def batched_leg(psms, workload: str, steps: int, rhs_chunk: int):
 
 
 def interpolation_leg(psms, ctx, w, nprop, steps: int, ns=(1, 2, 4)):
-    """The estimator with gauge-field interpolation (N factors, FP64): seconds per
-    estimate and the spread of Delta over the noise fields, which the method reduces
-    about as 1/sqrt(N). Each factor draws its own seeded noise."""
+    """The estimator with gauge-field interpolation (N factors, FP64), without and with
+    the relative gauge fixing of the pair (App. B, default parameters; g on the
+    block-interior sites): seconds per estimate and the spread of Delta over the noise
+    fields, which the method reduces about as 1/sqrt(N). Each factor draws its own seeded
+    noise; both variants see the same noise."""
     import torch
 
     from paper_1204_1306_amd import synth
 
     prm = mode_params(psms, "plain", w["tol"])
-    slots = list(range(1, 1 + nprop))
     nn = w["nnoise"]
     out = {}
-    for n in ns:
-        eta = torch.from_numpy(synth.gaussian_noise(w["L"], n * nn, 9100 + n)).to("cuda")
-        delta = torch.empty((nprop, nn), dtype=torch.float64, device="cuda")
-        ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, eta, prm, delta=delta, n_interp=n)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            _, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, slots, eta, prm, delta=delta, n_interp=n)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        d = delta.cpu().numpy()
-        out[f"n{n}"] = {"s_per_estimate": dt / (nprop * nn), "ms_per_step": 1e3 * dt,
-                        "delta_std": float(d.std()), "delta_mean": float(d.mean()),
-                        "inner_iters": st["inner_iters"]}
+    t0 = time.perf_counter()
+    g_fix = {}
+    for p in range(nprop):
+        _, g_fix[p] = ctx.relative_gauge_fix(0, 1 + p, 40 + 2 * p, 41 + 2 * p)
+    torch.cuda.synchronize()
+    out["gauge_fix_seconds"] = time.perf_counter() - t0
+    out["gauge_fix"] = g_fix[0]
+    for fixed in (False, True):
+        for n in ns:
+            eta = torch.from_numpy(synth.gaussian_noise(w["L"], n * nn, 9100 + n)).to("cuda")
+            delta = torch.empty((1, nn), dtype=torch.float64, device="cuda")
+            ds, dt_all, it = [], 0.0, 0
+            for p in range(nprop):
+                a, b = (40 + 2 * p, 41 + 2 * p) if fixed else (0, 1 + p)
+                ctx.logdet_ratio(psms.OP_SCHUR, a, [b], eta, prm, delta=delta, n_interp=n)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    _, st = ctx.logdet_ratio(psms.OP_SCHUR, a, [b], eta, prm, delta=delta, n_interp=n)
+                torch.cuda.synchronize()
+                dt_all += (time.perf_counter() - t0) / steps
+                it += st["inner_iters"]
+                ds.append(delta.cpu().numpy()[0])
+            d = np.concatenate(ds)
+            out[f"{'fixed_' if fixed else ''}n{n}"] = {"s_per_estimate": dt_all / (nprop * nn),
+                                                       "ms_per_step": 1e3 * dt_all, "delta_std": float(d.std()),
+                                                       "delta_mean": float(d.mean()), "inner_iters": it}
     return out
 
 

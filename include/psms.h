@@ -198,6 +198,38 @@ psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* 
                               int nnoise, int n_interp, const psms_solve_params* params, double* delta,
                               psms_solve_stats* stats);
 
+/* Relative gauge fixing of a field pair (Sec. 4.2, eqs. relgf, choiceg, matrixMgf;
+ * App. B): the gauge transformation g, defined on the block-interior sites of the
+ * context's blocks (no nearest neighbour in another block) and 1 elsewhere, that
+ * minimises eq. relgf with g1 = g2^-1 = g, i.e. the distance (eq. sprodgf) between
+ * U^g(x,mu) = g(x) U(x,mu) g(x+mu)^+ and U'^(g^-1)(x,mu) = g(x)^+ U'(x,mu) g(x+mu).
+ * Since the link term depends on G = g^2 only, the steepest descent of App. B (eq. ming)
+ * runs on G, fixing U' to U, with Delta of eq. GF:Delta on the current pair and the step
+ * exp(alpha/2 C), C the traceless anti-Hermitian part of Delta - Delta^+ (the sign that
+ * lowers eq. relgf); a step that raises eq. relgf is rejected and alpha lowered by 0.01
+ * down to alpha_min, after which a rejected step ends the descent; the descent stops when
+ * the mean of theta (eq. GF:theta, -Tr C^2) over the domain is below theta_tol, or after
+ * max_iter steps. Then g = G^(1/2) (principal root), and U^g goes into slot_gU, U'^(g^-1)
+ * into slot_gUp (both SU(3); usable as the end points of the interpolation of
+ * psms_logdet_ratio, eq. gfparam). g_out (may be NULL, host or device): [V][3][3]
+ * complex FP64. FP64 throughout. PSMS_EINVAL on a context with outer blocks. */
+typedef struct {
+  double alpha;      /* step scale (App. B: 0.15) */
+  double alpha_min;  /* smallest step scale after rejections (0.10) */
+  double theta_tol;  /* stop when the mean theta over the domain is below it (1e-3) */
+  int max_iter;      /* steps tried at most (1000) */
+} psms_gf_params;
+typedef struct {
+  int iterations;          /* steps tried */
+  double functional_start; /* eq. sprodgf of (U, U') */
+  double functional_end;   /* eq. sprodgf of (U^g, U'^(g^-1)) */
+  double theta_end;        /* mean theta over the domain at the last check */
+  double alpha_end;
+} psms_gf_stats;
+void psms_default_gf_params(psms_gf_params* p);
+psms_status psms_relative_gauge_fix(psms_ctx* ctx, int slot_U, int slot_Up, const psms_gf_params* params, int slot_gU,
+                                    int slot_gUp, double* g_out, psms_gf_stats* stats);
+
 /* The block-Schur filter of the recursive decomposition (Sec. 3, eq. ddrec; the second
  * acceptance step of eq. 4step), on a context with outer blocks (geom.outer_b): for every
  * proposal p, noise field j and outer block B (lexicographic order of x // outer_b),
@@ -212,6 +244,45 @@ psms_status psms_logdet_ratio(psms_ctx* ctx, psms_op op, int slot_U, const int* 
  * delta: host or device memory, nprop * nnoise * nouter doubles. */
 psms_status psms_logdet_ratio_blocks(psms_ctx* ctx, int slot_U, const int* slot_Up, int nprop, const double* noise,
                                      int nnoise, const psms_solve_params* params, double* delta, psms_solve_stats* stats);
+
+/* The hierarchy of acceptance steps of one recursion level (Sec. 2, eq. hierarchy;
+ * Sec. 3, eq. 4step; App. A.2, eq. paccstoch; App. C, eq. Si) for a proposal U -> U'
+ * (slots slot_U, slot_Up, loaded in both contexts) that changes links inside the
+ * smallest blocks only (PSMS_EINVAL otherwise). `in` has the smallest blocks b' as its
+ * blocks and the blocks B as outer_b; `out` has B as its blocks (same lattice, kappa,
+ * device and stream). Each step accepts when its uniform u in [0, 1) is below
+ * exp(-Delta), i.e. with probability min{1, e^-Delta}, one Delta per decision:
+ *  1) every b' separately: Delta1 = beta[0] dS1_b', dS1_b' = -2 (ln|det D_b'(U')| -
+ *     ln|det D_b'(U)|) exactly (psms_block_logdet); U1 = U' in the accepted b', U elsewhere;
+ *  2) every B separately: Delta2 = dS2_B + beta[1] sum_{b' in B, accepted} dS1_b', dS2_B the
+ *     block-Schur estimator of U1 against U with noise field 0 (psms_logdet_ratio_blocks);
+ *     U2 = U1 in the accepted B, U elsewhere;
+ *  3) Delta3 = dS3 + beta[2] sum_{b' kept in U2} dS1_b', dS3 the Schur estimator of the
+ *     blocks B (psms_logdet_ratio, SCHUR) of U2 against U with noise field 1;
+ *     the new state is U2 when accepted, else U.
+ * beta are the coefficients of the exactly computed block-determinant action at the three
+ * steps (App. C); they must sum to 1. uniforms: nsmall + nouter + 1 values (steps 1, 2, 3;
+ * blocks in lexicographic order); noise: 2 fields, density exp(-|eta|^2). The two work
+ * slots are overwritten in both contexts; with slot_out >= 0 the new state is loaded there
+ * in both contexts. The proposal step itself and any gauge-action terms are the caller's. */
+typedef struct {
+  double beta[3];              /* coefficients of the block-determinant action per step (1, 0, 0) */
+  psms_solve_params solve;     /* the solves of steps 2 and 3 */
+  int work_slot[2];            /* slots overwritten in both contexts (62, 63) */
+  int slot_out;                /* -1: not loaded */
+} psms_filter_params;
+typedef struct {
+  double* delta1;   /* [nsmall] or NULL */
+  int* accept1;     /* [nsmall] or NULL */
+  double* delta2;   /* [nouter] or NULL */
+  int* accept2;     /* [nouter] or NULL */
+  double delta3;
+  int accept3;
+  int inner_iters;  /* Krylov iterations of steps 2 and 3 */
+} psms_filter_result;
+void psms_default_filter_params(psms_filter_params* p);
+psms_status psms_filter_step(psms_ctx* in, psms_ctx* out, int slot_U, int slot_Up, const psms_filter_params* params,
+                             const double* uniforms, const double* noise, psms_filter_result* result);
 
 /* Exact block determinants: the first acceptance step of eq. 4step (the block filter,
  * Sec. 3), whose determinants the paper computes exactly by LU for blocks of up to about

@@ -185,6 +185,29 @@ void launch_lu_init(hipStream_t st, double* M, int n, int npad, int nmat);
 // minpiv[mat] = min(minpiv[mat], |u_cc|); inv: scratch of 4 * 64 * 64 doubles per matrix
 void launch_lu_factor(hipStream_t st, double* M, int npad, int nmat, double2* logdet, double* minpiv, double* inv);
 
+// --- relative gauge fixing (kernels_gf.hip): links in the boundary layout [V][4][3][3]
+int gf_partials(const Geo& g);  // workgroups (partial sums) of the per-site kernels
+void launch_gf_unpack(hipStream_t st, const Geo& g, const void* links_f64, double* U);
+void launch_gf_eye(hipStream_t st, const Geo& g, double* G);
+// K = exp(half_alpha C) on the block-interior sites (1 elsewhere); theta partial sums
+void launch_gf_step(hipStream_t st, const Geo& g, const double* U, const double* Upc, double* K, double half_alpha,
+                    double* theta_part);
+// Upt(x,mu) = K(x)^+ Upc(x,mu) K(x+mu); partial sums of Re Tr(U^+ Upt)
+void launch_gf_trial(hipStream_t st, const Geo& g, const double* U, const double* Upc, const double* K, double* Upt,
+                     double* f_part);
+void launch_gf_overlap(hipStream_t st, const Geo& g, const double* U, const double* Up, double* f_part);
+void launch_gf_accept(hipStream_t st, const Geo& g, double* G, const double* K);
+// g = G^(1/2) on the domain; Ug = U^g, Upg = U'^(g^-1)
+void launch_gf_finish(hipStream_t st, const Geo& g, const double* G, double* gout, const double* U, const double* Up,
+                      double* Ug, double* Upg);
+
+// out = U' on the links inside the blocks x // b whose accept flag (lexicographic block
+// index) is set, U elsewhere (boundary layout)
+void launch_merge_links(hipStream_t st, const Geo& g, const int* b, const int* accept, const double* U, const double* Up,
+                        double* out);
+// per-workgroup max |U' - U| over the links that leave their block x // b
+void launch_change_across(hipStream_t st, const Geo& g, const int* b, const double* U, const double* Up, double* part);
+
 // --- gauge-covariant network
 // one layer (forward, or adjoint with adj = 1) on F32 activations [batch][channel][field]
 void launch_net_layer(hipStream_t st, const Geo& g, const void* links, const void* in, void* out, const float2* W, int cin_f,

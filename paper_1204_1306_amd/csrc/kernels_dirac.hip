@@ -553,31 +553,6 @@ void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int l
 }
 
 // ----------------------------------------------------------------- layout conversion
-// Internal (parity, s) of the site with coordinates x.
-__device__ __forceinline__ void coords_to_internal(const Geo& g, const int (&x)[4], int& p, int& s) {
-  int B[4], l[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    B[m] = x[m] / g.b[m];
-    l[m] = x[m] - B[m] * g.b[m];
-  }
-  int lexB = ((B[0] * g.NB[1] + B[1]) * g.NB[2] + B[2]) * g.NB[3] + B[3];
-  int col = (B[0] + B[1] + B[2] + B[3]) & 1;
-  int ll = ((l[0] * g.b[1] + l[1]) * g.b[2] + l[2]) * g.b[3] + l[3];
-  p = (x[0] + x[1] + x[2] + x[3]) & 1;
-  s = (col * g.nblk_c + (lexB >> 1)) * g.Vbh + (ll >> 1);
-}
-
-// Internal (parity, s) of a lexicographic site.
-__device__ __forceinline__ void lex_to_internal(const Geo& g, int lex, int& p, int& s) {
-  int x[4];
-  int r = lex;
-  x[3] = r % g.L[3]; r /= g.L[3];
-  x[2] = r % g.L[2]; r /= g.L[2];
-  x[1] = r % g.L[1]; x[0] = r / g.L[1];
-  coords_to_internal(g, x, p, s);
-}
-
 // out (layout `to`) = in (layout `from`): the same fields in another block order.
 // Parity is a property of the site, so only the index within the parity changes.
 template <class S>

@@ -1449,13 +1449,11 @@ const char* psms_last_error(const psms_ctx* c) { return c ? c->err.c_str() : "nu
 
 unsigned long long psms_device_bytes(const psms_ctx* c) { return c ? (unsigned long long)c->held : 0ull; }
 
-psms_status psms_gauge_load(psms_ctx* c, int slot, const double* U) {
-  API_BEGIN(c)
-  REQUIRE(slot >= 0 && slot < 64, "slot out of range");
-  REQUIRE(U != nullptr, "null gauge field");
+// Loads the device field dU (boundary layout) into slot: internal FP64 and 12-real copies
+// in every layout, outer-face links removed, unitarity checked. Returns PSMS_ENOTSU3 (the
+// FP64 copy still loaded) for links that are not SU(3).
+static psms_status load_links(psms_ctx* c, int slot, const double* dU) {
   Slot& s = c->slots[slot];
-  size_t nd = size_t(c->V) * 4 * 18;
-  const double* dU = stage_in(c, U, nd, "stage_gauge");
   if (!s.f64) s.f64 = dev_alloc(c, size_t(c->V) * 4 * 9 * 16);
   if (!s.c12) s.c12 = dev_alloc(c, size_t(c->V) * 4 * 3 * 16);
   launch_pack_links(c->st, c->g, dU, s.f64, LK_F64);
@@ -1493,6 +1491,111 @@ psms_status psms_gauge_load(psms_ctx* c, int slot, const double* U) {
     c->err = "gauge field deviates from SU(3) by " + std::to_string(dev) + "; mixed precision disabled for this slot";
     return PSMS_ENOTSU3;
   }
+  return PSMS_OK;
+}
+
+psms_status psms_gauge_load(psms_ctx* c, int slot, const double* U) {
+  API_BEGIN(c)
+  REQUIRE(slot >= 0 && slot < 64, "slot out of range");
+  REQUIRE(U != nullptr, "null gauge field");
+  const double* dU = stage_in(c, U, size_t(c->V) * 4 * 18, "stage_gauge");
+  return load_links(c, slot, dU);
+  API_END(c)
+  return PSMS_OK;
+}
+
+void psms_default_gf_params(psms_gf_params* p) {
+  if (!p) return;
+  p->alpha = 0.15;
+  p->alpha_min = 0.10;
+  p->theta_tol = 1e-3;
+  p->max_iter = 1000;
+}
+
+psms_status psms_relative_gauge_fix(psms_ctx* c, int slot_U, int slot_Up, const psms_gf_params* gp, int slot_gU,
+                                    int slot_gUp, double* g_out, psms_gf_stats* stats) {
+  API_BEGIN(c)
+  psms_gf_params def;
+  psms_default_gf_params(&def);
+  const psms_gf_params& P = gp ? *gp : def;
+  REQUIRE(P.alpha > 0 && P.alpha_min > 0 && P.alpha_min <= P.alpha && P.max_iter >= 0 && P.theta_tol >= 0,
+          "bad gauge-fixing parameters");
+  for (int sl : {slot_U, slot_Up, slot_gU, slot_gUp}) REQUIRE(sl >= 0 && sl < 64, "slot out of range");
+  REQUIRE(c->slots[slot_U].loaded && c->slots[slot_Up].loaded, "gauge slot not loaded");
+  REQUIRE(slot_gU != slot_gUp, "the two output slots must differ");
+  REQUIRE(!c->g.ob[0], "relative gauge fixing takes a context without outer blocks");
+  const Geo& g = c->g;
+  const size_t nl = size_t(c->V) * 4 * 18, ns = size_t(c->V) * 18;
+  double* U = dscratch<double>(c, "gf_U", nl);
+  double* Up = dscratch<double>(c, "gf_Up", nl);
+  double* Upc = dscratch<double>(c, "gf_Upc", nl);
+  double* Upt = dscratch<double>(c, "gf_Upt", nl);
+  double* K = dscratch<double>(c, "gf_K", ns);
+  double* G = dscratch<double>(c, "gf_G", ns);
+  double* gf = dscratch<double>(c, "gf_g", ns);
+  const int np = gf_partials(g);
+  double* part = dscratch<double>(c, "gf_part", np);
+  launch_gf_unpack(c->st, g, c->slots[slot_U].f64, U);
+  launch_gf_unpack(c->st, g, c->slots[slot_Up].f64, Up);
+  HIPCHK(hipMemcpyAsync(Upc, Up, nl * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  launch_gf_eye(c->st, g, G);
+  long long ndom = 1;
+  for (int m = 0; m < 4; ++m) ndom *= std::max(0, g.b[m] - 2);
+  ndom *= g.nblk;
+  auto total = [&](void) {
+    std::vector<double> h = to_host(c, part, np);
+    double t = 0.0;
+    for (double v : h) t += v;
+    return t;
+  };
+  const double norm = 12.0 * c->V;
+  launch_gf_overlap(c->st, g, U, Upc, part);
+  double f = (norm - total()) / norm;
+  psms_gf_stats st{0, f, f, 0.0, P.alpha};
+  double alpha = P.alpha;
+  int it = 0;
+  while (ndom > 0 && it < P.max_iter) {
+    launch_gf_step(c->st, g, U, Upc, K, 0.5 * alpha, part);
+    const double th = total() / double(ndom);
+    st.theta_end = th;
+    if (th < P.theta_tol) break;
+    launch_gf_trial(c->st, g, U, Upc, K, Upt, part);
+    const double fn = (norm - total()) / norm;
+    ++it;
+    if (fn > f) {
+      // the step raised eq. relgf: rejected, alpha lowered by 0.01 down to alpha_min
+      if (alpha - 0.01 < P.alpha_min - 1e-12) break;
+      alpha -= 0.01;
+      continue;
+    }
+    std::swap(Upc, Upt);
+    f = fn;
+    launch_gf_accept(c->st, g, G, K);
+  }
+  // Upc/Upt were swapped on the host only: keep the buffer names pointing where they were
+  c->bufs["gf_Upc"].p = Upc;
+  c->bufs["gf_Upt"].p = Upt;
+  st.iterations = it;
+  st.functional_end = f;
+  st.alpha_end = alpha;
+  // g = G^(1/2), then the fixed pair into the output slots (U and Upt hold them in turn)
+  double* Ug = Upt;
+  double* Upg = dscratch<double>(c, "gf_Upg", nl);
+  launch_gf_finish(c->st, g, G, gf, U, Up, Ug, Upg);
+  HIPCHK(hipGetLastError());
+  psms_status s1 = load_links(c, slot_gU, Ug);
+  psms_status s2 = load_links(c, slot_gUp, Upg);
+  if (g_out) {
+    if (is_device_ptr(g_out)) {
+      HIPCHK(hipMemcpyAsync(g_out, gf, ns * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    } else {
+      HIPCHK(hipMemcpyAsync(g_out, gf, ns * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (stats) *stats = st;
+  if (s1 != PSMS_OK) return s1;
+  if (s2 != PSMS_OK) return s2;
   API_END(c)
   return PSMS_OK;
 }
@@ -2077,6 +2180,144 @@ psms_status psms_logdet_ratio_blocks(psms_ctx* c, int slot_U, const int* slot_Up
     return PSMS_ENOTCONV;
   }
   API_END(c)
+  return PSMS_OK;
+}
+
+void psms_default_filter_params(psms_filter_params* p) {
+  if (!p) return;
+  p->beta[0] = 1.0;
+  p->beta[1] = 0.0;
+  p->beta[2] = 0.0;
+  psms_default_params(&p->solve);
+  p->work_slot[0] = 62;
+  p->work_slot[1] = 63;
+  p->slot_out = -1;
+}
+
+psms_status psms_filter_step(psms_ctx* in, psms_ctx* out, int slot_U, int slot_Up, const psms_filter_params* fp,
+                             const double* uniforms, const double* noise, psms_filter_result* res) {
+  if (!in || !out) return PSMS_EINVAL;
+  API_BEGIN(out)
+  REQUIRE(fp && uniforms && noise && res, "null argument");
+  const Geo& gi = in->g;
+  const Geo& go = out->g;
+  REQUIRE(gi.ob[0] > 0 && !go.ob[0], "the first context needs outer blocks, the second none");
+  for (int m = 0; m < 4; ++m) {
+    REQUIRE(gi.L[m] == go.L[m], "the two contexts must share the lattice");
+    REQUIRE(gi.ob[m] == go.b[m], "the outer blocks of the first context must be the blocks of the second");
+  }
+  REQUIRE(in->geom.kappa == out->geom.kappa && in->geom.antiperiodic_t == out->geom.antiperiodic_t &&
+              in->device == out->device && in->st == out->st,
+          "the two contexts must share kappa, boundary conditions, device and stream");
+  REQUIRE(std::fabs(fp->beta[0] + fp->beta[1] + fp->beta[2] - 1.0) < 1e-12,
+          "the beta coefficients of the block-determinant action must sum to 1 (App. C)");
+  const int w1 = fp->work_slot[0], w2 = fp->work_slot[1];
+  for (int sl : {slot_U, slot_Up, w1, w2}) REQUIRE(sl >= 0 && sl < 64, "slot out of range");
+  REQUIRE(w1 != w2 && w1 != slot_U && w1 != slot_Up && w2 != slot_U && w2 != slot_Up, "work slots must be free");
+  for (psms_ctx* c : {in, out})
+    REQUIRE(c->slots[slot_U].loaded && c->slots[slot_Up].loaded, "U and U' must be loaded in both contexts");
+  const int nsmall = gi.nblk, nouter = go.nblk;
+  // lexicographic outer block of each lexicographic small block
+  std::vector<int> small_outer(nsmall);
+  for (int lex = 0; lex < nsmall; ++lex) {
+    int B[4], r = lex, O[4];
+    for (int m = 3; m >= 0; --m) {
+      B[m] = r % gi.NB[m];
+      r /= gi.NB[m];
+    }
+    for (int m = 0; m < 4; ++m) O[m] = B[m] * gi.b[m] / gi.ob[m];
+    small_outer[lex] = ((O[0] * go.NB[1] + O[1]) * go.NB[2] + O[2]) * go.NB[3] + O[3];
+  }
+  const double* u1 = uniforms;
+  const double* u2 = uniforms + nsmall;
+  const double u3 = uniforms[nsmall + nouter];
+  // step 1: exact block filter on the smallest blocks
+  std::vector<double> ld(size_t(2) * nsmall * 2);
+  const int pair[2] = {slot_U, slot_Up};
+  psms_status s = psms_block_logdet(in, pair, 2, ld.data());
+  if (s != PSMS_OK) {
+    out->err = std::string("block filter: ") + in->err;
+    return s;
+  }
+  std::vector<double> dS1(nsmall);
+  std::vector<int> a1(nsmall);
+  for (int k = 0; k < nsmall; ++k) {
+    dS1[k] = -2.0 * (ld[(size_t(nsmall) + k) * 2] - ld[size_t(k) * 2]);
+    const double d = fp->beta[0] * dS1[k];
+    a1[k] = u1[k] < std::exp(-d) ? 1 : 0;
+    if (res->delta1) res->delta1[k] = d;
+    if (res->accept1) res->accept1[k] = a1[k];
+  }
+  // the fields in the boundary layout (from the context without outer blocks: uncut links)
+  const size_t nl = size_t(out->V) * 4 * 18;
+  double* U = dscratch<double>(out, "flt_U", nl);
+  double* Up = dscratch<double>(out, "flt_Up", nl);
+  double* U1 = dscratch<double>(out, "flt_U1", nl);
+  double* U2 = dscratch<double>(out, "flt_U2", nl);
+  int* acc = dscratch<int>(out, "flt_acc", std::max(nsmall, nouter));
+  const int np = gf_partials(go);
+  double* part = dscratch<double>(out, "flt_part", np);
+  launch_gf_unpack(out->st, go, out->slots[slot_U].f64, U);
+  launch_gf_unpack(out->st, go, out->slots[slot_Up].f64, Up);
+  launch_change_across(out->st, go, gi.b, U, Up, part);
+  {
+    std::vector<double> h = to_host(out, part, np);
+    double m = 0.0;
+    for (double v : h) m = (v > m || v != v) ? v : m;
+    REQUIRE(m == 0.0, "the proposal changes links between the smallest blocks (the block filters would not decouple)");
+  }
+  HIPCHK(hipMemcpyAsync(acc, a1.data(), sizeof(int) * nsmall, hipMemcpyHostToDevice, out->st));
+  launch_merge_links(out->st, go, gi.b, acc, U, Up, U1);
+  HIPCHK(hipStreamSynchronize(out->st));  // a1 is read by the merge before it goes out of use
+  s = load_links(in, w1, U1);
+  if (s != PSMS_OK && s != PSMS_ENOTSU3) return s;
+  s = load_links(out, w1, U1);
+  if (s != PSMS_OK && s != PSMS_ENOTSU3) return s;
+  // step 2: block-Schur filter per outer block, one noise field
+  std::vector<double> dS2(nouter);
+  psms_solve_stats st2{}, st3{};
+  s = psms_logdet_ratio_blocks(in, slot_U, &w1, 1, noise, 1, &fp->solve, dS2.data(), &st2);
+  if (s != PSMS_OK) {
+    out->err = std::string("block-Schur filter: ") + in->err;
+    return s;
+  }
+  std::vector<double> blk_sum(nouter, 0.0);
+  for (int k = 0; k < nsmall; ++k)
+    if (a1[k]) blk_sum[small_outer[k]] += dS1[k];
+  std::vector<int> a2(nouter);
+  for (int b = 0; b < nouter; ++b) {
+    const double d = dS2[b] + fp->beta[1] * blk_sum[b];
+    a2[b] = u2[b] < std::exp(-d) ? 1 : 0;
+    if (res->delta2) res->delta2[b] = d;
+    if (res->accept2) res->accept2[b] = a2[b];
+  }
+  HIPCHK(hipMemcpyAsync(acc, a2.data(), sizeof(int) * nouter, hipMemcpyHostToDevice, out->st));
+  launch_merge_links(out->st, go, go.b, acc, U, U1, U2);
+  HIPCHK(hipStreamSynchronize(out->st));
+  s = load_links(out, w2, U2);
+  if (s != PSMS_OK && s != PSMS_ENOTSU3) return s;
+  // step 3: global Schur filter of the outer blocks' decomposition, one noise field
+  double dS3 = 0.0;
+  s = psms_logdet_ratio(out, PSMS_OP_SCHUR, slot_U, &w2, 1, noise + size_t(out->V) * 24, 1, 1, &fp->solve, &dS3, &st3);
+  if (s != PSMS_OK) return s;
+  double blk_all = 0.0;
+  for (int k = 0; k < nsmall; ++k)
+    if (a1[k] && a2[small_outer[k]]) blk_all += dS1[k];
+  const double d3 = dS3 + fp->beta[2] * blk_all;
+  const int a3 = u3 < std::exp(-d3) ? 1 : 0;
+  res->delta3 = d3;
+  res->accept3 = a3;
+  res->inner_iters = st2.inner_iters + st3.inner_iters;
+  if (fp->slot_out >= 0) {
+    REQUIRE(fp->slot_out < 64, "slot_out out of range");
+    const double* fin = a3 ? U2 : U;
+    s = load_links(in, fp->slot_out, fin);
+    if (s != PSMS_OK && s != PSMS_ENOTSU3) return s;
+    s = load_links(out, fp->slot_out, fin);
+    if (s != PSMS_OK && s != PSMS_ENOTSU3) return s;
+  }
+  HIPCHK(hipStreamSynchronize(out->st));
+  API_END(out)
   return PSMS_OK;
 }
 

@@ -52,6 +52,27 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GfParams(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("alpha_min", C.c_double), ("theta_tol", C.c_double), ("max_iter", C.c_int)]
+
+
+class GfStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("functional_start", C.c_double), ("functional_end", C.c_double),
+                ("theta_end", C.c_double), ("alpha_end", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FilterParams(C.Structure):
+    _fields_ = [("beta", C.c_double * 3), ("solve", SolveParams), ("work_slot", C.c_int * 2), ("slot_out", C.c_int)]
+
+
+class FilterResult(C.Structure):
+    _fields_ = [("delta1", C.c_void_p), ("accept1", C.c_void_p), ("delta2", C.c_void_p), ("accept2", C.c_void_p),
+                ("delta3", C.c_double), ("accept3", C.c_int), ("inner_iters", C.c_int)]
+
+
 class TrainParams(C.Structure):
     _fields_ = [("npairs", C.c_int), ("batch", C.c_int), ("epochs", C.c_int), ("chunk", C.c_int), ("lr", C.c_double),
                 ("solve_tol", C.c_double), ("seed", C.c_ulonglong), ("ckpt_path", C.c_char_p), ("ckpt_every", C.c_int)]
@@ -92,6 +113,12 @@ _SIGS = {
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "psms_log_ratio_estimate": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "psms_block_logdet": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "psms_default_gf_params": (None, [C.c_void_p]),
+    "psms_default_filter_params": (None, [C.c_void_p]),
+    "psms_filter_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    "psms_relative_gauge_fix": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                          C.c_void_p]),
     "psms_logdet_ratio_blocks": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
                                            C.c_void_p, C.c_void_p]),
     "psms_net_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_ulonglong, C.c_double]),
@@ -157,6 +184,36 @@ def log_ratio_estimate(delta) -> np.ndarray:
     if s != 0:
         raise PsmsError(s, "psms_log_ratio_estimate: null, empty or non-finite input")
     return out
+
+
+def filter_step(inner: "Context", outer: "Context", slot_U: int, slot_Up: int, uniforms, noise, beta=(1.0, 0.0, 0.0),
+                solve: SolveParams | None = None, work_slots=(62, 63), slot_out: int = -1) -> dict:
+    """psms_filter_step: the three filters of one recursion level; returns the exponents
+    and decisions of every step."""
+    lib = load_library()
+    p = FilterParams()
+    lib.psms_default_filter_params(C.byref(p))
+    p.beta[:] = list(beta)
+    if solve is not None:
+        p.solve = solve
+    p.work_slot[:] = list(work_slots)
+    p.slot_out = slot_out
+    nsmall = int(np.prod(np.asarray(inner.L) // np.asarray(inner.b)))
+    nouter = int(np.prod(np.asarray(outer.L) // np.asarray(outer.b)))
+    u = np.ascontiguousarray(np.asarray(uniforms, np.float64))
+    if u.size != nsmall + nouter + 1:
+        raise ValueError(f"uniforms must hold {nsmall} + {nouter} + 1 values")
+    d1, a1 = np.empty(nsmall), np.empty(nsmall, np.int32)
+    d2, a2 = np.empty(nouter), np.empty(nouter, np.int32)
+    r = FilterResult()
+    r.delta1, r.accept1 = d1.ctypes.data, a1.ctypes.data
+    r.delta2, r.accept2 = d2.ctypes.data, a2.ctypes.data
+    s = lib.psms_filter_step(inner._h, outer._h, slot_U, slot_Up, C.byref(p), C.c_void_p(u.ctypes.data), _ptr(noise),
+                             C.byref(r))
+    if s != 0:
+        raise PsmsError(s, lib.psms_last_error(outer._h).decode())
+    return {"delta1": d1, "accept1": a1.astype(bool), "delta2": d2, "accept2": a2.astype(bool), "delta3": r.delta3,
+            "accept3": bool(r.accept3), "inner_iters": r.inner_iters}
 
 
 def _is_torch(a) -> bool:
@@ -334,6 +391,18 @@ class Context:
         if check:
             self._check(s)
         return delta, st.as_dict()
+
+    def relative_gauge_fix(self, slot_U: int, slot_Up: int, slot_gU: int, slot_gUp: int, want_g: bool = False, **kw):
+        """psms_relative_gauge_fix; returns (g [V,3,3] complex or None, stats)."""
+        p = GfParams()
+        self._lib.psms_default_gf_params(C.byref(p))
+        for k, v in kw.items():
+            setattr(p, k, v)
+        g = np.empty((self.V, 3, 3), np.complex128) if want_g else None
+        st = GfStats()
+        self._check(self._lib.psms_relative_gauge_fix(self._h, slot_U, slot_Up, C.byref(p), slot_gU, slot_gUp,
+                                                      C.c_void_p(g.ctypes.data) if want_g else None, C.byref(st)))
+        return g, st.as_dict()
 
     def n_outer(self) -> int:
         return int(np.prod(np.asarray(self.L) // np.asarray(self.outer_b))) if self.outer_b else 0
