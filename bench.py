@@ -484,19 +484,22 @@ def main():
     ctx.close()
     torch.cuda.empty_cache()
 
-    # plain FP64 on the same batch, in a fresh context (its Krylov basis is FP64)
-    _, ctxp, _, _, _, _ = setup(args.workload, inputs=(w, inputs[1], inputs[2], inputs[3][:0]))
-    for k, v in tune.items():
-        ctxp.set_tuning(k, v)
+    # plain FP64 on the same batch, in a fresh context (its Krylov basis is FP64);
+    # --plain-steps 0 skips it (profiling runs of the headline step alone)
     plain = mode_params(psms, "plain", w["tol"], args.workload)
     plain.rhs_chunk = args.plain_rhs_chunk
-    dtp, stp, _, d_plain = run_steps(psms, ctxp, noise, delta, nprop, plain, args.plain_steps, 0)
-    s_plain = dtp / args.plain_steps / nest
-    log(f"plain f64: {1e3 * dtp / args.plain_steps:.2f} ms/step, solver {stp[-1]}")
-    if learned and d_learned is not None and "error" not in learned:
-        learned["max_abs_delta_diff_vs_plain"] = float(np.abs(d_learned - d_plain[:d_learned.shape[0],
-                                                                                   :d_learned.shape[1]]).max())
-    ctxp.close()
+    s_plain, stp, d_plain = None, [None], None
+    if args.plain_steps > 0:
+        _, ctxp, _, _, _, _ = setup(args.workload, inputs=(w, inputs[1], inputs[2], inputs[3][:0]))
+        for k, v in tune.items():
+            ctxp.set_tuning(k, v)
+        dtp, stp, _, d_plain = run_steps(psms, ctxp, noise, delta, nprop, plain, args.plain_steps, 0)
+        s_plain = dtp / args.plain_steps / nest
+        log(f"plain f64: {1e3 * dtp / args.plain_steps:.2f} ms/step, solver {stp[-1]}")
+        if learned and d_learned is not None and "error" not in learned:
+            learned["max_abs_delta_diff_vs_plain"] = float(np.abs(d_learned - d_plain[:d_learned.shape[0],
+                                                                                       :d_learned.shape[1]]).max())
+        ctxp.close()
     del noise, delta
     torch.cuda.empty_cache()
 
@@ -566,11 +569,12 @@ def main():
                                "plain_cycles": plain.sap_cycles, "plain_block_iters": plain.block_iters}},
         "plain_f64_s_per_estimate": s_plain,
         "plain_f64_rhs_chunk": args.plain_rhs_chunk,
-        "speedup_vs_plain_f64": s_plain / value,
-        "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()),
+        "speedup_vs_plain_f64": s_plain / value if s_plain else None,
+        "max_abs_delta_diff_vs_plain": float(np.abs(d_fast - d_plain).max()) if d_plain is not None else None,
         # ln mean_j exp(-Delta_pj) per proposal, from the same noise in both modes
         "log_ratio_estimate": {"fast": [round(float(v), 8) for v in psms.log_ratio_estimate(d_fast)],
-                               "plain": [round(float(v), 8) for v in psms.log_ratio_estimate(d_plain)]},
+                               "plain": ([round(float(v), 8) for v in psms.log_ratio_estimate(d_plain)]
+                                         if d_plain is not None else None)},
         "learned": learned,
         "batched": batched,
         "interpolation": interp,

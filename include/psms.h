@@ -359,7 +359,9 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
 /* Launch tuning of the context. Keys: "dslash_variant_f64", "dslash_variant_f32",
  * "dslash_variant_bf16" (full-lattice stencil form, 0..5: one lane or two wave groups
  * per site, times three register budgets; 6: four lanes per site; 7: one workgroup per
- * block of at most 256 sites with the block's input spinor in LDS, other blocks as 0),
+ * block of at most 256 sites with the block's input spinor in LDS; 8: as 7, with every
+ * link read once per block and the backward hops passed between sites in LDS; 7 and 8
+ * run other block sizes as 0),
  * "nr_f64", "nr_low" (right-hand sides per
  * stencil thread: 1, 2 or 4), "xcd_map" (1: each XCD sweeps a contiguous range of
  * tiles), "net_mfma" (1: network channel mixing on the matrix cores in bf16, 0: FP32 on
@@ -377,7 +379,12 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
  * 2; FP64 block solves always use 2) and "block_tol_prec" (block inverses to tolerance in
  * a mixed-precision solve with SU(3) links: 1 FP32 block passes inside FP64 defect
  * correction, 2 FP64 block solves, 0, the default, FP32 passes for blocks of more than
- * 256 sites and FP64 for smaller ones).
+ * 256 sites and FP64 for smaller ones) and "sap_bf16" (mixed precision with a BF16 Krylov
+ * basis: 1, the default, keeps the Schwarz preconditioner's residual, iterate and
+ * corrections in BF16, 0 in FP32) and "block_xcd" (block-solver launches: 1 runs the
+ * right-hand sides of one block back to back on one XCD, which then serves their link
+ * reads from its L2, and gives each XCD a contiguous range of blocks; 0 the launch order;
+ * 2, the default, 1 when the links the launch reads exceed the 256 MB Infinity Cache).
  * Unknown keys or values give
  * PSMS_EINVAL. Results do not depend on the tuning beyond rounding; only speed does. */
 psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);

@@ -325,9 +325,13 @@ template <class T, class P> __device__ __forceinline__ void hop_fwd(int mu, cons
   }
 }
 
-// acc += c * U(x-mu,mu)^+ (1 + gamma_mu) psi   (psi = psi(x-mu))
-template <class T, class P> __device__ __forceinline__ void hop_bwd(int mu, const SU3<T>& U, const P& p, T c, Spinor<T>& acc) {
-  cx<T> h0[3], h1[3], w0[3], w1[3];
+// The backward hop in two halves, so that the site that owns the link and the spinor
+// can compute the colour part and hand it to its +mu neighbour:
+//   bwd_half:  w0, w1 = U^+ times the two independent rows of (1 + gamma_mu) psi;
+//   bwd_recon: acc += c * (the full spinor those two rows determine).
+template <class T, class P>
+__device__ __forceinline__ void bwd_half(int mu, const SU3<T>& U, const P& p, cx<T> (&w0)[3], cx<T> (&w1)[3]) {
+  cx<T> h0[3], h1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     switch (mu) {
@@ -339,6 +343,9 @@ template <class T, class P> __device__ __forceinline__ void hop_bwd(int mu, cons
   }
   su3_dag_mul(U, h0, w0);
   su3_dag_mul(U, h1, w1);
+}
+template <class T>
+__device__ __forceinline__ void bwd_recon(int mu, cx<T> (&w0)[3], cx<T> (&w1)[3], T c, Spinor<T>& acc) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     w0[a] = scale(c, w0[a]);
@@ -352,6 +359,13 @@ template <class T, class P> __device__ __forceinline__ void hop_bwd(int mu, cons
       default: acc.v[2][a] = acc.v[2][a] + times_i(w0[a]); acc.v[3][a] = acc.v[3][a] - times_i(w1[a]); break;
     }
   }
+}
+
+// acc += c * U(x-mu,mu)^+ (1 + gamma_mu) psi   (psi = psi(x-mu))
+template <class T, class P> __device__ __forceinline__ void hop_bwd(int mu, const SU3<T>& U, const P& p, T c, Spinor<T>& acc) {
+  cx<T> w0[3], w1[3];
+  bwd_half(mu, U, p, w0, w1);
+  bwd_recon(mu, w0, w1, c, acc);
 }
 
 // ----------------------------------------------------------------- reductions

@@ -59,6 +59,7 @@ struct DslashParams {
 // Scratch bytes per lane (register spills) of the kernel that stencil form v runs for
 // input storage `in` and output storage `out` (F64 and F32 forms map to themselves;
 // BF16 input to BF16 or F32 output); 0 when the runtime does not say.
+constexpr int NVAR = 9;  // full-lattice stencil forms 0 .. NVAR - 1
 size_t dslash_variant_scratch(Prec in, Prec out, int v);
 void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int linkfmt, const FieldBatch& in,
                    const FieldBatch& out, const DslashParams& dp, int nr_pref);
@@ -149,6 +150,7 @@ struct BlockMRParams {
   const void* rho_in = nullptr;  // non-null: initial rho read from here (rho is still written)
   int x_assign = 0;              // 1: x = delta instead of x += delta
   int eo_lanes = 0;              // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
+  int xcd_map = 0;               // 1: the right-hand sides of one block run back to back on one XCD
 };
 // For every block of the colour: (optionally) the face update of rho_b from the
 // other colour's delta, then delta = MR approximation of D_b^-1 rho_b, x += delta,

@@ -26,8 +26,29 @@ struct BlockArgs {
   const void* rho_in;  // non-null: read the initial rho from here (same shape) instead of rho
   int x_assign;        // 1: x = delta instead of x += delta (x need not be initialised)
   int eo_lanes;        // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
+  int xcd_map;         // 1: workgroup order by XCD (block_coord)
   int* iters;
 };
+
+// Workgroup -> (block, right-hand side, proposal). The grid is (blocks of the colour,
+// right-hand sides, proposals), and workgroups are dealt to the 8 XCDs in turn, in the
+// order of their linear index w. With xcd_map, w is read as XCD w % 8 and position
+// w / 8 on it: consecutive positions on one XCD are the right-hand sides of one block,
+// which hop over the same links, so those reads meet in that XCD's L2; each XCD takes
+// a contiguous range of (proposal, block) pairs, whose faces neighbour each other.
+struct BlockCoord {
+  int blk, rhs, prop;
+};
+__device__ __forceinline__ BlockCoord block_coord(const BlockArgs& a) {
+  const int nb = gridDim.x, nr = gridDim.y, np = gridDim.z;
+  if (a.xcd_map && ((nb * np) & 7) == 0) {
+    const int w = blockIdx.x + nb * (blockIdx.y + nr * blockIdx.z);
+    const int i = w >> 3;
+    const int q = (w & 7) * ((nb * np) >> 3) + i / nr;
+    return {a.colour * a.g.nblk_c + q % nb, i % nr, q / nb};
+  }
+  return {a.colour * a.g.nblk_c + int(blockIdx.x), int(blockIdx.y), int(blockIdx.z)};
+}
 
 // Schwarz residual update across the faces of a block of colour c:
 // rho_c -= D_{c,c'} delta_c', i.e. acc += kappa * (the hops of site (p, s) that
@@ -136,9 +157,10 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   double* sm = sm3[0];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
-  const int blk = a.colour * g.nblk_c + blockIdx.x;
-  const int prop = blockIdx.z;
-  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  const BlockCoord bc = block_coord(a);
+  const int blk = bc.blk;
+  const int prop = bc.prop;
+  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
   const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
@@ -271,9 +293,10 @@ __global__ void __launch_bounds__(256) k_block_mr_eo_g(BlockArgs a) {
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
-  const int blk = a.colour * g.nblk_c + blockIdx.x;
-  const int prop = blockIdx.z;
-  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  const BlockCoord bc = block_coord(a);
+  const int blk = bc.blk;
+  const int prop = bc.prop;
+  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
   const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
@@ -420,9 +443,10 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
-  const int blk = a.colour * g.nblk_c + blockIdx.x;
-  const int prop = blockIdx.z;
-  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  const BlockCoord bc = block_coord(a);
+  const int blk = bc.blk;
+  const int prop = bc.prop;
+  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
   const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
@@ -570,9 +594,10 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
-  const int blk = a.colour * g.nblk_c + blockIdx.x;
-  const int prop = blockIdx.z;
-  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  const BlockCoord bc = block_coord(a);
+  const int blk = bc.blk;
+  const int prop = bc.prop;
+  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
   const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
@@ -724,19 +749,19 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
 template <class S, class LK, class T, bool STAGE = true>
 __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   constexpr int H = 128;  // sites per parity
-  // STAGE: 12-real links staged in LDS (98 KB, one workgroup per CU); otherwise read
-  // from L2 at each hop (49 KB, two workgroups per CU)
+  // STAGE: 12-real links staged in LDS (73 KB in FP32, two workgroups per CU); otherwise
+  // read from L2 at each hop (24 KB)
   constexpr bool LL = LdsLinks<LK>::on && STAGE;
-  __shared__ cx<T> ev[12][H];     // an even-site field
-  __shared__ cx<T> od[2][12][H];  // odd-site partial sums of the two lanes
-  __shared__ cx<T> eb[12][H];     // even-site partial sum of lane 1
+  __shared__ cx<T> ev[12][H];  // an even-site field; after a hop phase, lane 1's even partial sum
+  __shared__ cx<T> od[12][H];  // an odd-site field (the two lanes' hop sums, added in turn)
   __shared__ float4 lk_lds[LL ? 12 : 1][LL ? 2 * H : 1];
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
-  const int blk = a.colour * g.nblk_c + blockIdx.x;
-  const int prop = blockIdx.z;
-  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  const BlockCoord bc = block_coord(a);
+  const int blk = bc.blk;
+  const int prop = bc.prop;
+  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
   const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
@@ -807,8 +832,8 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
       }
     }
   };
-  // this lane's hops of the even site j, applied to od[0] (+ od[1])
-  auto phase_even = [&](T c, bool both, Spinor<T>& acc) {
+  // this lane's hops of the even site j, applied to od
+  auto phase_even = [&](T c, Spinor<T>& acc) {
     zero(acc);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
@@ -819,7 +844,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
         else link(mu, 1, q, gB[mu], U);
         Spinor<T> nb;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = both ? od[0][k][q] + od[1][k][q] : od[0][k][q];
+        for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = od[k][q];
         if (h == 0) hop_fwd(mu, U, nb, c, acc);
         else hop_bwd(mu, U, nb, c, acc);
       }
@@ -842,18 +867,18 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   // even right-hand side rho_e + k H_eo rho_o (lane 0); lane 1 keeps rho_o
   if (h == 1) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) od[0][k][j] = r.v[k / 3][k % 3];
+    for (int k = 0; k < 12; ++k) od[k][j] = r.v[k / 3][k % 3];
   }
   __syncthreads();
-  phase_even(kp, false, acc);
+  phase_even(kp, acc);
   if (h == 1) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) eb[k][j] = acc.v[k / 3][k % 3];
+    for (int k = 0; k < 12; ++k) ev[k][j] = acc.v[k / 3][k % 3];
   }
   __syncthreads();
   if (h == 0) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) r.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + eb[k][j];
+    for (int k = 0; k < 12; ++k) r.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + ev[k][j];
   }
 
   int it = 0;
@@ -866,19 +891,26 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
       }
       __syncthreads();
       phase_odd(kp, acc);
+      if (h == 0) {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) od[h][k][j] = acc.v[k / 3][k % 3];
+        for (int k = 0; k < 12; ++k) od[k][j] = acc.v[k / 3][k % 3];
+      }
       __syncthreads();
-      phase_even(mk, true, acc);
       if (h == 1) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) eb[k][j] = acc.v[k / 3][k % 3];
+        for (int k = 0; k < 12; ++k) od[k][j] = od[k][j] + acc.v[k / 3][k % 3];
+      }
+      __syncthreads();
+      phase_even(mk, acc);
+      if (h == 1) {  // ev is free: every read of it was in phase_odd
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ev[k][j] = acc.v[k / 3][k % 3];
       }
       __syncthreads();
       double prr = 0.0, pri = 0.0, pp = 0.0;
       if (h == 0) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + eb[k][j];
+        for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + ev[k][j];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -919,13 +951,15 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   }
   __syncthreads();
   phase_odd(kp, acc);
+  if (h == 0) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) od[h][k][j] = acc.v[k / 3][k % 3];
+    for (int k = 0; k < 12; ++k) od[k][j] = acc.v[k / 3][k % 3];
+  }
   __syncthreads();
   if (h == 1) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      d.v[k / 3][k % 3] = r.v[k / 3][k % 3] + od[0][k][j] + od[1][k][j];
+      d.v[k / 3][k % 3] = r.v[k / 3][k % 3] + od[k][j] + acc.v[k / 3][k % 3];
       r.v[k / 3][k % 3] = {T(0), T(0)};
     }
   }
@@ -966,9 +1000,10 @@ __global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
-  const int blk = a.colour * g.nblk_c + blockIdx.x;
-  const int prop = blockIdx.z;
-  const size_t roff = size_t(prop * a.nrhs + blockIdx.y) * a.rhs_stride;
+  const BlockCoord bc = block_coord(a);
+  const int blk = bc.blk;
+  const int prop = bc.prop;
+  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
   const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
@@ -1276,6 +1311,7 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
   a.rho_in = bp.rho_in;
   a.x_assign = bp.x_assign;
   a.eo_lanes = bp.eo_lanes;
+  a.xcd_map = bp.xcd_map;
   a.iters = iters_out;
   if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);
   else if (rho.prec == P_F32 && linkfmt == LK_F32C12) block_go<StF32, LkF32C12, float>(st, a, rho.nprop);

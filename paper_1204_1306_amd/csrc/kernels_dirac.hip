@@ -344,6 +344,26 @@ static void dslash_quad_go(hipStream_t st, const DslashArgs& a, int nprop) {
   launch_timed((k_dslash_quad<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
 }
 
+// Workgroup -> (position in the block schedule, right-hand side, proposal) for the
+// one-workgroup-per-block forms (7, 8), whose grid is (blocks, right-hand sides,
+// proposals). Workgroups go to the 8 XCDs in turn by linear index w; with xcd_map, w
+// is read as XCD w % 8 and position w / 8 on it: each XCD takes a contiguous range of
+// the schedule and runs the right-hand sides of one block back to back, so that they
+// find that block's links in its L2.
+struct TileCoord {
+  int q, rhs, prop;
+};
+__device__ __forceinline__ TileCoord tile_coord(const DslashArgs& a) {
+  const int nb = gridDim.x, nr = gridDim.y, np = gridDim.z;
+  if (a.xcd_map && ((nb * np) & 7) == 0) {
+    const int w = blockIdx.x + nb * (blockIdx.y + nr * blockIdx.z);
+    const int i = w >> 3;
+    const int q = (w & 7) * ((nb * np) >> 3) + i / nr;
+    return {q % nb, i % nr, q / nb};
+  }
+  return {int(blockIdx.x), int(blockIdx.y), int(blockIdx.z)};
+}
+
 // Block-tile form (variant 7) for blocks of at most 256 sites: one workgroup per block,
 // one lane per site of either parity. The block's input spinor (both parities) is read
 // once into LDS; a hop that stays in the block reads its neighbour from there and only
@@ -355,18 +375,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
   const int Vbh = g.Vbh;
-  const int nwg = gridDim.x, w = blockIdx.x;
-  const int q = (a.xcd_map && (nwg & 7) == 0) ? (w & 7) * (nwg >> 3) + (w >> 3) : w;
-  const int blk = g.border[q];
+  const TileCoord tc = tile_coord(a);
+  const int blk = g.border[tc.q];
   const int t = threadIdx.x;
   const int p = t >= Vbh ? 1 : 0;
   const int i = t - p * Vbh;
   const bool active = t < 2 * Vbh;
   const int s = blk * Vbh + i;
-  const int prop = blockIdx.z;
+  const int prop = tc.prop;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
-  const typename SI::unit* in = reinterpret_cast<const typename SI::unit*>(a.in) + size_t(prop * a.nrhs + blockIdx.y) * a.in_rhs_stride;
-  typename SO::unit* out = reinterpret_cast<typename SO::unit*>(a.out) + size_t(prop * a.nrhs + blockIdx.y) * a.out_rhs_stride;
+  const typename SI::unit* in = reinterpret_cast<const typename SI::unit*>(a.in) + size_t(prop * a.nrhs + tc.rhs) * a.in_rhs_stride;
+  typename SO::unit* out = reinterpret_cast<typename SO::unit*>(a.out) + size_t(prop * a.nrhs + tc.rhs) * a.out_rhs_stride;
 
   Spinor<T> acc;
   if (active) {
@@ -432,17 +451,129 @@ static void dslash_block_go(hipStream_t st, const DslashArgs& a, int nprop) {
   launch_timed((k_dslash_block<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
 }
 
+// Block-tile form with exchange (variant 8) for blocks of at most 256 sites: one
+// workgroup per block, one lane per site of either parity, as variant 7, but every
+// link and every in-block spinor is read from memory once per block. Direction by
+// direction, the lane of site y loads its own forward link U(y,mu) and uses it twice:
+// for its own forward hop, with psi(y + mu) read from the block's spinors in LDS, and
+// for the backward hop of its neighbour y + mu, U(y,mu)^+ (1 + gamma_mu) psi(y), whose
+// two colour vectors it leaves in LDS for that neighbour. Only the hops that leave the
+// block read from memory: the neighbour's spinor, and for a backward hop its link.
+template <class SI, class SO, class LK, class T, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k_dslash_tile(DslashArgs a) {
+  __shared__ cx<T> sp[2][12][128];  // the block's input spinor, both parities
+  __shared__ cx<T> hb[2][6][128];   // backward half spinors, by the receiving site
+  const Geo& g = a.g;
+  const size_t Vh = g.Vh;
+  const int Vbh = g.Vbh;
+  const TileCoord tc = tile_coord(a);
+  const int blk = g.border[tc.q];
+  const int t = threadIdx.x;
+  const int p = t >= Vbh ? 1 : 0;
+  const int i = t - p * Vbh;
+  const bool active = t < 2 * Vbh;
+  const int s = blk * Vbh + i;
+  const int prop = tc.prop;
+  const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
+  const typename SI::unit* in = reinterpret_cast<const typename SI::unit*>(a.in) + size_t(prop * a.nrhs + tc.rhs) * a.in_rhs_stride;
+  typename SO::unit* out = reinterpret_cast<typename SO::unit*>(a.out) + size_t(prop * a.nrhs + tc.rhs) * a.out_rhs_stride;
+  const typename SI::unit* nin = in + size_t(1 - p) * SI::NC * Vh;
+
+  Spinor<T> acc;
+  zero(acc);
+  SiteInfo si;
+  if (active) {
+    SI::load(in + size_t(p) * SI::NC * Vh, Vh, s, acc);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) sp[p][k][i] = acc.v[k / 3][k % 3];
+    const T cd = T(a.cdiag);
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.v[sc][c] = scale(cd, acc.v[sc][c]);
+    site_info(g, p, s, si);
+  }
+  const T ch = T(a.chop);
+  const LdsSpinor<T, 128> own{{sp[p], i}};
+  __syncthreads();
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    Nbr nf, nb;
+    if (active) {
+      nf = neighbour(g, si, mu, +1);
+      nb = neighbour(g, si, mu, -1);
+      SU3<T> U;
+      LK::load(lk + size_t(p * 4 + mu) * LK::NC * Vh, Vh, s, U);
+      if (!nf.cross) {
+        const int r = nf.s - blk * Vbh;
+        cx<T> w0[3], w1[3];
+        bwd_half(mu, U, own, w0, w1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          hb[1 - p][c][r] = w0[c];
+          hb[1 - p][3 + c][r] = w1[c];
+        }
+        const LdsSpinor<T, 128> v{{sp[1 - p], r}};
+        hop_fwd(mu, U, v, ch, acc);
+      } else {
+        Spinor<T> v;
+        SI::load(nin, Vh, nf.s, v);
+        hop_fwd(mu, U, v, ch * T(nf.sign), acc);
+      }
+    }
+    __syncthreads();
+    if (active) {
+      if (!nb.cross) {
+        cx<T> w0[3], w1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          w0[c] = hb[p][c][i];
+          w1[c] = hb[p][3 + c][i];
+        }
+        bwd_recon(mu, w0, w1, ch, acc);
+      } else {
+        SU3<T> U;
+        LK::load(lk + size_t((1 - p) * 4 + mu) * LK::NC * Vh, Vh, nb.s, U);
+        Spinor<T> v;
+        SI::load(nin, Vh, nb.s, v);
+        hop_bwd(mu, U, v, ch * T(nb.sign), acc);
+      }
+    }
+    if (mu < 3) __syncthreads();  // hb is written again by the next direction
+  }
+  if (!active) return;
+  typename SO::unit* op = out + size_t(p) * SO::NC * Vh;
+  if (a.accumulate) {
+    Spinor<T> d;
+    SO::load(op, Vh, s, d);
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.v[sc][c] = acc.v[sc][c] + d.v[sc][c];
+  }
+  if (a.nt_out) SO::store_nt(op, Vh, s, acc);
+  else SO::store(op, Vh, s, acc);
+}
+
+template <class SI, class SO, class LK, class T, int W>
+static void dslash_tile_go(hipStream_t st, const DslashArgs& a, int nprop) {
+  dim3 grid(a.g.nblk, a.nrhs, nprop);
+  launch_timed((k_dslash_tile<SI, SO, LK, T, W>), grid, dim3(256), 0, st, a);
+}
+
 // Full-lattice stencil variants (form x register budget), chosen by the autotuner:
 //   0: one lane per site          1: two wave groups per site
 //   2: one lane, >= 4 waves/SIMD  3: split, >= 4 waves/SIMD
 //   4: one lane, >= 6 waves/SIMD  5: split, >= 6 waves/SIMD
 //   6: four lanes per site, >= 2 waves/SIMD
 //   7: one workgroup per block of <= 256 sites, the block's input spinor in LDS
-//      (other block sizes, or part of the lattice: variant 0)
+//   8: as 7, each link read once per block and the backward hops handed on in LDS
+//      (7, 8: other block sizes, or part of the lattice: variant 0)
 template <class SI, class SO, class LK, class T>
 static void dslash_variant(hipStream_t st, const DslashArgs& a, int nprop, int v) {
-  if (v == 7 && !(2 * a.g.Vbh <= 256 && a.np == 2 && a.p0 == 0 && a.nb == a.g.nblk)) v = 0;
+  if (v >= 7 && !(2 * a.g.Vbh <= 256 && a.np == 2 && a.p0 == 0 && a.nb == a.g.nblk)) v = 0;
   switch (v) {
+    case 8: dslash_tile_go<SI, SO, LK, T, 1>(st, a, nprop); break;
     case 7: dslash_block_go<SI, SO, LK, T, 1>(st, a, nprop); break;
     case 1: dslash_split_go<SI, SO, LK, T, 1>(st, a, nprop); break;
     case 2: dslash_one_go<SI, SO, LK, T, 4>(st, a, nprop); break;
@@ -479,6 +610,7 @@ static void dslash_sel(hipStream_t st, const DslashArgs& a, int nprop, int sel, 
 template <class SI, class SO, class LK, class T>
 static const void* variant_kernel(int v) {
   switch (v) {
+    case 8: return reinterpret_cast<const void*>(&k_dslash_tile<SI, SO, LK, T, 1>);
     case 7: return reinterpret_cast<const void*>(&k_dslash_block<SI, SO, LK, T, 1>);
     case 1: return reinterpret_cast<const void*>(&k_dslash_split<SI, SO, LK, T, 1>);
     case 2: return reinterpret_cast<const void*>(&k_dslash<SI, SO, LK, T, HOP_ALL, 1, 4>);

@@ -86,6 +86,9 @@ struct psms_ctx {
   int block_eo = 2;            // LDS-resident block solver: 1 even-odd, 0 plain, 2 by launch shape
   int block_eo_lanes = 0;      // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int block_tol_prec = 0;      // mixed block inverses to tolerance: 1 FP32 passes, 2 FP64, 0 = by block size
+  int sap_bf16 = 1;            // BF16 Krylov basis: Schwarz fields in BF16 (1) or FP32 (0)
+  int block_xcd = 2;           // block launches: right-hand sides of a block back to back on one XCD
+                               // (1), launch order (0), 1 when the links exceed the Infinity Cache (2)
   // pinned host slots for the lagged convergence check of the GCR iteration
   double* pinned[2] = {nullptr, nullptr};
   size_t pinned_n = 0;
@@ -403,6 +406,15 @@ Links links_of(psms_ctx* c, const int* slots, int nprop, int fmt) {
   return L;
 }
 
+// Workgroup order of a block-solver launch over `nprop` gauge fields (tuning key
+// block_xcd). Running the right-hand sides of a block back to back on one XCD pays when
+// the links the launch reads do not stay in the 256 MB Infinity Cache between them.
+static int block_xcd_of(psms_ctx* c, int fmt, int nprop) {
+  if (c->block_xcd != 2) return c->block_xcd;
+  const double link_bytes = double(c->V) * 4 * (fmt == LK_F64 ? 144 : 48) * nprop;
+  return link_bytes > 256.0 * (1 << 20) ? 1 : 0;
+}
+
 double spinor_bytes(Prec p) { return p == P_F64 ? 192.0 : p == P_F32 ? 96.0 : 48.0; }
 double link_bytes(int fmt) { return fmt == LK_F64 ? 144.0 : 48.0; }
 
@@ -539,6 +551,7 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
       bp.face = (cy > 0 || col > 0) ? 1 : 0;
       bp.lanes = c->block_lanes;
       bp.eo_lanes = c->block_eo_lanes;
+      bp.xcd_map = block_xcd_of(c, L.fmt, np);
       bp.eo = eo_form;
       if (direct && cy == 0) {
         bp.rho_in = r.p;
@@ -840,7 +853,7 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
     double itol = pp->inner_tol;
     if (wp == P_BF16) itol = std::max(itol, 5e-3);
     GcrCfg cf{wp, P_F32, itol, restart, restart, pp->pc == PSMS_PC_NONE ? PSMS_PC_NONE : PSMS_PC_SAP,
-              SapCfg{pp->sap_cycles, pp->block_iters, P_F32}};
+              SapCfg{pp->sap_cycles, pp->block_iters, (wp == P_BF16 && c->sap_bf16) ? P_BF16 : P_F32}};
     if (use_net) {
       cf.pc = PSMS_PC_NET;
       cf.net_links = &L32;
@@ -1013,6 +1026,7 @@ double solve_colour_mixed(psms_ctx* c, const int* slots, int col, const FieldBat
       BlockMRParams bp{col, maxit - total, 1e-5, c->geom.kappa};
       bp.lanes = c->block_lanes;
       bp.eo_lanes = c->block_eo_lanes;
+      bp.xcd_map = block_xcd_of(c, L32.fmt, rho.nprop);
       bp.eo = c->block_eo != 0 ? 1 : 0;
       launch_block_mr(c->st, c->g, L32.p, L32.fmt, rho, e, dl, pb, bp, it);
     }
@@ -1100,6 +1114,7 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
     BlockMRParams bp{col, maxit, tol, c->geom.kappa};
     bp.lanes = c->block_lanes;
     bp.eo_lanes = c->block_eo_lanes;
+    bp.xcd_map = block_xcd_of(c, L.fmt, rho.nprop);
     bp.eo = c->block_eo != 0 ? 1 : 0;  // to a tolerance the even-odd form always pays
     launch_block_mr(c->st, c->g, L.p, L.fmt, rho, x, dl, pb, bp, it);
   }
@@ -2588,22 +2603,27 @@ static int* tuning_slot(psms_ctx* c, const char* key) {
   if (!std::strcmp(key, "block_eo")) return &c->block_eo;
   if (!std::strcmp(key, "block_eo_lanes")) return &c->block_eo_lanes;
   if (!std::strcmp(key, "block_tol_prec")) return &c->block_tol_prec;
+  if (!std::strcmp(key, "sap_bf16")) return &c->sap_bf16;
+  if (!std::strcmp(key, "block_xcd")) return &c->block_xcd;
   return nullptr;
 }
 static const char* tuning_keys[] = {"dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low",
                                     "xcd_map", "net_mfma", "block_solver", "block_lanes", "block_eo",
-                                    "block_eo_lanes", "block_tol_prec"};
+                                    "block_eo_lanes", "block_tol_prec", "sap_bf16", "block_xcd"};
 
 psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   API_BEGIN(c)
   REQUIRE(key != nullptr, "null key");
   int* t = tuning_slot(c, key);
   REQUIRE(t != nullptr, std::string("unknown tuning key ") + key);
-  if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 7, "stencil variant must be in [0, 7]");
+  if (std::strncmp(key, "dslash_variant", 14) == 0) REQUIRE(value >= 0 && value <= 8, "stencil variant must be in [0, 8]");
   else if (!std::strcmp(key, "block_eo"))
     REQUIRE(value >= 0 && value <= 3, "block_eo must be 0 (plain), 1 (even-odd), 2 (by launch shape) or 3 (even-odd, links from L2)");
-  else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver"))
+  else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver") ||
+           !std::strcmp(key, "sap_bf16"))
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
+  else if (!std::strcmp(key, "block_xcd"))
+    REQUIRE(value >= 0 && value <= 2, "block_xcd must be 0 (launch order), 1 (by XCD) or 2 (by link footprint)");
   else if (!std::strcmp(key, "block_eo_lanes"))
     REQUIRE(value == 0 || value == 2 || value == 4, "even-odd lanes per site must be 0 (default), 2 or 4");
   else if (!std::strcmp(key, "block_tol_prec"))
@@ -2719,15 +2739,15 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     const int fmt = P == P_F64 ? LK_F64 : LK_F32C12;
     // Forms whose kernels spill registers to scratch are not timed while any form does not:
     // their cost depends on what else occupies the caches, so an isolated timing misleads.
-    bool spills[8], any_clean = false;
-    for (int v = 0; v <= 7; ++v) {
+    bool spills[NVAR], any_clean = false;
+    for (int v = 0; v < NVAR; ++v) {
       spills[v] = dslash_variant_scratch(P, P, v) > 0 || (P == P_BF16 && dslash_variant_scratch(P, P_F32, v) > 0);
       any_clean |= !spills[v];
     }
     // BF16 inputs also meet FP32 outputs (a different kernel under the same form number):
     // a third measurement, the batched shape into FP32
     const int nsh = P == P_BF16 ? 3 : 2;
-    double tv[8][3];
+    double tv[NVAR][3];
     for (auto& row : tv) row[0] = row[1] = row[2] = 1e30;
     // each tuning buffer (input, output, Gaussian staging) is kept within 2 GiB
     const size_t cap = std::max<size_t>(1, (size_t(2) << 30) / (size_t(c->V) * 24 * sizeof(double)));
@@ -2741,7 +2761,7 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
       fill(in);
       const int r = si == 0 ? reps : std::max(3, reps / 4);
       for (int round = 0; round < 4; ++round)  // round 0 only warms up (clocks, first launches)
-        for (int v = 0; v <= 7; ++v) {
+        for (int v = 0; v < NVAR; ++v) {
           if (any_clean && spills[v]) continue;
           c->variant[pr] = v;
           const double t = time_dslash(c, L, in, out, r);
@@ -2749,11 +2769,11 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
         }
     }
     double fastest[3] = {1e30, 1e30, 1e30};
-    for (int v = 0; v <= 7; ++v)
+    for (int v = 0; v < NVAR; ++v)
       for (int si = 0; si < nsh; ++si) fastest[si] = std::min(fastest[si], tv[v][si]);
     int best = -1;
     double worst_best = 1e30;
-    for (int v = 0; v <= 7; ++v) {
+    for (int v = 0; v < NVAR; ++v) {
       if (any_clean && spills[v]) continue;
       double worst = 0;
       for (int si = 0; si < nsh; ++si) worst = std::max(worst, tv[v][si] / fastest[si]);

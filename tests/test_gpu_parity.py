@@ -55,7 +55,7 @@ def test_dw_f64_matches_oracle(psms, L, b):
                                  ((16, 16, 16, 16), (8, 8, 8, 8)), ((8, 16, 16, 16), (4, 8, 8, 8)),
                                  ((12, 4, 4, 4), (2, 2, 2, 2))])
 def test_dw_every_stencil_form(psms, L, b):
-    """Every full-lattice stencil form the autotuner can pick (variants 0..7, one right-hand
+    """Every full-lattice stencil form the autotuner can pick (variants 0..8, one right-hand
     side per thread, three right-hand sides per launch), FP64 against the oracle to 1e-13
     and FP32 links/spinors to 2e-6."""
     kappa = 0.137
@@ -66,7 +66,7 @@ def test_dw_every_stencil_form(psms, L, b):
     ctx.gauge_load(0, U)
     ctx.set_tuning("nr_f64", 1)
     ctx.set_tuning("nr_low", 1)
-    for v in range(8):
+    for v in range(9):
         say("case stencil form", v, L)
         ctx.set_tuning("dslash_variant_f64", v)
         ctx.set_tuning("dslash_variant_f32", v)

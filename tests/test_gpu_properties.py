@@ -184,7 +184,7 @@ def _round_c(psi, fn):
     return fn(r).view(np.complex128).reshape(psi.shape)
 
 
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(9))
 def test_low_precision_stencil_every_form(psms, variant):
     """psms_apply_dw_lowp against the oracle's D applied (in FP64) to the input rounded
     as the library rounds it. Bounds, per complex component i of each field:
