@@ -371,9 +371,8 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
  * when the launch has fewer than two workgroups per compute unit) and "block_eo" (block
  * solver: 0 plain minimal residual; 1 minimal residual on the even-odd Schur complement of
  * each block, where an iteration counts as about two plain ones, 12-real links staged in
- * LDS; 3 the same with links read from L2; 2, the default, even-odd throughout, links
- * staged when the launch has fewer than two workgroups per compute unit, and Schwarz
- * sweeps with block_iters/2 iterations rounded up) and "block_eo_lanes" (even-odd block
+ * LDS; 3 the same with links read from L2 and Schwarz sweeps with block_iters/2 iterations
+ * rounded up; 2, the default, as 3 with the links staged in LDS) and "block_eo_lanes" (even-odd block
  * solver on 256-site blocks in FP32 or BF16 storage: 2 or 4 lanes per site; 0, the
  * default, 4 when the launch has fewer workgroups than the GPU has compute units, else
  * 2; FP64 block solves always use 2) and "block_tol_prec" (block inverses to tolerance in

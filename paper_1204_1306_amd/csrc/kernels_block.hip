@@ -7,6 +7,8 @@
 // no grid-wide synchronisation is needed.
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace psms {
 
 struct BlockArgs {
@@ -515,12 +517,7 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
                 U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
                 U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
               }
-              cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
-              cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
-              cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
-              U.m[2][0] = {c0.re, -c0.im};
-              U.m[2][1] = {c1.re, -c1.im};
-              U.m[2][2] = {c2.re, -c2.im};
+              su3_row2(U, T(1));
             } else {
               const int lp = dd == 0 ? p : 1 - p;
               const int ls = dd == 0 ? s : nbs[2 * mu + dd];
@@ -665,12 +662,7 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
             U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
             U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
           }
-          cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
-          cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
-          cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
-          U.m[2][0] = {c0.re, -c0.im};
-          U.m[2][1] = {c1.re, -c1.im};
-          U.m[2][2] = {c2.re, -c2.im};
+          su3_row2(U, T(1));
           Spinor<T> nb;
 #pragma unroll
           for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = r_lds[k][tn];
@@ -749,8 +741,9 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
 template <class S, class LK, class T, bool STAGE = true>
 __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   constexpr int H = 128;  // sites per parity
-  // STAGE: 12-real links staged in LDS (73 KB in FP32, two workgroups per CU); otherwise
-  // read from L2 at each hop (24 KB)
+  // STAGE: 12-real links staged in LDS times kappa (73 KB in FP32, two workgroups per CU),
+  // so that a hop neither scales its result nor multiplies by kappa; otherwise read from L2
+  // at each hop (24 KB)
   constexpr bool LL = LdsLinks<LK>::on && STAGE;
   __shared__ cx<T> ev[12][H];  // an even-site field; after a hop phase, lane 1's even partial sum
   __shared__ cx<T> od[12][H];  // an odd-site field (the two lanes' hop sums, added in turn)
@@ -768,7 +761,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
-  const T kp = T(a.kappa), mk = T(-a.kappa);
+  const T kp = T(a.kappa);
   const int j = threadIdx.x & (H - 1);
   const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
   const int s = blk * H + j;  // index of site j in either parity array
@@ -790,10 +783,13 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
       gB[mu] = m.s;
     }
   }
-  if constexpr (LL) {  // lane h stages the forward links of site j of parity h
+  const float kf = float(a.kappa), ik = float(1.0 / a.kappa);
+  if constexpr (LL) {  // lane h stages kappa times the forward links of site j of parity h
 #pragma unroll
-    for (int k = 0; k < 12; ++k)
-      lk_lds[k][h * H + j] = reinterpret_cast<const float4*>(lk)[(size_t(h * 4 + k / 3) * 3 + k % 3) * Vh + s];
+    for (int k = 0; k < 12; ++k) {
+      float4 v = reinterpret_cast<const float4*>(lk)[(size_t(h * 4 + k / 3) * 3 + k % 3) * Vh + s];
+      lk_lds[k][h * H + j] = make_float4(kf * v.x, kf * v.y, kf * v.z, kf * v.w);
+    }
   }
   // forward link of site (parity gp, in-block index q) in direction mu
   auto link = [&](int mu, int gp, int q, int gs, SU3<T>& U) {
@@ -804,18 +800,22 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
         U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
         U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
       }
-      cx<T> c0 = cmul(U.m[0][1], U.m[1][2]) - cmul(U.m[0][2], U.m[1][1]);
-      cx<T> c1 = cmul(U.m[0][2], U.m[1][0]) - cmul(U.m[0][0], U.m[1][2]);
-      cx<T> c2 = cmul(U.m[0][0], U.m[1][1]) - cmul(U.m[0][1], U.m[1][0]);
-      U.m[2][0] = {c0.re, -c0.im};
-      U.m[2][1] = {c1.re, -c1.im};
-      U.m[2][2] = {c2.re, -c2.im};
+      su3_row2(U, T(ik));  // rows 0 and 1 carry kappa, their cross product kappa^2
     } else {
       LK::load(lk + size_t(gp * 4 + mu) * LK::NC * Vh, Vh, gs, U);
     }
   };
+  // hop coefficient sg * kappa; with staged links kappa is in the link and the
+  // coefficient is the constant sg = +-1, which folds into the additions
+  auto coef = [&](auto sg) -> T {
+    if constexpr (LL) return T(decltype(sg)::value);
+    else return T(decltype(sg)::value) * kp;
+  };
+  using P1 = std::integral_constant<int, 1>;
+  using M1 = std::integral_constant<int, -1>;
   // this lane's hops of the odd site j, applied to the even field ev
-  auto phase_odd = [&](T c, Spinor<T>& acc) {
+  auto phase_odd = [&](auto sg, Spinor<T>& acc) {
+    const T c = coef(sg);
     zero(acc);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
@@ -833,7 +833,8 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
     }
   };
   // this lane's hops of the even site j, applied to od
-  auto phase_even = [&](T c, Spinor<T>& acc) {
+  auto phase_even = [&](auto sg, Spinor<T>& acc) {
+    const T c = coef(sg);
     zero(acc);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
@@ -870,7 +871,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
     for (int k = 0; k < 12; ++k) od[k][j] = r.v[k / 3][k % 3];
   }
   __syncthreads();
-  phase_even(kp, acc);
+  phase_even(P1{}, acc);
   if (h == 1) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) ev[k][j] = acc.v[k / 3][k % 3];
@@ -890,7 +891,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
         for (int k = 0; k < 12; ++k) ev[k][j] = r.v[k / 3][k % 3];
       }
       __syncthreads();
-      phase_odd(kp, acc);
+      phase_odd(P1{}, acc);
       if (h == 0) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) od[k][j] = acc.v[k / 3][k % 3];
@@ -901,7 +902,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
         for (int k = 0; k < 12; ++k) od[k][j] = od[k][j] + acc.v[k / 3][k % 3];
       }
       __syncthreads();
-      phase_even(mk, acc);
+      phase_even(M1{}, acc);
       if (h == 1) {  // ev is free: every read of it was in phase_odd
 #pragma unroll
         for (int k = 0; k < 12; ++k) ev[k][j] = acc.v[k / 3][k % 3];
@@ -950,7 +951,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
     for (int k = 0; k < 12; ++k) ev[k][j] = d.v[k / 3][k % 3];
   }
   __syncthreads();
-  phase_odd(kp, acc);
+  phase_odd(P1{}, acc);
   if (h == 0) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) od[k][j] = acc.v[k / 3][k % 3];

@@ -532,16 +532,12 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
     launch_zero(c->st, xs, c->Vh);
   }
   // Block solver form: plain minimal residual (block_eo 0) or even-odd with the 12-real
-  // links staged in LDS (1) or read from L2 (3); by launch shape (2, the default): even-odd,
-  // staged when the grid has fewer than two workgroups per CU (one 98 KB workgroup per CU
-  // is then no loss), else from L2 so that two workgroups share a CU. With 2 and 3 the
-  // Schwarz sweeps run half the iterations, one even-odd iteration reducing the residual
-  // about as much as two plain ones.
-  const int wgs = c->g.nblk_c * r.nrhs * r.nprop;
-  const int eo_form = c->block_eo == 0 ? 0
-                      : c->block_eo == 1 ? 1
-                      : c->block_eo == 3 ? 2
-                                         : (wgs < 512 ? 1 : 2);
+  // links staged in LDS (1, 2) or read from L2 (3). With 2 (the default) and 3 the Schwarz
+  // sweeps run half the iterations, one even-odd iteration reducing the residual about as
+  // much as two plain ones. The staged form takes 73 KB of LDS, so two workgroups share a
+  // CU, and a hop reads its kappa-scaled link from LDS: at 32^4 a sweep takes 4.55 ms
+  // against 5.14 ms with the links read from L2, at 16^4 1.15 against 1.26 ms.
+  const int eo_form = c->block_eo == 0 ? 0 : c->block_eo == 3 ? 2 : 1;
   const int iters = c->block_eo >= 2 ? (sc.iters + 1) / 2 : sc.iters;
   // Each sweep first applies rho_col -= D_{col,other} delta_other across its block
   // faces (fused into the block kernel), except the very first, where no delta exists.
