@@ -166,6 +166,10 @@ void gcr_backsub(hipStream_t st, const double2* T, const double2* alpha, int n, 
 void scatter_col(hipStream_t st, const double* src, int k, int m, int nrhs, double* dst);
 void defect_scales(hipStream_t st, const double* v, const int* active, int nrhs, double* inv, double2* sq);
 void launch_axpy_mixed(hipStream_t st, const Geo& g, const double2* a, const FieldBatch& x, const FieldBatch& y, int sgn);
+// y += sgn * sum_j c[r * cstride + j] X_j with the basis X in another storage than y
+// (BF16 -> F32, F32 -> F64, BF16 -> F64); false for any other pair (nothing launched)
+bool launch_lincomb_mixed(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const double2* c,
+                          int cstride, const FieldBatch& y, int sgn);
 void reduce_dot_mixed(hipStream_t st, const Geo& g, const FieldBatch& x, const FieldBatch& y, const Reducer& R, double2* out);
 // fused passes for a BF16 basis vector x and an FP32 residual y (fused_mixed_ok)
 bool fused_mixed_ok(const FieldBatch& x, const FieldBatch& y);

@@ -92,6 +92,48 @@ void launch_axpy_mixed(hipStream_t st, const Geo& g, const double2* a, const Fie
     hipLaunchKernelGGL((k_axpy_site<StBF16, StF64, double>), grid, dim3(256), 0, st, g, a, (const uint4*)x.p, (double2*)y.p, double(sgn));
 }
 
+// y += sign * sum_{j < m} c[r * cstride + j] X_j, X_j = x + j * vstride (units of SX): the
+// solution update of a restart cycle from a basis in another storage, one pass over y
+template <class SX, class SY, class T>
+__global__ void k_lincomb_site(Geo g, const double2* __restrict__ c, int cstride, int m,
+                               const typename SX::unit* __restrict__ x, size_t vstride, typename SY::unit* __restrict__ y,
+                               double sgn) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * g.Vh) return;
+  int p = t / g.Vh, i = t - p * g.Vh, r = blockIdx.y;
+  Spinor<T> yv;
+  SY::load(y + (size_t(r) * 2 + p) * SY::NC * g.Vh, g.Vh, i, yv);
+  for (int j = 0; j < m; ++j) {
+    const double2 cj = c[size_t(r) * cstride + j];
+    const cx<T> A = {T(sgn * cj.x), T(sgn * cj.y)};
+    Spinor<T> xv;
+    SX::load(x + size_t(j) * vstride + (size_t(r) * 2 + p) * SX::NC * g.Vh, g.Vh, i, xv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) yv.v[q][cc] = yv.v[q][cc] + cmul(A, xv.v[q][cc]);
+  }
+  SY::store(y + (size_t(r) * 2 + p) * SY::NC * g.Vh, g.Vh, i, yv);
+}
+
+bool launch_lincomb_mixed(hipStream_t st, const Geo& g, const FieldBatch& basis, size_t vstride, int m, const double2* c,
+                          int cstride, const FieldBatch& y, int sgn) {
+  if (m <= 0) return true;
+  dim3 grid((2 * g.Vh + 255) / 256, y.nprop * y.nrhs);
+  if (basis.prec == P_BF16 && y.prec == P_F32)
+    hipLaunchKernelGGL((k_lincomb_site<StBF16, StF32, float>), grid, dim3(256), 0, st, g, c, cstride, m,
+                       (const uint4*)basis.p, vstride, (float4*)y.p, double(sgn));
+  else if (basis.prec == P_F32 && y.prec == P_F64)
+    hipLaunchKernelGGL((k_lincomb_site<StF32, StF64, double>), grid, dim3(256), 0, st, g, c, cstride, m,
+                       (const float4*)basis.p, vstride, (double2*)y.p, double(sgn));
+  else if (basis.prec == P_BF16 && y.prec == P_F64)
+    hipLaunchKernelGGL((k_lincomb_site<StBF16, StF64, double>), grid, dim3(256), 0, st, g, c, cstride, m,
+                       (const uint4*)basis.p, vstride, (double2*)y.p, double(sgn));
+  else
+    return false;
+  return true;
+}
+
 // partial (x, y) per workgroup at site level; final pass shared with the unit-level reducer
 template <class SX, class SY>
 __global__ void k_dot_site(Geo g, const typename SX::unit* __restrict__ x, const typename SY::unit* __restrict__ y,

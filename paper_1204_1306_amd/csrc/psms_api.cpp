@@ -306,8 +306,8 @@ void build_geo(psms_ctx* c, const int* L, const int* b, int apbc, const int* ob,
         }
   // schedule of blocks for full-lattice launches: black block bi then white block
   // bi (neighbours along direction 3), in lexicographic order of bi. (A Morton order
-  // of the block coordinates was measured slower: it scatters the per-block chunks
-  // of every component plane.)
+  // of the block coordinates was measured slower, also for the one-workgroup-per-block
+  // forms at 32^4: FP64 283 -> 340 us per launch.)
   std::vector<int> order(nblk);
   for (int k = 0; k < nblk; ++k) order[k] = (k & 1) * g.nblk_c + (k >> 1);
   uint32_t* dl = (uint32_t*)dev_alloc(c, lc.size() * 4);
@@ -521,15 +521,17 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
   FieldBatch rho = field(c, "sap_rho", sc.prec, np, nr);
   FieldBatch dl = field(c, "sap_delta", sc.prec, np, nr);
   FieldBatch pb = field(c, "sap_p", sc.prec, np, nr);
-  // The sweeps of the first cycle read their residual straight from r and assign the
-  // iterate (x = delta), so neither a copy of r nor a zeroed iterate is needed; the
-  // iterate is z itself when z has the solver's storage.
-  const bool direct = z.prec == sc.prec && r.prec == sc.prec;
-  FieldBatch xs = direct ? z : field(c, "sap_x", sc.prec, np, nr);
-  if (!direct || sc.cycles <= 0) {
+  // The sweeps of the first cycle assign the iterate (x = delta), so it needs no zeroing,
+  // and read their residual straight from r when r has the solver's storage (else from a
+  // converted copy); the iterate is z itself when z has the solver's storage.
+  const bool dz = z.prec == sc.prec, dr = r.prec == sc.prec;
+  FieldBatch xs = dz ? z : field(c, "sap_x", sc.prec, np, nr);
+  if (sc.cycles <= 0) {
+    ProfScope ps(c, FAM_BLAS, 0);
+    launch_zero(c->st, xs, c->Vh);
+  } else if (!dr) {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_copy(c->st, c->g, r, rho, nullptr);
-    launch_zero(c->st, xs, c->Vh);
   }
   // Block solver form: plain minimal residual (block_eo 0) or even-odd with the 12-real
   // links staged in LDS (1, 2) or read from L2 (3). With 2 (the default) and 3 the Schwarz
@@ -549,15 +551,15 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
       bp.eo_lanes = c->block_eo_lanes;
       bp.xcd_map = block_xcd_of(c, L.fmt, np);
       bp.eo = eo_form;
-      if (direct && cy == 0) {
-        bp.rho_in = r.p;
+      if (cy == 0) {
+        if (dr) bp.rho_in = r.p;
         bp.x_assign = 1;
       }
       ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho, bp.face));
       launch_block_mr(c->st, c->g, L.p, L.fmt, rho, xs, dl, pb, bp, nullptr);
     }
   }
-  if (!direct) {
+  if (!dz) {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_copy(c->st, c->g, xs, z, nullptr);
   }
@@ -703,7 +705,7 @@ GcrResult fgcr(psms_ctx* c, const Links& L, const GcrCfg& cf, const FieldBatch& 
       gcr_backsub(st, T, ALPHA, used, m, nr, BETA);
       if (x.prec == cf.wprec) {
         launch_lincomb(st, g, Z, vstride, used, BETA, m, x, +1);
-      } else {
+      } else if (!launch_lincomb_mixed(st, g, Z, vstride, used, BETA, m, x, +1)) {
         // x += beta_j Z_j with Z in a different storage: one mixed axpy per basis vector
         double2* bj = dscratch<double2>(c, "gcr_bj", nr);
         for (int j = 0; j < used; ++j) {
