@@ -43,8 +43,8 @@ __device__ __forceinline__ void net_transport(const Geo& g, const float4* __rest
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp) {
     cx<float> w[3];
-    if (fwd) su3_mul(U, v.v[sp], w);
-    else su3_dag_mul(U, v.v[sp], w);
+    if (fwd) su3_mul_sum(U, v.v[sp], w);
+    else su3_dag_mul_sum(U, v.v[sp], w);
 #pragma unroll
     for (int a = 0; a < 3; ++a) o.v[sp][a] = scale(n.sign, w[a]);
   }
@@ -242,6 +242,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
   const int M = 8 * a.cout, mblk = (M + 31) / 32, ksteps = 9 * a.cin, nblk = 3 * NET_NS / 32;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // output blocks: wave w takes blk = w + 4 i, i.e. (mb, nb) = (blk % mblk, blk / mblk);
+  // mblk divides 4, so all of a wave's blocks share mb and one A fragment per k-step
+  const int mbw = wave % mblk;
   f32x16 acc[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -250,6 +253,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
   // staging: thread -> one site (l) and the channels cg, cg + 4; its neighbours and
   // boundary signs are computed once, each link is loaded once for both channels
   static_assert(NET_NS == 64 && NET_MAXC == 8, "staging assumes 64 sites and at most 8 channels");
+  static_assert(4 % ((8 * NET_MAXC + 31) / 32) == 0, "the row blocks of the output divide the 4 waves");
   const int l = threadIdx.x & 63, cg = threadIdx.x >> 6;
   const int site = site0 + l;
   const bool valid = site < 2 * g.Vh;
@@ -288,6 +292,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
   };
   fetch(0);
   for (int t = 0; t < 9; ++t) {
+    // the A fragments of direction t, requested before the staging hides their latency
+    uint2 af[NET_MAXC];
+#pragma unroll
+    for (int kk = 0; kk < NET_MAXC; ++kk)
+      if (kk < a.cin) af[kk] = a.A[(size_t(mbw) * ksteps + t * a.cin + kk) * 64 + lane];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int ci = cg + 4 * h;
@@ -302,8 +311,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
               cx<float> w[3];
-              if (fwd) su3_mul(U, x.v[sp], w);
-              else su3_dag_mul(U, x.v[sp], w);
+              if (fwd) su3_mul_sum(U, x.v[sp], w);
+              else su3_dag_mul_sum(U, x.v[sp], w);
 #pragma unroll
               for (int c = 0; c < 3; ++c) v.v[sp][c] = scale(nsign[t - 1], w[c]);
             }
@@ -326,19 +335,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
     }
     __syncthreads();
     if (t < 8) fetch(t + 1);
-    for (int kk = 0; kk < a.cin; ++kk) {
-      const int kb = t * a.cin + kk;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int blk = wave + 4 * i;
-        if (blk < mblk * nblk) {
-          const int mb = blk / nblk, nb = blk % nblk;
-          const uint2 au = a.A[(size_t(mb) * ksteps + kb) * 64 + lane];
-          const short* bp = &Bs[nb * 32 + (lane & 31)][kk * 8 + (lane >> 5) * 4];
-          bf16x4 av, bv;
-          av[0] = short(au.x & 0xffffu); av[1] = short(au.x >> 16); av[2] = short(au.y & 0xffffu); av[3] = short(au.y >> 16);
-          bv[0] = bp[0]; bv[1] = bp[1]; bv[2] = bp[2]; bv[3] = bp[3];
-          acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc[i], 0, 0, 0);
+    for (int kk = 0; kk < NET_MAXC; ++kk) {
+      if (kk < a.cin) {
+        const uint2 au = af[kk];
+        bf16x4 av;
+        av[0] = short(au.x & 0xffffu); av[1] = short(au.x >> 16); av[2] = short(au.y & 0xffffu); av[3] = short(au.y >> 16);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int blk = wave + 4 * i;
+          if (blk < mblk * nblk) {
+            const int nb = blk / mblk;
+            const short* bp = &Bs[nb * 32 + (lane & 31)][kk * 8 + (lane >> 5) * 4];
+            bf16x4 bv;
+            bv[0] = bp[0]; bv[1] = bp[1]; bv[2] = bp[2]; bv[3] = bp[3];
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc[i], 0, 0, 0);
+          }
         }
       }
     }
@@ -349,7 +361,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
   for (int i = 0; i < 3; ++i) {
     const int blk = wave + 4 * i;
     if (blk < mblk * nblk) {
-      const int mb = blk / nblk, nb = blk % nblk;
+      const int mb = blk % mblk, nb = blk / mblk;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int row = mb * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
@@ -384,11 +396,11 @@ void launch_net_layer_mfma(hipStream_t st, const Geo& g, const void* links, cons
   a.cin = adj ? cout_f : cin_f;
   a.cout = adj ? cin_f : cout_f;
   dim3 grid((2 * g.Vh + NET_NS - 1) / NET_NS, batch);
-  // Large launches run the form built for three waves per SIMD (168 VGPRs, a small spill;
-  // its LDS also allows three): 15% faster at 8192 workgroups. Small ones keep the
-  // unconstrained form (two waves), 5% faster at 1024 workgroups.
-  if (size_t(grid.x) * grid.y >= 4096) hipLaunchKernelGGL((k_net_layer_mfma<3>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_net_layer_mfma<1>), grid, dim3(256), 0, st, a);
+  // Two waves per SIMD (no register limit): with the A fragments of a direction held in
+  // registers, a form forced to three waves per SIMD spills 152 B per lane and takes
+  // 4.45 ms per application at 16^4 x 8 fields against 3.07 ms. (A double-buffered
+  // staged tile, staging direction t + 1 while the matrix cores take t, measured 3.13 ms.)
+  hipLaunchKernelGGL((k_net_layer_mfma<1>), grid, dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------- weight gradient

@@ -113,14 +113,13 @@ def test_net_loss_and_gradient_parity(psms, mfma):
     assert rel(g, flat(ref_g)) < (1e-4 if mfma == 0 else 5e-2)
 
 
-def test_net_three_wave_form_agrees_with_two_wave_form(psms):
-    """Launches of >= 4096 workgroups run the matrix-core layer built for three waves per
-    SIMD; smaller ones the unconstrained form. At 16^4 (1024 workgroups per field) four
-    fields cross the threshold and two do not. Both forms take the same MFMA steps in the
-    same order, so the forward results agree to FP32 rounding (1e-6), the loss and its
-    gradient over four pairs equal the sums over two + two pairs (the gradient's site
-    reduction is split differently: 1e-5), and the three-wave forward matches the FP64
-    oracle within the bf16 tolerance."""
+def test_net_large_launch_agrees_with_small_launch(psms):
+    """The matrix-core layer on a launch of 4096 workgroups (16^4, four fields: the shape
+    of the training and preconditioning passes) against two fields (2048 workgroups).
+    Every field takes the same MFMA steps in the same order, so the forward results agree
+    to FP32 rounding (1e-6), the loss and its gradient over four pairs equal the sums over
+    two + two pairs (the gradient's site reduction is split differently: 1e-5), and the
+    large launch's forward matches the FP64 oracle within the bf16 tolerance."""
     chans = (1, 8, 8, 8, 1)
     L, b = (16, 16, 16, 16), (4, 4, 4, 4)
     U = synth.gauge_field(L, 0.6, 4999)
@@ -132,7 +131,7 @@ def test_net_three_wave_form_agrees_with_two_wave_form(psms):
     ctx.gauge_load(0, U)
     ctx.net_init(chans)
     ctx.net_set_weights(flat(ws))
-    say("case net three-wave form: forward")
+    say("case net large launch: forward")
     out4 = ctx.net_apply(0, r)
     out2 = ctx.net_apply(0, r[:2])
     d = rel(out4[:2], out2)
@@ -140,9 +139,9 @@ def test_net_three_wave_form_agrees_with_two_wave_form(psms):
     assert d < 1e-6
     ref, _ = net.forward(U, ws, r[3], L)
     err = rel(out4[3], ref)
-    say(f"  three-wave form against the FP64 oracle: {err:.2e} (bound {TOL[1]})")
+    say(f"  large launch against the FP64 oracle: {err:.2e} (bound {TOL[1]})")
     assert err < TOL[1]
-    say("case net three-wave form: loss and gradient")
+    say("case net large launch: loss and gradient")
     l4, g4 = ctx.net_loss_grad(0, r, e)
     la, ga = ctx.net_loss_grad(0, r[:2], e[:2])
     lb, gb = ctx.net_loss_grad(0, r[2:], e[2:])
