@@ -330,7 +330,9 @@ def interpolation_leg(psms, ctx, w, nprop, steps: int, ns=(1, 2, 4)):
     the relative gauge fixing of the pair (App. B, default parameters; g on the
     block-interior sites): seconds per estimate and the spread of Delta over the noise
     fields, which the method reduces about as 1/sqrt(N). Each factor draws its own seeded
-    noise; both variants see the same noise."""
+    noise; both variants see the same noise. Then the unfixed pair in mixed precision
+    (FP32 inner solves; the intermediate fields, not SU(3), on FP32 18-real links), with
+    the largest difference of its Deltas from the FP64 ones."""
     import torch
 
     from paper_1204_1306_amd import synth
@@ -345,26 +347,33 @@ def interpolation_leg(psms, ctx, w, nprop, steps: int, ns=(1, 2, 4)):
     torch.cuda.synchronize()
     out["gauge_fix_seconds"] = time.perf_counter() - t0
     out["gauge_fix"] = g_fix[0]
-    for fixed in (False, True):
+    mixed = mode_params(psms, "mixed", w["tol"])
+    d_f64 = {}
+    for variant in ("", "fixed_", "mixed_"):
+        fixed = variant == "fixed_"
+        pv = mixed if variant == "mixed_" else prm
         for n in ns:
             eta = torch.from_numpy(synth.gaussian_noise(w["L"], n * nn, 9100 + n)).to("cuda")
             delta = torch.empty((1, nn), dtype=torch.float64, device="cuda")
             ds, dt_all, it = [], 0.0, 0
             for p in range(nprop):
                 a, b = (40 + 2 * p, 41 + 2 * p) if fixed else (0, 1 + p)
-                ctx.logdet_ratio(psms.OP_SCHUR, a, [b], eta, prm, delta=delta, n_interp=n)
+                ctx.logdet_ratio(psms.OP_SCHUR, a, [b], eta, pv, delta=delta, n_interp=n)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 for _ in range(steps):
-                    _, st = ctx.logdet_ratio(psms.OP_SCHUR, a, [b], eta, prm, delta=delta, n_interp=n)
+                    _, st = ctx.logdet_ratio(psms.OP_SCHUR, a, [b], eta, pv, delta=delta, n_interp=n)
                 torch.cuda.synchronize()
                 dt_all += (time.perf_counter() - t0) / steps
                 it += st["inner_iters"]
                 ds.append(delta.cpu().numpy()[0])
             d = np.concatenate(ds)
-            out[f"{'fixed_' if fixed else ''}n{n}"] = {"s_per_estimate": dt_all / (nprop * nn),
-                                                       "ms_per_step": 1e3 * dt_all, "delta_std": float(d.std()),
-                                                       "delta_mean": float(d.mean()), "inner_iters": it}
+            out[f"{variant}n{n}"] = {"s_per_estimate": dt_all / (nprop * nn), "ms_per_step": 1e3 * dt_all,
+                                     "delta_std": float(d.std()), "delta_mean": float(d.mean()), "inner_iters": it}
+            if variant == "":
+                d_f64[n] = d
+            elif variant == "mixed_":
+                out[f"{variant}n{n}"]["max_abs_delta_diff_vs_f64"] = float(np.abs(d - d_f64[n]).max())
     return out
 
 

@@ -108,13 +108,15 @@ unsigned long long psms_device_bytes(const psms_ctx* ctx);
 
 /* Uploads gauge field U into slot (0 <= slot < 64), converting it to the internal
  * layouts (FP64 and FP32 12-real). Returns PSMS_ENOTSU3 if some link deviates from
- * SU(3) by more than 1e-6 (the FP64 copy is still loaded; mixed precision is then
- * refused for this slot), PSMS_EINVAL if an entry is NaN or Inf (the slot is then
- * left unloaded). */
+ * SU(3) by more than 1e-6: the FP64 copy is still loaded, mixed-precision operators
+ * and solves then use FP32 copies of all 18 reals of each link (made on first use),
+ * and the network and psms_apply_dw_noalloc in MIXED refuse the slot (PSMS_ENOTSU3).
+ * PSMS_EINVAL if an entry is NaN or Inf (the slot is then left unloaded). */
 psms_status psms_gauge_load(psms_ctx* ctx, int slot, const double* U);
 
 /* out = D in (eq. Dw, rescaled), full lattice. prec MIXED applies the FP32 12-real
- * link, FP32 spinor kernel (input rounded to FP32). */
+ * link, FP32 spinor kernel (input rounded to FP32); for a slot that is not SU(3), FP32
+ * 18-real links. */
 psms_status psms_apply_dw(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs, psms_prec prec);
 
 /* out = D in (eq. Dw, rescaled) with the operands of the mixed-precision inner solves:
@@ -122,8 +124,8 @@ psms_status psms_apply_dw(psms_ctx* ctx, int slot, const double* in, double* out
  * even), arithmetic in FP32, the result stored in out_storage and returned as FP64.
  * Pairs: F32 -> F32, BF16 -> BF16, BF16 -> F32 (an FP32 input with a BF16 output is
  * PSMS_EINVAL). The stencil form is that of the context's tuning for the input
- * storage ("dslash_variant_f32" / "dslash_variant_bf16"). Needs SU(3) links
- * (PSMS_ENOTSU3 otherwise). */
+ * storage ("dslash_variant_f32" / "dslash_variant_bf16"); for a slot that is not
+ * SU(3), FP32 18-real links and the one-lane form. */
 psms_status psms_apply_dw_lowp(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs,
                                psms_inner_storage in_storage, psms_inner_storage out_storage);
 
@@ -136,7 +138,9 @@ psms_status psms_apply_dw_lowp(psms_ctx* ctx, int slot, const double* in, double
  * nrhs fields need 2 x nrhs x V x 192 bytes (F64) or 96 bytes (MIXED), and a larger
  * request is PSMS_EINVAL. All calls on one device share that array: calls that overlap
  * on one device (other streams, other threads, other contexts) race and must be
- * serialised by the caller. Results equal those of psms_apply_dw. */
+ * serialised by the caller. Results equal those of psms_apply_dw. MIXED needs a slot
+ * holding SU(3) links (PSMS_ENOTSU3 otherwise: the FP32 18-real copies that other
+ * calls make for such a slot would need an allocation). */
 psms_status psms_apply_dw_noalloc(psms_ctx* ctx, int slot, const double* in, double* out, int nrhs, psms_prec prec);
 
 /* Even-odd preconditioned operator on even sites: out_e = in_e - kappa^2 H_eo H_oe in_e
@@ -188,9 +192,9 @@ psms_status psms_apply_schur_inv(psms_ctx* ctx, int slot, const double* in, doub
  * delta[p*nnoise + j] = sum_i (|M_i xi_ij|^2 - |xi_ij|^2), M_i = D(U_{i+1})^-1 D(U_i)
  * (eq. Mparam; the Schur complements for SCHUR), eq. staccN. noise then holds N groups
  * of nnoise fields, group i (fields i*nnoise .. i*nnoise + nnoise - 1) for factor i.
- * The intermediate fields are not SU(3), so N > 1 needs prec PSMS_F64 (else
- * PSMS_EINVAL); they use two free gauge slots (PSMS_EINVAL when fewer are free), which
- * are free again on return.
+ * The intermediate fields are not SU(3): in MIXED their inner solves use FP32 18-real
+ * links (FP64 outside, as always). They use two free gauge slots (PSMS_EINVAL when
+ * fewer are free), which are free again on return.
  * SCHUR: the full solve inside (1 - PQ(U'))^-1 starts from the exact solution of the
  * same system with U, a by-product of applying (1 - PQ(U)); tol still refers to |b|.
  * delta may be host or device memory (nprop*nnoise doubles). */

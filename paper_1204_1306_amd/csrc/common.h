@@ -214,6 +214,24 @@ struct LkF32C12 {
   }
 };
 
+// F32F18: all 18 reals in FP32, for links that are not SU(3) (the fields between U and U'
+// of an interpolated estimate): 5 float4 planes, complex entries (2k, 2k + 1) in plane k,
+// entry 8 and a zero pad in plane 4.
+struct LkF32F18 {
+  using unit = float4;
+  static constexpr int NC = 5;
+  template <class T> __device__ __forceinline__ static void load(const unit* __restrict__ p, size_t Vh, int s, SU3<T>& u) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float4 d = p[k * Vh + s];
+      u.m[(2 * k) / 3][(2 * k) % 3] = {T(d.x), T(d.y)};
+      u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(d.z), T(d.w)};
+    }
+    float4 d = p[4 * Vh + s];
+    u.m[2][2] = {T(d.x), T(d.y)};
+  }
+};
+
 // ----------------------------------------------------------------- geometry
 struct Geo {
   int L[4], b[4], NB[4];

@@ -33,7 +33,7 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStrea
 }
 
 enum HopSel : int { HOP_ALL = 0, HOP_INTRA = 1, HOP_CROSS = 2 };
-enum LinkFmt : int { LK_F64 = 0, LK_F32C12 = 1 };
+enum LinkFmt : int { LK_F64 = 0, LK_F32C12 = 1, LK_F32F18 = 2 };
 
 // A batch of spinor fields: nprop groups of nrhs fields, [prop][rhs][p][unit][Vh].
 struct FieldBatch {
@@ -74,6 +74,8 @@ void launch_unpack(hipStream_t st, const Geo& g, const FieldBatch& src, double* 
 void launch_pack_links(hipStream_t st, const Geo& g, const double* U, void* dst, int linkfmt);
 // zero the links that leave their outer block (g.ob), in the internal format given
 void launch_cut_links(hipStream_t st, const Geo& g, void* links, int linkfmt);
+// FP32 18-real links from the internal FP64 links of the same layout (any field, SU(3) or not)
+void launch_links_f64_to_f18(hipStream_t st, const Geo& g, const void* f64, void* f18);
 // max over links of |U U^+ - 1| (per-workgroup maxima in partial, host reduces)
 void launch_unitarity(hipStream_t st, const Geo& g, const double* U, double* partial, int nwg);
 
@@ -151,6 +153,7 @@ struct BlockMRParams {
   int x_assign = 0;              // 1: x = delta instead of x += delta
   int eo_lanes = 0;              // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int xcd_map = 0;               // 1: the right-hand sides of one block run back to back on one XCD
+  int rho_in_f32 = 0;            // 1: rho_in is FP32 (the kernel's storage otherwise)
 };
 // For every block of the colour: (optionally) the face update of rho_b from the
 // other colour's delta, then delta = MR approximation of D_b^-1 rho_b, x += delta,

@@ -29,6 +29,8 @@ struct BlockArgs {
   int x_assign;        // 1: x = delta instead of x += delta (x need not be initialised)
   int eo_lanes;        // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int xcd_map;         // 1: workgroup order by XCD (block_coord)
+  int rin_f32;         // 1: rho_in is an FP32 field (units of rin_stride per right-hand side)
+  size_t rin_stride;
   int* iters;
 };
 
@@ -50,6 +52,22 @@ __device__ __forceinline__ BlockCoord block_coord(const BlockArgs& a) {
     return {a.colour * a.g.nblk_c + q % nb, i % nr, q / nb};
   }
   return {a.colour * a.g.nblk_c + int(blockIdx.x), int(blockIdx.y), int(blockIdx.z)};
+}
+
+// The initial residual of parity par at site s of right-hand side rix (proposal-major
+// index): from rho (already offset to that right-hand side), or from rho_in, which has the
+// kernel's storage or, with rin_f32, FP32 (the first Schwarz sweep reading an FP32 Krylov
+// residual directly, with no converted copy).
+template <class S, class T>
+__device__ __forceinline__ void load_rho0(const BlockArgs& a, const typename S::unit* rho, size_t rix, int par, int s,
+                                          Spinor<T>& v) {
+  const size_t Vh = a.g.Vh;
+  if (a.rho_in && a.rin_f32) {
+    StF32::load(reinterpret_cast<const float4*>(a.rho_in) + rix * a.rin_stride + size_t(par) * StF32::NC * Vh, Vh, s, v);
+  } else {
+    const typename S::unit* base = a.rho_in ? reinterpret_cast<const typename S::unit*>(a.rho_in) + rix * a.rhs_stride : rho;
+    S::load(base + size_t(par) * S::NC * Vh, Vh, s, v);
+  }
 }
 
 // Schwarz residual update across the faces of a block of colour c:
@@ -162,10 +180,10 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   const BlockCoord bc = block_coord(a);
   const int blk = bc.blk;
   const int prop = bc.prop;
-  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
+  const size_t rix = size_t(prop * a.nrhs + bc.rhs);
+  const size_t roff = rix * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
-  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   unit* pb = reinterpret_cast<unit*>(a.pbuf) + roff;
@@ -178,7 +196,7 @@ __global__ void __launch_bounds__(256) k_block_mr(BlockArgs a) {
   for (int j = threadIdx.x; j < nsite; j += blockDim.x) {
     int p = j / g.Vbh, s = blk * g.Vbh + (j - p * g.Vbh);
     Spinor<T> v, z;
-    S::load(rin + size_t(p) * S::NC * Vh, Vh, s, v);
+    load_rho0<S>(a, rho, rix, p, s, v);
     if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), v);
     if (a.face || a.rho_in) S::store(rho + size_t(p) * S::NC * Vh, Vh, s, v);
     zero(z);
@@ -298,10 +316,10 @@ __global__ void __launch_bounds__(256) k_block_mr_eo_g(BlockArgs a) {
   const BlockCoord bc = block_coord(a);
   const int blk = bc.blk;
   const int prop = bc.prop;
-  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
+  const size_t rix = size_t(prop * a.nrhs + bc.rhs);
+  const size_t roff = rix * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
-  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   unit* pb = reinterpret_cast<unit*>(a.pbuf) + roff;
@@ -315,7 +333,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo_g(BlockArgs a) {
   for (int j = threadIdx.x; j < 2 * H; j += blockDim.x) {
     const int p = j / H, s = blk * H + (j - p * H);
     Spinor<T> v;
-    S::load(rin + p * odd, Vh, s, v);
+    load_rho0<S>(a, rho, rix, p, s, v);
     if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, kp, v);
     if (a.face || a.rho_in) S::store(rho + p * odd, Vh, s, v);
 #pragma unroll
@@ -448,10 +466,10 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
   const BlockCoord bc = block_coord(a);
   const int blk = bc.blk;
   const int prop = bc.prop;
-  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
+  const size_t rix = size_t(prop * a.nrhs + bc.rhs);
+  const size_t roff = rix * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
-  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
@@ -484,7 +502,7 @@ __global__ void __launch_bounds__(VB) k_block_mr_lds(BlockArgs a) {
       for (int k = 0; k < 3; ++k) lk_lds[mu * 3 + k][t] = reinterpret_cast<const float4*>(lk)[(size_t(p * 4 + mu) * 3 + k) * Vh + s];
   }
   Spinor<T> r, d;
-  S::load(rin + size_t(p) * S::NC * Vh, Vh, s, r);
+  load_rho0<S>(a, rho, rix, p, s, r);
   if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), r);
   zero(d);
   double b2 = 0.0;
@@ -594,10 +612,10 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
   const BlockCoord bc = block_coord(a);
   const int blk = bc.blk;
   const int prop = bc.prop;
-  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
+  const size_t rix = size_t(prop * a.nrhs + bc.rhs);
+  const size_t roff = rix * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
-  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
@@ -629,7 +647,7 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
   zero(d);
   double b2 = 0.0;
   if (h == 0) {
-    S::load(rin + size_t(p) * S::NC * Vh, Vh, s, r);
+    load_rho0<S>(a, rho, rix, p, s, r);
     if (a.face) face_update<S, LK, T>(g, lk, dl, p, s, T(a.kappa), r);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -754,10 +772,10 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
   const BlockCoord bc = block_coord(a);
   const int blk = bc.blk;
   const int prop = bc.prop;
-  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
+  const size_t rix = size_t(prop * a.nrhs + bc.rhs);
+  const size_t roff = rix * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
-  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
@@ -854,7 +872,7 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
 
   // own site (parity h): rho (+ the face update), |rho|^2 over the block
   Spinor<T> r, d, acc;
-  S::load(rin + size_t(h) * S::NC * Vh, Vh, s, r);
+  load_rho0<S>(a, rho, rix, h, s, r);
   if (a.face) face_update<S, LK, T>(g, lk, dl, h, s, kp, r);
   double b2 = 0.0;
 #pragma unroll
@@ -1004,10 +1022,10 @@ __global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
   const BlockCoord bc = block_coord(a);
   const int blk = bc.blk;
   const int prop = bc.prop;
-  const size_t roff = size_t(prop * a.nrhs + bc.rhs) * a.rhs_stride;
+  const size_t rix = size_t(prop * a.nrhs + bc.rhs);
+  const size_t roff = rix * a.rhs_stride;
   using unit = typename S::unit;
   unit* rho = reinterpret_cast<unit*>(a.rho) + roff;
-  const unit* rin = a.rho_in ? reinterpret_cast<const unit*>(a.rho_in) + roff : rho;
   unit* x = reinterpret_cast<unit*>(a.x) + roff;
   unit* dl = reinterpret_cast<unit*>(a.delta) + roff;
   const typename LK::unit* lk = reinterpret_cast<const typename LK::unit*>(a.links[prop]);
@@ -1025,7 +1043,7 @@ __global__ void __launch_bounds__(512) k_block_mr_eo4(BlockArgs a) {
   Spinor<T> acc, xv;
   zero(acc);
   zero(xv);
-  if (h == 0) S::load(rin + size_t(fp) * S::NC * Vh, Vh, s, acc);
+  if (h == 0) load_rho0<S>(a, rho, rix, fp, s, acc);
   else if (!a.x_assign) S::load(x + size_t(fp) * S::NC * Vh, Vh, s, xv);
   // the site tables head the chain of dependent reads of the face update: read them
   // before the link staging so that their latency overlaps it
@@ -1313,10 +1331,14 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
   a.x_assign = bp.x_assign;
   a.eo_lanes = bp.eo_lanes;
   a.xcd_map = bp.xcd_map;
+  a.rin_f32 = bp.rho_in_f32;
+  a.rin_stride = units_per_field(P_F32, g.Vh);
   a.iters = iters_out;
   if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);
   else if (rho.prec == P_F32 && linkfmt == LK_F32C12) block_go<StF32, LkF32C12, float>(st, a, rho.nprop);
   else if (rho.prec == P_BF16 && linkfmt == LK_F32C12) block_go<StBF16, LkF32C12, float>(st, a, rho.nprop);
+  else if (rho.prec == P_F32 && linkfmt == LK_F32F18) block_go<StF32, LkF32F18, float>(st, a, rho.nprop);
+  else if (rho.prec == P_BF16 && linkfmt == LK_F32F18) block_go<StBF16, LkF32F18, float>(st, a, rho.nprop);
 }
 
 }  // namespace psms

@@ -682,6 +682,15 @@ void launch_dslash(hipStream_t st, const Geo& g, const void* const* links, int l
     dslash_sel<StBF16, StF32, LkF32C12, float>(st, a, in.nprop, dp.sel, nr_pref);
   else if (in.prec == P_F32 && out.prec == P_BF16 && linkfmt == LK_F32C12)
     dslash_sel<StF32, StBF16, LkF32C12, float>(st, a, in.nprop, dp.sel, nr_pref);
+  // FP32 18-real links (fields that are not SU(3)): the one-lane forms
+  else if (in.prec == P_F32 && out.prec == P_F32 && linkfmt == LK_F32F18)
+    dslash_sel<StF32, StF32, LkF32F18, float>(st, a, in.nprop, dp.sel, nr_pref);
+  else if (in.prec == P_BF16 && out.prec == P_BF16 && linkfmt == LK_F32F18)
+    dslash_sel<StBF16, StBF16, LkF32F18, float>(st, a, in.nprop, dp.sel, nr_pref);
+  else if (in.prec == P_BF16 && out.prec == P_F32 && linkfmt == LK_F32F18)
+    dslash_sel<StBF16, StF32, LkF32F18, float>(st, a, in.nprop, dp.sel, nr_pref);
+  else if (in.prec == P_F32 && out.prec == P_BF16 && linkfmt == LK_F32F18)
+    dslash_sel<StF32, StBF16, LkF32F18, float>(st, a, in.nprop, dp.sel, nr_pref);
 }
 
 // ----------------------------------------------------------------- layout conversion
@@ -806,6 +815,26 @@ __global__ void k_cut_links(Geo g, void* __restrict__ links, int fmt) {
 
 void launch_cut_links(hipStream_t st, const Geo& g, void* links, int linkfmt) {
   hipLaunchKernelGGL(k_cut_links, dim3((2 * g.Vh + 255) / 256), dim3(256), 0, st, g, links, linkfmt);
+}
+
+__global__ void k_links_f64_to_f18(Geo g, const double2* __restrict__ src, float4* __restrict__ dst) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * g.Vh) return;
+  const int p = t / g.Vh, s = t - p * g.Vh;
+  const size_t Vh = g.Vh;
+  for (int mu = 0; mu < 4; ++mu) {
+    const double2* a = src + size_t(p * 4 + mu) * LkF64::NC * Vh;
+    float4* d = dst + size_t(p * 4 + mu) * LkF32F18::NC * Vh;
+    for (int k = 0; k < 5; ++k) {
+      const double2 x = a[(2 * k) * Vh + s];
+      const double2 y = 2 * k + 1 < 9 ? a[(2 * k + 1) * Vh + s] : make_double2(0.0, 0.0);
+      d[k * Vh + s] = make_float4(float(x.x), float(x.y), float(y.x), float(y.y));
+    }
+  }
+}
+void launch_links_f64_to_f18(hipStream_t st, const Geo& g, const void* f64, void* f18) {
+  hipLaunchKernelGGL(k_links_f64_to_f18, dim3((2 * g.Vh + 255) / 256), dim3(256), 0, st, g,
+                     (const double2*)f64, (float4*)f18);
 }
 
 // max that keeps a NaN (fmax drops it), so a link holding NaN or Inf marks the field

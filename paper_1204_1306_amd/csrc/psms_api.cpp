@@ -50,6 +50,8 @@ struct Slot {
   void* c12 = nullptr;
   void* f64_s = nullptr;  // the same links in the solver layout (when the layouts differ)
   void* c12_s = nullptr;
+  void* f18 = nullptr;    // FP32 18-real copies, made on first use by a mixed-precision
+  void* f18_s = nullptr;  // launch that includes a field that is not SU(3)
 };
 
 struct ProfRec {
@@ -390,21 +392,54 @@ struct Links {
   int fmt;
 };
 
-Links links_of(psms_ctx* c, const int* slots, int nprop, int fmt) {
+// FP32 18-real copies of a slot's links in both layouts (from its FP64 links, so outer-face
+// cuts carry over), made once per load.
+static void build_f18(psms_ctx* c, Slot& sl) {
+  // the internal layouts: g and, when the solver has its own, gs (swapped in solver view)
+  const Geo& gmain = c->solver_view ? c->gs : c->g;
+  launch_links_f64_to_f18(c->st, gmain, sl.f64, sl.f18);
+  if (c->split) {
+    const Geo& gsolv = c->solver_view ? c->g : c->gs;
+    launch_links_f64_to_f18(c->st, gsolv, sl.f64_s, sl.f18_s);
+  }
+}
+static void ensure_f18(psms_ctx* c, Slot& sl) {
+  if (sl.f18) return;
+  sl.f18 = dev_alloc(c, size_t(c->V) * 4 * LkF32F18::NC * 16);
+  if (c->split) sl.f18_s = dev_alloc(c, size_t(c->V) * 4 * LkF32F18::NC * 16);
+  build_f18(c, sl);
+}
+
+// Links of `nprop` gauge slots in the format fmt. A request for FP32 links (LK_F32C12)
+// gets the 12-real form when every slot is SU(3); with allow_f18 and a slot that is not,
+// every slot of the launch gets the 18-real form (LK_F32F18) instead; without allow_f18
+// (the network, which needs SU(3)) such a slot is PSMS_ENOTSU3.
+Links links_of(psms_ctx* c, const int* slots, int nprop, int fmt, bool allow_f18) {
   Links L{};
   L.fmt = fmt;
+  bool all_su3 = true;
   for (int i = 0; i < nprop; ++i) {
     REQUIRE(slots[i] >= 0 && slots[i] < 64 && c->slots[slots[i]].loaded, "gauge slot not loaded");
-    const Slot& sl = c->slots[slots[i]];
-    if (fmt == LK_F32C12) {
-      if (!sl.su3) throw Err{PSMS_ENOTSU3, "mixed precision needs SU(3) links (12-real compression)"};
+    all_su3 &= c->slots[slots[i]].su3;
+  }
+  if (fmt == LK_F32C12 && !all_su3) {
+    if (!allow_f18) throw Err{PSMS_ENOTSU3, "this operation needs SU(3) links (12-real compression)"};
+    L.fmt = LK_F32F18;
+  }
+  for (int i = 0; i < nprop; ++i) {
+    Slot& sl = c->slots[slots[i]];
+    if (L.fmt == LK_F32C12) {
       L.p[i] = c->solver_view ? sl.c12_s : sl.c12;
+    } else if (L.fmt == LK_F32F18) {
+      ensure_f18(c, sl);
+      L.p[i] = c->solver_view ? sl.f18_s : sl.f18;
     } else {
       L.p[i] = c->solver_view ? sl.f64_s : sl.f64;
     }
   }
   return L;
 }
+Links links_of(psms_ctx* c, const int* slots, int nprop, int fmt) { return links_of(c, slots, nprop, fmt, false); }
 
 // Workgroup order of a block-solver launch over `nprop` gauge fields (tuning key
 // block_xcd). Running the right-hand sides of a block back to back on one XCD pays when
@@ -522,14 +557,16 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
   FieldBatch dl = field(c, "sap_delta", sc.prec, np, nr);
   FieldBatch pb = field(c, "sap_p", sc.prec, np, nr);
   // The sweeps of the first cycle assign the iterate (x = delta), so it needs no zeroing,
-  // and read their residual straight from r when r has the solver's storage (else from a
-  // converted copy); the iterate is z itself when z has the solver's storage.
+  // and read their residual straight from r when r has the solver's storage or is the FP32
+  // residual of BF16 sweeps (else from a converted copy); the iterate is z itself when z
+  // has the solver's storage.
   const bool dz = z.prec == sc.prec, dr = r.prec == sc.prec;
+  const bool dr32 = !dr && r.prec == P_F32 && sc.prec == P_BF16;  // the sweeps read an FP32 residual too
   FieldBatch xs = dz ? z : field(c, "sap_x", sc.prec, np, nr);
   if (sc.cycles <= 0) {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_zero(c->st, xs, c->Vh);
-  } else if (!dr) {
+  } else if (!dr && !dr32) {
     ProfScope ps(c, FAM_BLAS, 0);
     launch_copy(c->st, c->g, r, rho, nullptr);
   }
@@ -552,7 +589,8 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
       bp.xcd_map = block_xcd_of(c, L.fmt, np);
       bp.eo = eo_form;
       if (cy == 0) {
-        if (dr) bp.rho_in = r.p;
+        if (dr || dr32) bp.rho_in = r.p;
+        bp.rho_in_f32 = dr32 ? 1 : 0;
         bp.x_assign = 1;
       }
       ProfScope ps(c, FAM_BLOCK, block_bytes(c, L, rho, bp.face));
@@ -779,7 +817,7 @@ FullSolveOut solve_full_impl(psms_ctx* c, const int* slots, const psms_solve_par
   const bool use_net = pp->pc == PSMS_PC_NET;
   if (use_net) REQUIRE(c->net.nlayers > 0, "PC_NET needs a network (psms_net_init or psms_net_load)");
   Links L32{};
-  if (pp->prec != PSMS_F64 || use_net) L32 = links_of(c, slots, np, LK_F32C12);
+  if (pp->prec != PSMS_F64 || use_net) L32 = links_of(c, slots, np, LK_F32C12, !use_net);
   if (pp->prec == PSMS_F64) {
     GcrCfg cf{P_F64, P_F64, pp->tol, pp->max_iter, restart, pp->pc == PSMS_PC_NONE ? PSMS_PC_NONE : PSMS_PC_SAP,
               SapCfg{pp->sap_cycles, pp->block_iters, P_F64}};
@@ -989,7 +1027,7 @@ double solve_colour_mixed(psms_ctx* c, const int* slots, int col, const FieldBat
                           int maxit, int* iters_host) {
   const int np = b.nprop, nrb = b.nrhs, nr = np * nrb;
   Links L64 = links_of(c, slots, np, LK_F64);
-  Links L32 = links_of(c, slots, np, LK_F32C12);
+  Links L32 = links_of(c, slots, np, LK_F32C12, true);
   FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
   FieldBatch rt = field(c, "bs_rt", P_F64, np, nrb);
   FieldBatch rho = field(c, "bs_rho32", P_F32, np, nrb);
@@ -1064,11 +1102,7 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
   const int np = b.nprop, nrb = b.nrhs, nr = np * nrb;
   Links L = links_of(c, slots, np, LK_F64);
   const bool passes32 = c->block_tol_prec == 1 || (c->block_tol_prec == 0 && 2 * c->g.Vbh != 256);
-  if (mixed && c->block_solver == 0 && passes32) {
-    bool su3 = true;
-    for (int i = 0; i < np; ++i) su3 &= c->slots[slots[i]].su3;
-    if (su3) return solve_colour_mixed(c, slots, col, b, x, tol, maxit, iters_host);
-  }
+  if (mixed && c->block_solver == 0 && passes32) return solve_colour_mixed(c, slots, col, b, x, tol, maxit, iters_host);
   if (c->block_solver == 1) {
     FieldBatch bc = field(c, "bs_bc", P_F64, np, nrb);
     {
@@ -1076,15 +1110,13 @@ double solve_colour(psms_ctx* c, const int* slots, int col, const FieldBatch& b,
       launch_copy(c->st, c->g, b, bc, nullptr);
       launch_keep_colour(c->st, c->g, bc, col);
     }
-    bool su3 = true;
-    for (int i = 0; i < np; ++i) su3 &= c->slots[slots[i]].su3;
     psms_solve_params p;
     psms_default_params(&p);
     p.tol = tol;
     p.max_iter = maxit;
     p.restart = 32;
     p.pc = PSMS_PC_NONE;
-    p.prec = su3 ? PSMS_MIXED : PSMS_F64;
+    p.prec = PSMS_MIXED;
     p.inner_tol = 1e-4;
     ColourOperator guard(c, col);
     FullSolveOut o = solve_full_impl(c, slots, &p, bc, x);
@@ -1442,7 +1474,7 @@ void psms_destroy(psms_ctx* c) {
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& s : c->slots)
-    for (void* p : {s.f64, s.c12, s.f64_s, s.c12_s})
+    for (void* p : {s.f64, s.c12, s.f64_s, s.c12_s, s.f18, s.f18_s})
       if (p) (void)hipFree(p);
   for (void* p : c->geo_mem) (void)hipFree(p);
   for (auto& r : c->recs) {
@@ -1488,6 +1520,7 @@ static psms_status load_links(psms_ctx* c, int slot, const double* dU) {
       launch_cut_links(c->st, c->gs, s.c12_s, LK_F32C12);
     }
   }
+  if (s.f18) build_f18(c, s);  // 18-real copies made for the previous field follow the new one
   const int nwg = 256;
   double* part = dscratch<double>(c, "unit_partial", nwg);
   launch_unitarity(c->st, c->g, dU, part, nwg);
@@ -1620,7 +1653,7 @@ psms_status psms_apply_dw(psms_ctx* c, int slot, const double* in, double* out, 
   const double* din = stage_in(c, in, nd, "stage_in");
   double* dout = stage_out(c, out, nd, "stage_out");
   Prec p = prec == PSMS_F64 ? P_F64 : P_F32;
-  Links L = links_of(c, &slot, 1, prec == PSMS_F64 ? LK_F64 : LK_F32C12);
+  Links L = links_of(c, &slot, 1, prec == PSMS_F64 ? LK_F64 : LK_F32C12, true);
   FieldBatch a = field(c, "api_a", p, 1, nrhs), b = field(c, "api_b", p, 1, nrhs);
   launch_pack(c->st, c->g, din, a);
   apply_D(c, L, a, b);
@@ -1644,7 +1677,7 @@ psms_status psms_apply_dw_lowp(psms_ctx* c, int slot, const double* in, double* 
   double* dout = stage_out(c, out, nd, "stage_out");
   Prec pi = in_storage == PSMS_SPINOR_BF16 ? P_BF16 : P_F32;
   Prec po = out_storage == PSMS_SPINOR_BF16 ? P_BF16 : P_F32;
-  Links L = links_of(c, &slot, 1, LK_F32C12);
+  Links L = links_of(c, &slot, 1, LK_F32C12, true);
   FieldBatch a = field(c, "api_lp_a", pi, 1, nrhs), b = field(c, "api_lp_b", po, 1, nrhs);
   launch_pack(c->st, c->g, din, a);
   dslash(c, L, a, b, HOP_ALL, -1, 1.0, -c->geom.kappa, 0);
@@ -2026,6 +2059,7 @@ static void interp_slot(psms_ctx* c, int dst, int s0, int s1, int N, int i) {
   }
   d.loaded = true;
   d.su3 = false;
+  if (d.f18) build_f18(c, d);  // FP32 copies made for an earlier field of this slot
 }
 
 psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* slot_Up, int nprop, const double* noise,
@@ -2034,8 +2068,6 @@ psms_status psms_logdet_ratio(psms_ctx* c, psms_op op, int slot_U, const int* sl
   check_params(pp);
   REQUIRE(op == PSMS_OP_FULL || op == PSMS_OP_SCHUR, "unknown operator");
   REQUIRE(n_interp >= 1 && n_interp <= 1024, "n_interp must be in [1, 1024]");
-  REQUIRE(n_interp == 1 || pp->prec == PSMS_F64,
-          "intermediate fields are not SU(3): n_interp > 1 needs prec PSMS_F64");
   REQUIRE(nprop >= 1 && nnoise >= 1 && slot_Up && noise && delta, "bad sizes or null pointers");
   REQUIRE(slot_U >= 0 && slot_U < 64 && c->slots[slot_U].loaded, "gauge slot not loaded");
   for (int p = 0; p < nprop; ++p)

@@ -115,15 +115,21 @@ def test_dw_mixed_precision(psms):
         assert rel(out[r], dirac.apply_D(U, psi[r], kappa, L)) < 2e-6
 
 
-def test_non_su3_links_refuse_mixed(psms):
+def test_non_su3_links_in_both_precisions(psms):
+    """Links scaled off SU(3): the load reports it, FP64 is exact, and mixed precision runs
+    on FP32 18-real links (a 12-real rebuild would be off by the scale) within FP32
+    rounding; the network, which takes 12-real links only, refuses the slot."""
     L, b = (4, 4, 4, 4), (2, 2, 2, 2)
     U = 0.9 * synth.gauge_field(L, 0.6, 17)
     ctx = make_ctx(psms, L, b, 0.12)
     assert ctx.gauge_load(0, U, allow_non_su3=True) is False
     psi = synth.gaussian_noise(L, 1, 18)[0]
-    assert rel(ctx.apply_dw(0, psi), dirac.apply_D(U, psi, 0.12, L)) < 1e-13
+    ref = dirac.apply_D(U, psi, 0.12, L)
+    assert rel(ctx.apply_dw(0, psi), ref) < 1e-13
+    assert rel(ctx.apply_dw(0, psi, prec=psms.MIXED), ref) < 2e-6
+    ctx.net_init((1, 1))
     with pytest.raises(psms.PsmsError):
-        ctx.apply_dw(0, psi, prec=psms.MIXED)
+        ctx.net_apply(0, psi)
 
 
 @pytest.mark.parametrize("L,b", GEOMS)
@@ -300,9 +306,10 @@ def test_logdet_ratio_small_workload(psms):
 def test_logdet_ratio_interpolated(psms):
     """Gauge-field interpolation (Sec. 4.3, eqs. gfparam, Mparam, staccN) with N = 3 on the
     4^4 workload, two proposals: same-noise Delta (sum over the three factors, each with its
-    own noise group) within 1e-8 absolute of the oracle, SCHUR and FULL. Mixed precision is
-    refused (the intermediate fields are not SU(3)), and the two slots the call borrows are
-    free again afterwards."""
+    own noise group) within 1e-8 absolute of the oracle, SCHUR and FULL, in FP64 and in mixed
+    precision (the intermediate fields are not SU(3): their inner solves use FP32 18-real
+    links inside FP64 defect correction), and the two slots the call borrows are free again
+    afterwards."""
     w, U, Ups, _ = synth.workload_inputs("4x4x4x4", nprop=2)
     N, nn = 3, 2
     eta = synth.gaussian_noise(w["L"], N * nn, 4711)
@@ -312,17 +319,19 @@ def test_logdet_ratio_interpolated(psms):
     ctx.gauge_load(2, Ups[1])
     prm = psms.default_params(tol=1e-12, max_iter=5000)
     g = schur.Geometry(w["L"], w["b"])
+    prm_mixed = psms.default_params(tol=1e-12, max_iter=5000, prec=psms.MIXED)
     for op, kind in ((psms.OP_SCHUR, "schur"), (psms.OP_FULL, "full")):
-        say("case interpolated", kind, "N", N)
-        d, st = ctx.logdet_ratio(op, 0, [1, 2], eta, prm, n_interp=N)
-        assert d.shape == (2, nn)
-        for p in range(2):
-            for j in range(nn):
-                ref = estimator.delta_interpolated(g, U, Ups[p], w["kappa"], [eta[i * nn + j] for i in range(N)], op=kind)
-                say(f"  p {p} j {j}: {d[p, j]:.12f} oracle {ref:.12f}")
-                assert abs(d[p, j] - ref) < 1e-8
-    with pytest.raises(psms.PsmsError):
-        ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, psms.default_params(tol=1e-10, prec=psms.MIXED), n_interp=N)
+        refs = {(p, j): estimator.delta_interpolated(g, U, Ups[p], w["kappa"], [eta[i * nn + j] for i in range(N)],
+                                                     op=kind) for p in range(2) for j in range(nn)}
+        for name, pr in (("f64", prm), ("mixed", prm_mixed)):
+            say("case interpolated", kind, name, "N", N)
+            d, st = ctx.logdet_ratio(op, 0, [1, 2], eta, pr, n_interp=N)
+            assert d.shape == (2, nn)
+            assert st["true_rel_residual"] <= 1.01e-12
+            for p in range(2):
+                for j in range(nn):
+                    say(f"  p {p} j {j}: {d[p, j]:.12f} oracle {refs[p, j]:.12f}")
+                    assert abs(d[p, j] - refs[p, j]) < 1e-8
     ctx.gauge_load(62, U)  # a borrowed slot, loadable again
     ctx.gauge_load(63, U)
 
@@ -330,27 +339,67 @@ def test_logdet_ratio_interpolated(psms):
 def test_logdet_ratio_interpolated_split_schwarz_blocks(psms):
     """The interpolated estimator (N = 2) in a context whose Schwarz blocks (2^4) differ from
     its domain blocks (4^4), so the intermediate fields are formed in both link layouts:
-    the same Deltas as the unsplit context. Both solve to 1e-12, where each Delta is
-    within 1e-8 of the exact value (the 8^4 estimator tests against the oracle), so the
-    two agree to 2e-8."""
+    the same Deltas as the unsplit context, in FP64 and in mixed precision (whose FP32
+    18-real links of the intermediate fields then exist in both layouts). All solve to
+    1e-12, where each Delta is within 1e-8 of the exact value (the 8^4 estimator tests
+    against the oracle), so any two agree to 2e-8."""
     w, U, Ups, _ = synth.workload_inputs("8x8x8x8", nprop=1)
     N, nn = 2, 2
     eta = synth.gaussian_noise(w["L"], N * nn, 4801)
-    prm = psms.default_params(tol=1e-12, max_iter=5000)
     out = []
-    for sap_b in (None, (2, 2, 2, 2)):
-        say("case interpolated, Schwarz blocks", sap_b)
-        ctx = psms.Context(w["L"], w["b"], w["kappa"], sap_b=sap_b)
-        ctx.gauge_load(0, U)
-        ctx.gauge_load(1, Ups[0])
-        d, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, prm, n_interp=N)
-        say("  delta", d.ravel(), st)
-        assert st["converged"] == 1
-        out.append(d)
-        ctx.close()
-    diff = float(np.abs(out[0] - out[1]).max())
-    say(f"  max |split - unsplit| = {diff:.2e} (bound 2e-8)")
+    for prec in (psms.F64, psms.MIXED):
+        prm = psms.default_params(tol=1e-12, max_iter=5000, prec=prec)
+        for sap_b in (None, (2, 2, 2, 2)):
+            say("case interpolated, Schwarz blocks", sap_b, "prec", prec)
+            ctx = psms.Context(w["L"], w["b"], w["kappa"], sap_b=sap_b)
+            ctx.gauge_load(0, U)
+            ctx.gauge_load(1, Ups[0])
+            d, st = ctx.logdet_ratio(psms.OP_SCHUR, 0, [1], eta, prm, n_interp=N)
+            say("  delta", d.ravel(), st)
+            assert st["converged"] == 1
+            out.append(d)
+            ctx.close()
+    diff = max(float(np.abs(o - out[0]).max()) for o in out[1:])
+    say(f"  max |case - unsplit FP64| = {diff:.2e} (bound 2e-8)")
     assert diff < 2e-8
+
+
+def test_dw_mixed_on_links_that_are_not_su3(psms):
+    """A field between U and U' (eq. gfparam with N = 2) is not SU(3): psms_gauge_load
+    reports PSMS_ENOTSU3, and the mixed-precision stencil then runs on FP32 copies of all
+    18 reals of each link. Against the oracle's D on the same field: FP32 operands within
+    2e-6 relative (as for SU(3) links), BF16 input with FP32 output within the bound of
+    a BF16 input (2^-8 relative per component, 8e-3 on the field). A second load of
+    another field into the slot replaces its FP32 copies. The network (12-real links only)
+    and psms_apply_dw_noalloc in MIXED (which may not allocate the copies) refuse it."""
+    w, U, Ups, _ = synth.workload_inputs("8x8x8x8", nprop=2)
+    L = w["L"]
+    psi = synth.gaussian_noise(L, 2, 4901)
+    ctx = make_ctx(psms, L, w["b"], w["kappa"])
+    for k, Up in enumerate(Ups):
+        Um = 0.5 * (U + Up)
+        say("case mixed stencil, interpolated field", k)
+        assert ctx.gauge_load(0, Um, allow_non_su3=True) is False
+        out = ctx.apply_dw(0, psi, prec=psms.MIXED)
+        for r in range(2):
+            ref = dirac.apply_D(Um, psi[r], w["kappa"], L)
+            e = rel(out[r], ref)
+            say(f"  FP32 18-real links: rel {e:.2e}")
+            assert e < 2e-6
+        lp = ctx.apply_dw_lowp(0, psi, psms.SPINOR_BF16, psms.SPINOR_F32)
+        e = rel(lp[0], dirac.apply_D(Um, psi[0], w["kappa"], L))
+        say(f"  BF16 input, FP32 output: rel {e:.2e}")
+        assert e < 8e-3
+    ctx.net_init((1, 2, 1))
+    with pytest.raises(psms.PsmsError):
+        ctx.net_apply(0, psi)
+    import torch
+
+    dpsi = torch.from_numpy(psi).to("cuda:0")
+    dout = torch.empty_like(dpsi)
+    assert ctx.apply_dw_noalloc(0, dpsi, dout, prec=psms.MIXED, check=False) == -5  # PSMS_ENOTSU3
+    assert ctx.apply_dw_noalloc(0, dpsi, dout, prec=psms.F64, check=False) == 0
+    ctx.close()
 
 
 def test_logdet_ratio_mixed_vs_f64_8x4(psms):
