@@ -30,6 +30,7 @@ struct BlockArgs {
   int eo_lanes;        // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int xcd_map;         // 1: workgroup order by XCD (block_coord)
   int rin_f32;         // 1: rho_in is an FP32 field (units of rin_stride per right-hand side)
+  int link16;          // 1: staged links in FP16 (Schwarz sweeps of the two-lane even-odd form)
   size_t rin_stride;
   int* iters;
 };
@@ -756,16 +757,21 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
 // Thread (j, h): site j of each parity; every hop phase gives each site two lanes
 // (h = 0 forward hops, h = 1 backward hops, wave-uniform), so no SIMD idles while
 // only one parity computes. The even-site state lives in lane 0, the odd in lane 1.
-template <class S, class LK, class T, bool STAGE = true>
-__global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+template <class S, class LK, class T, bool STAGE = true, bool L16 = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 3 : 1))) k_block_mr_eo(BlockArgs a) {
   constexpr int H = 128;  // sites per parity
   // STAGE: 12-real links staged in LDS times kappa (73 KB in FP32, two workgroups per CU),
   // so that a hop neither scales its result nor multiplies by kappa; otherwise read from L2
-  // at each hop (24 KB)
+  // at each hop (24 KB). L16: the staged links in FP16 (49 KB, three workgroups per CU), for
+  // Schwarz sweeps, whose fixed iteration counts do not need the last bits of the operator
   constexpr bool LL = LdsLinks<LK>::on && STAGE;
+  constexpr bool LH = LL && L16;
   __shared__ cx<T> ev[12][H];  // an even-site field; after a hop phase, lane 1's even partial sum
   __shared__ cx<T> od[12][H];  // an odd-site field (the two lanes' hop sums, added in turn)
-  __shared__ float4 lk_lds[LL ? 12 : 1][LL ? 2 * H : 1];
+  __shared__ float4 lk_lds[LL && !LH ? 12 : 1][LL && !LH ? 2 * H : 1];
+  __shared__ uint2 lk_h[LH ? 12 : 1][LH ? 2 * H : 1];
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
@@ -806,7 +812,12 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       float4 v = reinterpret_cast<const float4*>(lk)[(size_t(h * 4 + k / 3) * 3 + k % 3) * Vh + s];
-      lk_lds[k][h * H + j] = make_float4(kf * v.x, kf * v.y, kf * v.z, kf * v.w);
+      if constexpr (LH) {
+        const half4_t hv = {_Float16(kf * v.x), _Float16(kf * v.y), _Float16(kf * v.z), _Float16(kf * v.w)};
+        lk_h[k][h * H + j] = __builtin_bit_cast(uint2, hv);
+      } else {
+        lk_lds[k][h * H + j] = make_float4(kf * v.x, kf * v.y, kf * v.z, kf * v.w);
+      }
     }
   }
   // forward link of site (parity gp, in-block index q) in direction mu
@@ -814,7 +825,13 @@ __global__ void __launch_bounds__(256) k_block_mr_eo(BlockArgs a) {
     if constexpr (LL) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        float4 v = lk_lds[mu * 3 + k][gp * H + q];
+        float4 v;
+        if constexpr (LH) {
+          const half4_t hv = __builtin_bit_cast(half4_t, lk_h[mu * 3 + k][gp * H + q]);
+          v = make_float4(float(hv[0]), float(hv[1]), float(hv[2]), float(hv[3]));
+        } else {
+          v = lk_lds[mu * 3 + k][gp * H + q];
+        }
         U.m[(2 * k) / 3][(2 * k) % 3] = {T(v.x), T(v.y)};
         U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {T(v.z), T(v.w)};
       }
@@ -1284,6 +1301,7 @@ static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
         }
       }
       if (LL && !stage) launch_timed((k_block_mr_eo<S, LK, T, false>), grid, dim3(256), 0, st, a);
+      else if (LL && a.link16) launch_timed((k_block_mr_eo<S, LK, T, true, true>), grid, dim3(256), 0, st, a);
       else launch_timed((k_block_mr_eo<S, LK, T>), grid, dim3(256), 0, st, a);
       return;
     }
@@ -1332,6 +1350,7 @@ void launch_block_mr(hipStream_t st, const Geo& g, const void* const* links, int
   a.eo_lanes = bp.eo_lanes;
   a.xcd_map = bp.xcd_map;
   a.rin_f32 = bp.rho_in_f32;
+  a.link16 = bp.link16;
   a.rin_stride = units_per_field(P_F32, g.Vh);
   a.iters = iters_out;
   if (rho.prec == P_F64 && linkfmt == LK_F64) block_go<StF64, LkF64, double>(st, a, rho.nprop);

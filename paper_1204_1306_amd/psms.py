@@ -486,7 +486,7 @@ class Context:
     # ---------------------------------------------------------------- tuning
     TUNING_KEYS = ("dslash_variant_f64", "dslash_variant_f32", "dslash_variant_bf16", "nr_f64", "nr_low", "xcd_map",
                    "net_mfma", "block_solver", "block_lanes", "block_eo", "block_eo_lanes",
-                   "block_tol_prec", "sap_bf16", "block_xcd")
+                   "block_tol_prec", "sap_bf16", "block_xcd", "sap_link16")
 
     def set_tuning(self, key: str, value: int):
         self._check(self._lib.psms_set_tuning(self._h, key.encode(), int(value)))
