@@ -397,12 +397,12 @@ psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);
 psms_status psms_get_tuning(psms_ctx* ctx, const char* key, int* value);
 
 /* Autotuner: times every stencil form and right-hand-side blocking on this context's
- * geometry (HIP events; the mean of repeated launches, best of three interleaved rounds
+ * geometry (in the solvers' layout when the Schwarz blocks differ from the domain blocks) (HIP events; the mean of repeated launches, best of three interleaved rounds
  * after a warm-up round). Stencil forms are timed on two launch shapes: gauge slot `slot`
  * with 16 right-hand sides (1 from 2^20 sites up), and every other loaded gauge slot as
  * the proposals of one launch (up to the proposals one launch addresses, SU(3) slots only
  * for the reduced-precision forms; `slot` itself when there is no other) with 128
- * right-hand sides in all (8 from 2^20 sites up), on Gaussian inputs; BF16 forms also
+ * right-hand sides in all (from 2^20 sites up 8 per proposal), on Gaussian inputs; BF16 forms also
  * into FP32 outputs at the second shape. Forms whose kernels spill registers to scratch
  * are skipped while any form does not. The
  * form kept is the one whose worst slowdown against the fastest form of either shape is

@@ -2746,12 +2746,31 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     }
   } restore{c, c->prof};
   c->prof = false;
+  // The solvers apply the stencil in their own layout when the Schwarz blocks differ from
+  // the domain blocks (the 32^4 estimator: 4^4 inside 8^4): the forms are timed there.
+  struct SolverView {
+    psms_ctx* c;
+    bool on;
+    explicit SolverView(psms_ctx* cc) : c(cc), on(cc->split && !cc->solver_view) {
+      if (on) {
+        std::swap(c->g, c->gs);
+        c->solver_view = true;
+      }
+    }
+    ~SolverView() {
+      if (on) {
+        std::swap(c->g, c->gs);
+        c->solver_view = false;
+      }
+    }
+  } view(c);
   const int reps = c->V >= (1 << 20) ? 10 : 30;
   // Stencil forms are timed on two launch shapes the solvers make: one gauge field with
   // 16 right-hand sides (1 from 2^20 sites up, where one right-hand side is not bound by
   // launch latency), and the other loaded gauge fields as the proposals of one launch
-  // (as the batched estimator launches them) with 128 right-hand sides in all (8 from
-  // 2^20 sites up). After a warm-up round, each form keeps its best time over three
+  // (as the batched estimator launches them) with 128 right-hand sides in all (from 2^20
+  // sites up 8 per proposal, the 32^4 estimator's launches; each tuning buffer within
+  // 8 GiB). After a warm-up round, each form keeps its best time over three
   // interleaved rounds, so that clock changes during tuning favour no form. The pick is
   // the form whose worst slowdown against the fastest form of a shape is smallest: a form
   // that is fast on one shape and slow on the other loses to one that is good on both.
@@ -2785,11 +2804,11 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
     const int nsh = P == P_BF16 ? 3 : 2;
     double tv[NVAR][3];
     for (auto& row : tv) row[0] = row[1] = row[2] = 1e30;
-    // each tuning buffer (input, output, Gaussian staging) is kept within 2 GiB
-    const size_t cap = std::max<size_t>(1, (size_t(2) << 30) / (size_t(c->V) * 24 * sizeof(double)));
+    // each tuning buffer (input, output, Gaussian staging) is kept within 8 GiB
+    const size_t cap = std::max<size_t>(1, (size_t(8) << 30) / (size_t(c->V) * 24 * sizeof(double)));
     for (int si = 0; si < nsh; ++si) {
       const int np = si == 0 ? 1 : int(std::min<size_t>(props.size(), cap));
-      const int nrhs = int(std::min<size_t>(si == 0 ? (big ? 1 : 16) : std::max(1, (big ? 8 : 128) / np),
+      const int nrhs = int(std::min<size_t>(si == 0 ? (big ? 1 : 16) : (big ? 8 : std::max(1, 128 / np)),
                                             std::max<size_t>(1, cap / np)));
       Links L = links_of(c, si == 0 ? &slot : props.data(), np, fmt);
       FieldBatch in = field(c, "tune_in", P, np, nrhs);
