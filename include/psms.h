@@ -388,9 +388,11 @@ psms_status psms_net_load(psms_ctx* ctx, const char* path);
  * right-hand sides of one block back to back on one XCD, which then serves their link
  * reads from its L2, and gives each XCD a contiguous range of blocks; 0 the launch order;
  * 2, the default, 1 when the links the launch reads exceed the 256 MB Infinity Cache) and
- * "sap_link16" (mixed-precision Schwarz sweeps on 256-site blocks: 1, the default, stage
- * kappa times the 12-real links in LDS as FP16, three workgroups per compute unit; 0 as
- * FP32, two; block inverses to a tolerance always use FP32 links).
+ * "sap_link16" (mixed-precision Schwarz sweeps on 256-site blocks: 2, the default, stage
+ * kappa times the whole links in LDS as FP16 and exchange the block's fields between
+ * lanes in FP16, scaled to unit RMS per block, with the face update of 4^4 blocks spread
+ * over all lanes; 1 stages the 12-real links in FP16 and exchanges FP32 fields; 0 stages
+ * FP32 links; block inverses to a tolerance always use FP32 links).
  * Unknown keys or values give
  * PSMS_EINVAL. Results do not depend on the tuning beyond rounding; only speed does. */
 psms_status psms_set_tuning(psms_ctx* ctx, const char* key, int value);

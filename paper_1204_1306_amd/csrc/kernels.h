@@ -154,7 +154,8 @@ struct BlockMRParams {
   int eo_lanes = 0;              // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int xcd_map = 0;               // 1: the right-hand sides of one block run back to back on one XCD
   int rho_in_f32 = 0;            // 1: rho_in is FP32 (the kernel's storage otherwise)
-  int link16 = 0;                // 1: staged links in FP16 (fixed-iteration Schwarz sweeps only)
+  int link16 = 0;                // fixed-iteration Schwarz sweeps only: 1 staged 12-real links in FP16,
+                                 // 2 whole FP16 links and FP16 exchange fields
 };
 // For every block of the colour: (optionally) the face update of rho_b from the
 // other colour's delta, then delta = MR approximation of D_b^-1 rho_b, x += delta,

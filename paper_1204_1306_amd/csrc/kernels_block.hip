@@ -30,7 +30,8 @@ struct BlockArgs {
   int eo_lanes;        // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int xcd_map;         // 1: workgroup order by XCD (block_coord)
   int rin_f32;         // 1: rho_in is an FP32 field (units of rin_stride per right-hand side)
-  int link16;          // 1: staged links in FP16 (Schwarz sweeps of the two-lane even-odd form)
+  int link16;          // Schwarz sweeps of the two-lane even-odd form: 1 staged 12-real links in
+                       // FP16; 2 whole FP16 links and FP16 exchange fields
   size_t rin_stride;
   int* iters;
 };
@@ -759,19 +760,135 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
 // only one parity computes. The even-site state lives in lane 0, the odd in lane 1.
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 
-template <class S, class LK, class T, bool STAGE = true, bool L16 = false>
+// FP16 operands of the Schwarz sweeps: a spinor as 12 and an SU(3) matrix as 9 packed
+// (re, im) pairs. The spin projections add pairs in FP16; the colour products take the
+// halves directly as operands of FP32 fused multiply-adds (mixed-precision FMAs, no
+// conversions), and the hop sums accumulate in FP32.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+struct SpinorH { h2_t v[4][3]; };
+struct SU3H { h2_t m[3][3]; };
+__device__ __forceinline__ h2_t h_ti(h2_t a) { return h2_t{-a.y, a.x}; }
+__device__ __forceinline__ h2_t h_tmi(h2_t a) { return h2_t{a.y, -a.x}; }
+__device__ __forceinline__ float hf(_Float16 a) { return float(a); }
+__device__ __forceinline__ uint32_t h_pack(cx<float> z) {
+  return __builtin_bit_cast(uint32_t, h2_t{_Float16(z.re), _Float16(z.im)});
+}
+__device__ __forceinline__ cx<float> h_unpack(uint32_t w) {
+  const h2_t z = __builtin_bit_cast(h2_t, w);
+  return {float(z.x), float(z.y)};
+}
+// o = U v and o = U^+ v, each real component a chain of six fused multiply-adds
+__device__ __forceinline__ void su3h_mul(const SU3H& u, const h2_t (&v)[3], cx<float> (&o)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float re = __builtin_fmaf(hf(u.m[a][0].x), hf(v[0].x), 0.0f);
+    float im = __builtin_fmaf(hf(u.m[a][0].x), hf(v[0].y), 0.0f);
+    re = __builtin_fmaf(-hf(u.m[a][0].y), hf(v[0].y), re);
+    im = __builtin_fmaf(hf(u.m[a][0].y), hf(v[0].x), im);
+#pragma unroll
+    for (int b = 1; b < 3; ++b) {
+      re = __builtin_fmaf(hf(u.m[a][b].x), hf(v[b].x), re);
+      re = __builtin_fmaf(-hf(u.m[a][b].y), hf(v[b].y), re);
+      im = __builtin_fmaf(hf(u.m[a][b].x), hf(v[b].y), im);
+      im = __builtin_fmaf(hf(u.m[a][b].y), hf(v[b].x), im);
+    }
+    o[a] = {re, im};
+  }
+}
+__device__ __forceinline__ void su3h_dag_mul(const SU3H& u, const h2_t (&v)[3], cx<float> (&o)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float re = __builtin_fmaf(hf(u.m[0][a].x), hf(v[0].x), 0.0f);
+    float im = __builtin_fmaf(hf(u.m[0][a].x), hf(v[0].y), 0.0f);
+    re = __builtin_fmaf(hf(u.m[0][a].y), hf(v[0].y), re);
+    im = __builtin_fmaf(-hf(u.m[0][a].y), hf(v[0].x), im);
+#pragma unroll
+    for (int b = 1; b < 3; ++b) {
+      re = __builtin_fmaf(hf(u.m[b][a].x), hf(v[b].x), re);
+      re = __builtin_fmaf(hf(u.m[b][a].y), hf(v[b].y), re);
+      im = __builtin_fmaf(hf(u.m[b][a].x), hf(v[b].y), im);
+      im = __builtin_fmaf(-hf(u.m[b][a].y), hf(v[b].x), im);
+    }
+    o[a] = {re, im};
+  }
+}
+// acc += c U(x,mu) (1 - gamma_mu) psi(x+mu) and acc += c U(x-mu,mu)^+ (1 + gamma_mu) psi(x-mu),
+// the projections and reconstructions of hop_fwd and hop_bwd (chiral basis) on FP16 pairs
+__device__ __forceinline__ void hoph_fwd(int mu, const SU3H& U, const SpinorH& p, float c, Spinor<float>& acc) {
+  h2_t h0[3], h1[3];
+  cx<float> u0[3], u1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    switch (mu) {
+      case 0: h0[a] = p.v[0][a] + p.v[2][a]; h1[a] = p.v[1][a] + p.v[3][a]; break;
+      case 1: h0[a] = p.v[0][a] + h_ti(p.v[3][a]); h1[a] = p.v[1][a] + h_ti(p.v[2][a]); break;
+      case 2: h0[a] = p.v[0][a] + p.v[3][a]; h1[a] = p.v[1][a] - p.v[2][a]; break;
+      default: h0[a] = p.v[0][a] + h_ti(p.v[2][a]); h1[a] = p.v[1][a] - h_ti(p.v[3][a]); break;
+    }
+  }
+  su3h_mul(U, h0, u0);
+  su3h_mul(U, h1, u1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u0[a] = scale(c, u0[a]);
+    u1[a] = scale(c, u1[a]);
+    acc.v[0][a] = acc.v[0][a] + u0[a];
+    acc.v[1][a] = acc.v[1][a] + u1[a];
+    switch (mu) {
+      case 0: acc.v[2][a] = acc.v[2][a] + u0[a]; acc.v[3][a] = acc.v[3][a] + u1[a]; break;
+      case 1: acc.v[2][a] = acc.v[2][a] + times_mi(u1[a]); acc.v[3][a] = acc.v[3][a] + times_mi(u0[a]); break;
+      case 2: acc.v[2][a] = acc.v[2][a] - u1[a]; acc.v[3][a] = acc.v[3][a] + u0[a]; break;
+      default: acc.v[2][a] = acc.v[2][a] + times_mi(u0[a]); acc.v[3][a] = acc.v[3][a] + times_i(u1[a]); break;
+    }
+  }
+}
+__device__ __forceinline__ void hoph_bwd(int mu, const SU3H& U, const SpinorH& p, float c, Spinor<float>& acc) {
+  h2_t h0[3], h1[3];
+  cx<float> w0[3], w1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    switch (mu) {
+      case 0: h0[a] = p.v[0][a] - p.v[2][a]; h1[a] = p.v[1][a] - p.v[3][a]; break;
+      case 1: h0[a] = p.v[0][a] + h_tmi(p.v[3][a]); h1[a] = p.v[1][a] + h_tmi(p.v[2][a]); break;
+      case 2: h0[a] = p.v[0][a] - p.v[3][a]; h1[a] = p.v[1][a] + p.v[2][a]; break;
+      default: h0[a] = p.v[0][a] + h_tmi(p.v[2][a]); h1[a] = p.v[1][a] + h_ti(p.v[3][a]); break;
+    }
+  }
+  su3h_dag_mul(U, h0, w0);
+  su3h_dag_mul(U, h1, w1);
+  bwd_recon(mu, w0, w1, c, acc);
+}
+
+template <class S, class LK, class T, bool STAGE = true, int L16 = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 3 : 1))) k_block_mr_eo(BlockArgs a) {
   constexpr int H = 128;  // sites per parity
   // STAGE: 12-real links staged in LDS times kappa (73 KB in FP32, two workgroups per CU),
   // so that a hop neither scales its result nor multiplies by kappa; otherwise read from L2
-  // at each hop (24 KB). L16: the staged links in FP16 (49 KB, three workgroups per CU), for
-  // Schwarz sweeps, whose fixed iteration counts do not need the last bits of the operator
+  // at each hop (24 KB). For Schwarz sweeps, whose fixed iteration counts do not need the
+  // last bits of the operator, L16 = 1 stages the 12-real links in FP16 (49 KB, three
+  // workgroups per CU), and L16 = 2 stages whole links in FP16 and exchanges the fields
+  // between lanes in FP16 too (49 KB): each hop then reads 84 bytes of LDS instead of 120,
+  // rebuilds no row and converts nothing. The FP16 fields are the block's own, scaled to
+  // unit RMS per component (the minimal-residual iteration is homogeneous; its
+  // coefficients do not change), so their range is that of FP16 at any residual size.
   constexpr bool LL = LdsLinks<LK>::on && STAGE;
-  constexpr bool LH = LL && L16;
-  __shared__ cx<T> ev[12][H];  // an even-site field; after a hop phase, lane 1's even partial sum
-  __shared__ cx<T> od[12][H];  // an odd-site field (the two lanes' hop sums, added in turn)
-  __shared__ float4 lk_lds[LL && !LH ? 12 : 1][LL && !LH ? 2 * H : 1];
+  constexpr bool LH = LL && L16 == 1;
+  constexpr bool XH = LL && L16 == 2 && sizeof(T) == 4;
+  constexpr int NE = XH ? 1 : 12, NH = XH ? 1 : H;
+  __shared__ cx<T> ev[NE][NH];  // an even-site field; after a hop phase, lane 1's even partial sum
+  __shared__ cx<T> od[NE][NH];  // an odd-site field (the two lanes' hop sums, added in turn)
+  __shared__ float4 lk_lds[LL && !LH && !XH ? 12 : 1][LL && !LH && !XH ? 2 * H : 1];
   __shared__ uint2 lk_h[LH ? 12 : 1][LH ? 2 * H : 1];
+  // FP16 form (48 KB): the two fields in FP16 (four pairs per unit), then the whole FP16
+  // links, link (gp, mu, q) at index (gp * 4 + mu) * H + q in pairs 0-3, 4-7 and 8. Before
+  // the links are staged, the same memory holds the face hops of 4^4 blocks in FP32.
+  __shared__ uint4 xlds[XH ? 24 * H : 1];
+  uint4(*evh)[H] = reinterpret_cast<uint4(*)[H]>(xlds);
+  uint4(*odh)[H] = reinterpret_cast<uint4(*)[H]>(xlds + 3 * H);
+  uint4* lk_a = xlds + 6 * H;
+  uint4* lk_b = xlds + 14 * H;
+  uint32_t* lk_c = reinterpret_cast<uint32_t*>(xlds + 22 * H);
+  float4(*fc)[4 * H] = reinterpret_cast<float4(*)[4 * H]>(xlds);  // [6][512]: face hop t, 12 complex
   __shared__ double sm[3][16];
   const Geo& g = a.g;
   const size_t Vh = g.Vh;
@@ -792,7 +909,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
 
   // in-block neighbours of this lane's four hops: nA for the odd site j (even
   // neighbours), nB for the even site j (odd neighbours); -1 when the hop leaves the block
-  int nA[4], nB[4], gA[4], gB[4];
+  int nA[4], nB[4], gA[4], gB[4], lo[4];
   {
     SiteInfo so, se;
     site_info(g, 1, s, so);
@@ -805,10 +922,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
       Nbr m = neighbour(g, se, mu, h == 0 ? +1 : -1);
       nB[mu] = m.cross ? -1 : m.s - blk * H;
       gB[mu] = m.s;
+      lo[mu] = h ? so.l[mu] : se.l[mu];  // local coordinates of this lane's own site
     }
   }
   const float kf = float(a.kappa), ik = float(1.0 / a.kappa);
-  if constexpr (LL) {  // lane h stages kappa times the forward links of site j of parity h
+  if constexpr (LL && !XH) {  // lane h stages kappa times the forward links of site j of parity h
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       float4 v = reinterpret_cast<const float4*>(lk)[(size_t(h * 4 + k / 3) * 3 + k % 3) * Vh + s];
@@ -818,6 +936,129 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
       } else {
         lk_lds[k][h * H + j] = make_float4(kf * v.x, kf * v.y, kf * v.z, kf * v.w);
       }
+    }
+  }
+  // own site (parity h): rho (+ the face update)
+  Spinor<T> r, d, acc;
+  load_rho0<S>(a, rho, rix, h, s, r);
+  // FP16 form: the links to stage are written after the face update, whose hops use the
+  // same LDS; they are fetched as soon as the face hops are done, so that their latency
+  // overlaps the gather
+  float4 lraw[XH ? 12 : 1];
+  auto fetch_links = [&]() {
+    static_assert(!XH || std::is_same<LK, LkF32C12>::value, "the FP16 form stages 12-real FP32 links");
+#pragma unroll
+    for (int k = 0; k < 12; ++k) lraw[k] = reinterpret_cast<const float4*>(lk)[(size_t(h * 4 + k / 3) * 3 + k % 3) * Vh + s];
+  };
+  if constexpr (XH) {
+    // Face update of a 4^4 block: the 512 hops that enter it from its eight neighbours,
+    // two per lane and every lane busy. Hop t runs in direction t >> 7, forward from the
+    // face l_mu = 3 when t & 64 is 0, else backward from the face l_mu = 0; t & 63 holds
+    // the other three local coordinates, two bits each in increasing direction order. The
+    // hops go to LDS in FP32 and each lane adds those of its own site, in direction order.
+    if (a.face && g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4) {
+      SiteInfo si;
+      const uint32_t bw = g.bcoord[blk];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) si.B[m] = (bw >> (8 * m)) & 255;
+      si.colour = blk >= g.nblk_c ? 1 : 0;
+      si.lexB = 2 * (blk - si.colour * g.nblk_c) + (si.B[3] & 1);
+      // hop t in direction MU (a constant, so that the site tables index statically)
+      auto face_hop = [&](auto MU, int t) {
+        constexpr int mu = decltype(MU)::value;
+        const bool fwd = __builtin_amdgcn_readfirstlane((t >> 6) & 1) == 0;
+        int ll = 0, par = 0, c = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          int l;
+          if (m == mu) {
+            l = fwd ? 3 : 0;
+          } else {
+            l = (t >> (2 * c)) & 3;
+            ++c;
+          }
+          si.l[m] = l;
+          ll += l * g.sl[m];
+          par += l;
+        }
+        par &= 1;
+        si.locallex = ll;
+        const Nbr n = neighbour(g, si, mu, fwd ? +1 : -1);
+        Spinor<T> nb, f;
+        zero(f);
+        S::load(dl + size_t(1 - par) * S::NC * Vh, Vh, n.s, nb);
+        SU3<T> U;
+        if (fwd) {
+          LK::load(lk + size_t(par * 4 + mu) * LK::NC * Vh, Vh, blk * H + (ll >> 1), U);
+          hop_fwd(mu, U, nb, kp * T(n.sign), f);
+        } else {
+          LK::load(lk + size_t((1 - par) * 4 + mu) * LK::NC * Vh, Vh, n.s, U);
+          hop_bwd(mu, U, nb, kp * T(n.sign), f);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          fc[q][t] = make_float4(f.v[(2 * q) / 3][(2 * q) % 3].re, f.v[(2 * q) / 3][(2 * q) % 3].im,
+                                 f.v[(2 * q + 1) / 3][(2 * q + 1) % 3].re, f.v[(2 * q + 1) / 3][(2 * q + 1) % 3].im);
+      };
+      // waves 0-3 take directions 0, 0, 1, 1 (forward, backward in turn), then 2, 2, 3, 3
+      const int t0 = int(threadIdx.x);
+      if (__builtin_amdgcn_readfirstlane(t0 >> 7) == 0) {
+        face_hop(std::integral_constant<int, 0>{}, t0);
+        face_hop(std::integral_constant<int, 2>{}, t0 + 2 * H);
+      } else {
+        face_hop(std::integral_constant<int, 1>{}, t0);
+        face_hop(std::integral_constant<int, 3>{}, t0 + 2 * H);
+      }
+      fetch_links();
+      __syncthreads();
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        const int lm = lo[mu];
+        if (lm == 3 || lm == 0) {
+          int e = 0, c = 0;
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (m != mu) {
+              e |= lo[m] << (2 * c);
+              ++c;
+            }
+          const int t = mu * 128 + (lm == 3 ? 0 : 64) + e;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            const float4 v = fc[q][t];
+            cx<T>& z0 = r.v[(2 * q) / 3][(2 * q) % 3];
+            cx<T>& z1 = r.v[(2 * q + 1) / 3][(2 * q + 1) % 3];
+            z0 = {z0.re + v.x, z0.im + v.y};
+            z1 = {z1.re + v.z, z1.im + v.w};
+          }
+        }
+      }
+      __syncthreads();  // the links are staged over the face hops
+    } else {
+      if (a.face) face_update<S, LK, T>(g, lk, dl, h, s, kp, r);
+      fetch_links();
+    }
+  } else if (a.face) {
+    face_update<S, LK, T>(g, lk, dl, h, s, kp, r);
+  }
+  if constexpr (XH) {  // lane h stages kappa times the forward links of site j of parity h (whole, FP16)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      SU3<float> U;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float4 v = lraw[mu * 3 + k];
+        U.m[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+        U.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+      }
+      su3_row2(U, 1.0f);
+      uint32_t w[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) w[k] = h_pack(scale(kf, U.m[k / 3][k % 3]));
+      const int i = (h * 4 + mu) * H + j;
+      lk_a[i] = make_uint4(w[0], w[1], w[2], w[3]);
+      lk_b[i] = make_uint4(w[4], w[5], w[6], w[7]);
+      lk_c[i] = w[8];
     }
   }
   // forward link of site (parity gp, in-block index q) in direction mu
@@ -848,105 +1089,144 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
   };
   using P1 = std::integral_constant<int, 1>;
   using M1 = std::integral_constant<int, -1>;
-  // this lane's hops of the odd site j, applied to the even field ev
-  auto phase_odd = [&](auto sg, Spinor<T>& acc) {
+  // FP16 forms: link (gp, mu, q) and the spinor of site q of an exchange field
+  auto link_h = [&](int mu, int gp, int q, SU3H& U) {
+    const int i = (gp * 4 + mu) * H + q;
+    const uint4 x = lk_a[i], y = lk_b[i];
+    const uint32_t w[9] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, lk_c[i]};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) U.m[k / 3][k % 3] = __builtin_bit_cast(h2_t, w[k]);
+  };
+  auto spinor_h = [&](const uint4 (*f)[H], int q, SpinorH& p) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint4 x = f[k][q];
+      const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p.v[(4 * k + e) / 3][(4 * k + e) % 3] = __builtin_bit_cast(h2_t, w[e]);
+    }
+  };
+  // site j of the even (E = 0) or odd (E = 1) exchange field: put, add to, read
+  auto put = [&](int E, const Spinor<T>& v) {
+    if constexpr (XH) {
+      uint4 (*f)[H] = E ? odh : evh;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        f[k][j] = make_uint4(h_pack(v.v[(4 * k) / 3][(4 * k) % 3]), h_pack(v.v[(4 * k + 1) / 3][(4 * k + 1) % 3]),
+                             h_pack(v.v[(4 * k + 2) / 3][(4 * k + 2) % 3]), h_pack(v.v[(4 * k + 3) / 3][(4 * k + 3) % 3]));
+    } else {
+      cx<T>(*f)[NH] = E ? od : ev;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) f[k][j] = v.v[k / 3][k % 3];
+    }
+  };
+  auto get = [&](int E, Spinor<T>& v) {
+    if constexpr (XH) {
+      const uint4(*f)[H] = E ? odh : evh;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const uint4 x = f[k][j];
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v.v[(4 * k + e) / 3][(4 * k + e) % 3] = h_unpack(w[e]);
+      }
+    } else {
+      const cx<T>(*f)[NH] = E ? od : ev;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v.v[k / 3][k % 3] = f[k][j];
+    }
+  };
+  // this lane's hops of site j of parity P (1: the odd site, applied to the even field;
+  // 0: the even site, applied to the odd field)
+  auto phase = [&](auto P, auto sg, Spinor<T>& acc) {
+    constexpr int p = decltype(P)::value;
     const T c = coef(sg);
     zero(acc);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-      const int q = nA[mu];
+      const int q = p ? nA[mu] : nB[mu];
       if (q >= 0) {
-        SU3<T> U;
-        if (h == 0) link(mu, 1, j, s, U);  // U(x, mu) of the odd site
-        else link(mu, 0, q, gA[mu], U);    // U(x - mu, mu) of its even neighbour
-        Spinor<T> nb;
+        if constexpr (XH) {
+          SU3H U;
+          if (h == 0) link_h(mu, p, j, U);  // U(x, mu) of site j
+          else link_h(mu, 1 - p, q, U);     // U(x - mu, mu) of its neighbour
+          SpinorH nb;
+          spinor_h(p ? evh : odh, q, nb);
+          if (h == 0) hoph_fwd(mu, U, nb, c, acc);
+          else hoph_bwd(mu, U, nb, c, acc);
+        } else {
+          SU3<T> U;
+          if (h == 0) link(mu, p, j, s, U);
+          else link(mu, 1 - p, q, p ? gA[mu] : gB[mu], U);
+          Spinor<T> nb;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = ev[k][q];
-        if (h == 0) hop_fwd(mu, U, nb, c, acc);
-        else hop_bwd(mu, U, nb, c, acc);
+          for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = p ? ev[k][q] : od[k][q];
+          if (h == 0) hop_fwd(mu, U, nb, c, acc);
+          else hop_bwd(mu, U, nb, c, acc);
+        }
       }
     }
   };
-  // this lane's hops of the even site j, applied to od
-  auto phase_even = [&](auto sg, Spinor<T>& acc) {
-    const T c = coef(sg);
-    zero(acc);
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      const int q = nB[mu];
-      if (q >= 0) {
-        SU3<T> U;
-        if (h == 0) link(mu, 0, j, s, U);
-        else link(mu, 1, q, gB[mu], U);
-        Spinor<T> nb;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = od[k][q];
-        if (h == 0) hop_fwd(mu, U, nb, c, acc);
-        else hop_bwd(mu, U, nb, c, acc);
-      }
-    }
-  };
+  auto phase_odd = [&](auto sg, Spinor<T>& acc) { phase(std::integral_constant<int, 1>{}, sg, acc); };
+  auto phase_even = [&](auto sg, Spinor<T>& acc) { phase(std::integral_constant<int, 0>{}, sg, acc); };
 
-  // own site (parity h): rho (+ the face update), |rho|^2 over the block
-  Spinor<T> r, d, acc;
-  load_rho0<S>(a, rho, rix, h, s, r);
-  if (a.face) face_update<S, LK, T>(g, lk, dl, h, s, kp, r);
+  // |rho|^2 over the block
   double b2 = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < 3; ++c) b2 += double(r.v[q][c].re) * r.v[q][c].re + double(r.v[q][c].im) * r.v[q][c].im;
   b2 = wg_sum(b2, sm[0]);
-  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 : -1.0;
+  // FP16 exchange: work on sig * rho, with unit RMS per real component over the block
+  const T sig = XH && b2 > 0.0 ? T(sqrt(double(24 * 2 * H) / b2)) : T(1);
+  if constexpr (XH) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r.v[q][c] = scale(sig, r.v[q][c]);
+  }
+  const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 * double(sig) * double(sig) : -1.0;
   zero(d);
 
   // even right-hand side rho_e + k H_eo rho_o (lane 0); lane 1 keeps rho_o
-  if (h == 1) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) od[k][j] = r.v[k / 3][k % 3];
-  }
+  if (h == 1) put(1, r);
   __syncthreads();
   phase_even(P1{}, acc);
-  if (h == 1) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) ev[k][j] = acc.v[k / 3][k % 3];
-  }
+  if (h == 1) put(0, acc);
   __syncthreads();
   if (h == 0) {
+    Spinor<T> e;
+    get(0, e);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) r.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + ev[k][j];
+    for (int k = 0; k < 12; ++k) r.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + e.v[k / 3][k % 3];
   }
 
   int it = 0;
   if (b2 > 0.0) {
     for (; it < a.niter; ++it) {
       // p = (1 - k^2 H_eo H_oe) r on the even sites
-      if (h == 0) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) ev[k][j] = r.v[k / 3][k % 3];
-      }
+      if (h == 0) put(0, r);
       __syncthreads();
       phase_odd(P1{}, acc);
-      if (h == 0) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) od[k][j] = acc.v[k / 3][k % 3];
-      }
+      if (h == 0) put(1, acc);
       __syncthreads();
       if (h == 1) {
+        Spinor<T> o;
+        get(1, o);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) od[k][j] = od[k][j] + acc.v[k / 3][k % 3];
+        for (int k = 0; k < 12; ++k) o.v[k / 3][k % 3] = o.v[k / 3][k % 3] + acc.v[k / 3][k % 3];
+        put(1, o);
       }
       __syncthreads();
       phase_even(M1{}, acc);
-      if (h == 1) {  // ev is free: every read of it was in phase_odd
-#pragma unroll
-        for (int k = 0; k < 12; ++k) ev[k][j] = acc.v[k / 3][k % 3];
-      }
+      if (h == 1) put(0, acc);  // ev is free: every read of it was in phase_odd
       __syncthreads();
       double prr = 0.0, pri = 0.0, pp = 0.0;
       if (h == 0) {
+        Spinor<T> e;
+        get(0, e);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + ev[k][j];
+        for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + e.v[k / 3][k % 3];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -981,23 +1261,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
     }
   }
   // x_o = rho_o + k H_oe x_e; the odd residual is then zero
-  if (h == 0) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) ev[k][j] = d.v[k / 3][k % 3];
-  }
+  if (h == 0) put(0, d);
   __syncthreads();
   phase_odd(P1{}, acc);
-  if (h == 0) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) od[k][j] = acc.v[k / 3][k % 3];
-  }
+  if (h == 0) put(1, acc);
   __syncthreads();
   if (h == 1) {
+    Spinor<T> o;
+    get(1, o);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      d.v[k / 3][k % 3] = r.v[k / 3][k % 3] + od[k][j] + acc.v[k / 3][k % 3];
+      d.v[k / 3][k % 3] = r.v[k / 3][k % 3] + o.v[k / 3][k % 3] + acc.v[k / 3][k % 3];
       r.v[k / 3][k % 3] = {T(0), T(0)};
     }
+  }
+  if constexpr (XH) {  // back to the scale of rho
+    const T isig = T(1) / sig;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        r.v[q][c] = scale(isig, r.v[q][c]);
+        d.v[q][c] = scale(isig, d.v[q][c]);
+      }
   }
   S::store(rho + size_t(h) * S::NC * Vh, Vh, s, r);
   S::store(dl + size_t(h) * S::NC * Vh, Vh, s, d);
@@ -1301,7 +1587,8 @@ static void block_go(hipStream_t st, const BlockArgs& a, int nprop) {
         }
       }
       if (LL && !stage) launch_timed((k_block_mr_eo<S, LK, T, false>), grid, dim3(256), 0, st, a);
-      else if (LL && a.link16) launch_timed((k_block_mr_eo<S, LK, T, true, true>), grid, dim3(256), 0, st, a);
+      else if (LL && a.link16 == 2 && sizeof(T) == 4) launch_timed((k_block_mr_eo<S, LK, T, true, 2>), grid, dim3(256), 0, st, a);
+      else if (LL && a.link16) launch_timed((k_block_mr_eo<S, LK, T, true, 1>), grid, dim3(256), 0, st, a);
       else launch_timed((k_block_mr_eo<S, LK, T>), grid, dim3(256), 0, st, a);
       return;
     }

@@ -89,7 +89,7 @@ struct psms_ctx {
   int block_eo_lanes = 0;      // even-odd form on 256-site FP32 blocks: lanes per site (2, 4; 0 = by grid)
   int block_tol_prec = 0;      // mixed block inverses to tolerance: 1 FP32 passes, 2 FP64, 0 = by block size
   int sap_bf16 = 1;            // BF16 Krylov basis: Schwarz fields in BF16 (1) or FP32 (0)
-  int sap_link16 = 1;          // Schwarz sweeps with their staged links in FP16 (1) or FP32 (0)
+  int sap_link16 = 2;          // Schwarz sweeps: staged links FP32 (0), FP16 12-real (1), FP16 links and fields (2)
   int block_xcd = 2;           // block launches: right-hand sides of a block back to back on one XCD
                                // (1), launch order (0), 1 when the links exceed the Infinity Cache (2)
   // pinned host slots for the lagged convergence check of the GCR iteration
@@ -577,8 +577,10 @@ void sap_apply(psms_ctx* c, const Links& L, const SapCfg& sc, const FieldBatch& 
   // much as two plain ones. The staged form takes 73 KB of LDS, so two workgroups share a
   // CU, and a hop reads its kappa-scaled link from LDS: at 32^4 a sweep takes 4.55 ms
   // against 5.14 ms with the links read from L2, at 16^4 1.15 against 1.26 ms. With the
-  // staged links in FP16 (sap_link16, the default) it takes 49 KB and three workgroups
-  // share a CU: 3.70 ms at 32^4, 0.94 ms at 16^4, the same iteration counts.
+  // staged 12-real links in FP16 (sap_link16 1) it takes 49 KB and three workgroups
+  // share a CU: 3.66 ms at 32^4, 0.94 ms at 16^4, the same iteration counts. With whole
+  // FP16 links, the fields exchanged in FP16 and the face update spread over all lanes
+  // (sap_link16 2, the default; 4^4 blocks), 3.19 ms at 32^4, again the same iterations.
   // (Block inverses to a tolerance keep FP32 links.)
   const int eo_form = c->block_eo == 0 ? 0 : c->block_eo == 3 ? 2 : 1;
   const int iters = c->block_eo >= 2 ? (sc.iters + 1) / 2 : sc.iters;
@@ -2656,8 +2658,10 @@ psms_status psms_set_tuning(psms_ctx* c, const char* key, int value) {
   else if (!std::strcmp(key, "block_eo"))
     REQUIRE(value >= 0 && value <= 3, "block_eo must be 0 (plain), 1 (even-odd), 2 (by launch shape) or 3 (even-odd, links from L2)");
   else if (!std::strcmp(key, "xcd_map") || !std::strcmp(key, "net_mfma") || !std::strcmp(key, "block_solver") ||
-           !std::strcmp(key, "sap_bf16") || !std::strcmp(key, "sap_link16"))
+           !std::strcmp(key, "sap_bf16"))
     REQUIRE(value == 0 || value == 1, "flag must be 0 or 1");
+  else if (!std::strcmp(key, "sap_link16"))
+    REQUIRE(value >= 0 && value <= 2, "sap_link16 must be 0 (FP32 links), 1 (FP16 12-real links) or 2 (FP16 links and fields)");
   else if (!std::strcmp(key, "block_xcd"))
     REQUIRE(value >= 0 && value <= 2, "block_xcd must be 0 (launch order), 1 (by XCD) or 2 (by link footprint)");
   else if (!std::strcmp(key, "block_eo_lanes"))

@@ -193,11 +193,12 @@ def test_solve_parity(psms, prec, eo, lanes):
         assert np.linalg.norm(res) / np.linalg.norm(bvec[r]) <= 1e-10 * 1.01
 
 
-@pytest.mark.parametrize("link16", [0, 1])
+@pytest.mark.parametrize("link16", [0, 1, 2])
 def test_solve_schwarz_link_storage(psms, link16):
-    """Mixed-precision solves whose Schwarz sweeps stage their links in LDS as FP16 (the
-    default) or FP32: the flexible solver meets the FP64 true residual either way, so the
-    rounding of the preconditioner's links never reaches the answer."""
+    """Mixed-precision solves whose Schwarz sweeps stage their links in LDS as FP32 (0),
+    as FP16 12-real links (1) or as whole FP16 links with the fields exchanged between
+    lanes in FP16 (2): the flexible solver meets the FP64 true residual either way, so the
+    rounding inside the preconditioner never reaches the answer."""
     L, b = (8, 8, 8, 8), (4, 4, 4, 4)
     kappa = 0.155
     U = synth.gauge_field(L, 0.6, 2002)
@@ -207,7 +208,7 @@ def test_solve_schwarz_link_storage(psms, link16):
     ctx.set_tuning("sap_link16", link16)
     ctx.set_tuning("block_eo_lanes", 2)  # the two-lane form, which stages the links
     for st_ in (psms.SPINOR_F32, psms.SPINOR_BF16):
-        say("case solve, Schwarz links FP16" if link16 else "case solve, Schwarz links FP32", "storage", st_)
+        say("case solve, Schwarz LDS form", link16, "storage", st_)
         x, st = ctx.solve(0, bvec, psms.default_params(tol=1e-10, prec=psms.MIXED, inner_storage=st_))
         say(" stats", st)
         assert st["converged"] == 1
