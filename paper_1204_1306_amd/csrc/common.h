@@ -80,6 +80,15 @@ __host__ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return uint16_t(u >> 16);
 }
 __host__ __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
+// Two floats to a packed bfloat16 pair (lo, hi) with gfx950's conversion instruction: one
+// instruction per pair, but its results differ from f32_to_bf16 on some inputs, so it is
+// used only where the rounding of the last bit does not matter (the Schwarz
+// preconditioner's own fields); every other BF16 store rounds to nearest even exactly.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pack2(float lo, float hi) {
+  const bf16x2_t v = {__bf16(lo), __bf16(hi)};
+  return __builtin_bit_cast(uint32_t, v);
+}
 
 // Non-temporal 16-byte accesses (streamed data that is not read again soon: the
 // output of a full-lattice stencil), so the L2 keeps the neighbour spinors.

@@ -760,16 +760,16 @@ __global__ void __launch_bounds__(512) k_block_mr_lds2(BlockArgs a) {
 // only one parity computes. The even-site state lives in lane 0, the odd in lane 1.
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 
-// FP16 operands of the Schwarz sweeps: a spinor as 12 and an SU(3) matrix as 9 packed
-// (re, im) pairs. The spin projections add pairs in FP16; the colour products take the
-// halves directly as operands of FP32 fused multiply-adds (mixed-precision FMAs, no
-// conversions), and the hop sums accumulate in FP32.
+// FP16 arithmetic of the Schwarz sweeps: a spinor as 12 and an SU(3) matrix as 9 packed
+// (re, im) pairs. Spin projections, colour products and hop sums run on the pairs with
+// packed FP16 instructions (a complex multiply-add is two packed FMAs, the broadcasts and
+// swaps being operand modifiers); the iterate and residual stay in FP32.
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 struct SpinorH { h2_t v[4][3]; };
 struct SU3H { h2_t m[3][3]; };
 __device__ __forceinline__ h2_t h_ti(h2_t a) { return h2_t{-a.y, a.x}; }
 __device__ __forceinline__ h2_t h_tmi(h2_t a) { return h2_t{a.y, -a.x}; }
-__device__ __forceinline__ float hf(_Float16 a) { return float(a); }
+__device__ __forceinline__ h2_t h_fma(h2_t a, h2_t b, h2_t c) { return __builtin_elementwise_fma(a, b, c); }
 __device__ __forceinline__ uint32_t h_pack(cx<float> z) {
   return __builtin_bit_cast(uint32_t, h2_t{_Float16(z.re), _Float16(z.im)});
 }
@@ -777,46 +777,42 @@ __device__ __forceinline__ cx<float> h_unpack(uint32_t w) {
   const h2_t z = __builtin_bit_cast(h2_t, w);
   return {float(z.x), float(z.y)};
 }
-// o = U v and o = U^+ v, each real component a chain of six fused multiply-adds
-__device__ __forceinline__ void su3h_mul(const SU3H& u, const h2_t (&v)[3], cx<float> (&o)[3]) {
+__device__ __forceinline__ cx<float> h_f32(h2_t z) { return {float(z.x), float(z.y)}; }
+// o = U v: u v = u.re (v.re, v.im) + u.im (-v.im, v.re)
+__device__ __forceinline__ void su3h_mul(const SU3H& u, const h2_t (&v)[3], h2_t (&o)[3]) {
+  h2_t vs[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) vs[b] = h2_t{-v[b].y, v[b].x};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float re = __builtin_fmaf(hf(u.m[a][0].x), hf(v[0].x), 0.0f);
-    float im = __builtin_fmaf(hf(u.m[a][0].x), hf(v[0].y), 0.0f);
-    re = __builtin_fmaf(-hf(u.m[a][0].y), hf(v[0].y), re);
-    im = __builtin_fmaf(hf(u.m[a][0].y), hf(v[0].x), im);
-#pragma unroll
-    for (int b = 1; b < 3; ++b) {
-      re = __builtin_fmaf(hf(u.m[a][b].x), hf(v[b].x), re);
-      re = __builtin_fmaf(-hf(u.m[a][b].y), hf(v[b].y), re);
-      im = __builtin_fmaf(hf(u.m[a][b].x), hf(v[b].y), im);
-      im = __builtin_fmaf(hf(u.m[a][b].y), hf(v[b].x), im);
-    }
-    o[a] = {re, im};
+    h2_t c = u.m[a][0].xx * v[0];
+    c = h_fma(u.m[a][0].yy, vs[0], c);
+    c = h_fma(u.m[a][1].xx, v[1], c);
+    c = h_fma(u.m[a][1].yy, vs[1], c);
+    c = h_fma(u.m[a][2].xx, v[2], c);
+    o[a] = h_fma(u.m[a][2].yy, vs[2], c);
   }
 }
-__device__ __forceinline__ void su3h_dag_mul(const SU3H& u, const h2_t (&v)[3], cx<float> (&o)[3]) {
+// o = U^+ v: conj(u) v = u.re (v.re, v.im) + u.im (v.im, -v.re)
+__device__ __forceinline__ void su3h_dag_mul(const SU3H& u, const h2_t (&v)[3], h2_t (&o)[3]) {
+  h2_t vs[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) vs[b] = h2_t{v[b].y, -v[b].x};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float re = __builtin_fmaf(hf(u.m[0][a].x), hf(v[0].x), 0.0f);
-    float im = __builtin_fmaf(hf(u.m[0][a].x), hf(v[0].y), 0.0f);
-    re = __builtin_fmaf(hf(u.m[0][a].y), hf(v[0].y), re);
-    im = __builtin_fmaf(-hf(u.m[0][a].y), hf(v[0].x), im);
-#pragma unroll
-    for (int b = 1; b < 3; ++b) {
-      re = __builtin_fmaf(hf(u.m[b][a].x), hf(v[b].x), re);
-      re = __builtin_fmaf(hf(u.m[b][a].y), hf(v[b].y), re);
-      im = __builtin_fmaf(hf(u.m[b][a].x), hf(v[b].y), im);
-      im = __builtin_fmaf(-hf(u.m[b][a].y), hf(v[b].x), im);
-    }
-    o[a] = {re, im};
+    h2_t c = u.m[0][a].xx * v[0];
+    c = h_fma(u.m[0][a].yy, vs[0], c);
+    c = h_fma(u.m[1][a].xx, v[1], c);
+    c = h_fma(u.m[1][a].yy, vs[1], c);
+    c = h_fma(u.m[2][a].xx, v[2], c);
+    o[a] = h_fma(u.m[2][a].yy, vs[2], c);
   }
 }
-// acc += c U(x,mu) (1 - gamma_mu) psi(x+mu) and acc += c U(x-mu,mu)^+ (1 + gamma_mu) psi(x-mu),
+template <int SG> __device__ __forceinline__ void h_acc(h2_t& a, h2_t x) { a = SG > 0 ? a + x : a - x; }
+// acc += SG U(x,mu) (1 - gamma_mu) psi(x+mu) and acc += SG U(x-mu,mu)^+ (1 + gamma_mu) psi(x-mu):
 // the projections and reconstructions of hop_fwd and hop_bwd (chiral basis) on FP16 pairs
-__device__ __forceinline__ void hoph_fwd(int mu, const SU3H& U, const SpinorH& p, float c, Spinor<float>& acc) {
-  h2_t h0[3], h1[3];
-  cx<float> u0[3], u1[3];
+template <int SG> __device__ __forceinline__ void hoph_fwd(int mu, const SU3H& U, const SpinorH& p, SpinorH& acc) {
+  h2_t h0[3], h1[3], u0[3], u1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     switch (mu) {
@@ -830,21 +826,18 @@ __device__ __forceinline__ void hoph_fwd(int mu, const SU3H& U, const SpinorH& p
   su3h_mul(U, h1, u1);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    u0[a] = scale(c, u0[a]);
-    u1[a] = scale(c, u1[a]);
-    acc.v[0][a] = acc.v[0][a] + u0[a];
-    acc.v[1][a] = acc.v[1][a] + u1[a];
+    h_acc<SG>(acc.v[0][a], u0[a]);
+    h_acc<SG>(acc.v[1][a], u1[a]);
     switch (mu) {
-      case 0: acc.v[2][a] = acc.v[2][a] + u0[a]; acc.v[3][a] = acc.v[3][a] + u1[a]; break;
-      case 1: acc.v[2][a] = acc.v[2][a] + times_mi(u1[a]); acc.v[3][a] = acc.v[3][a] + times_mi(u0[a]); break;
-      case 2: acc.v[2][a] = acc.v[2][a] - u1[a]; acc.v[3][a] = acc.v[3][a] + u0[a]; break;
-      default: acc.v[2][a] = acc.v[2][a] + times_mi(u0[a]); acc.v[3][a] = acc.v[3][a] + times_i(u1[a]); break;
+      case 0: h_acc<SG>(acc.v[2][a], u0[a]); h_acc<SG>(acc.v[3][a], u1[a]); break;
+      case 1: h_acc<SG>(acc.v[2][a], h_tmi(u1[a])); h_acc<SG>(acc.v[3][a], h_tmi(u0[a])); break;
+      case 2: h_acc<-SG>(acc.v[2][a], u1[a]); h_acc<SG>(acc.v[3][a], u0[a]); break;
+      default: h_acc<SG>(acc.v[2][a], h_tmi(u0[a])); h_acc<SG>(acc.v[3][a], h_ti(u1[a])); break;
     }
   }
 }
-__device__ __forceinline__ void hoph_bwd(int mu, const SU3H& U, const SpinorH& p, float c, Spinor<float>& acc) {
-  h2_t h0[3], h1[3];
-  cx<float> w0[3], w1[3];
+template <int SG> __device__ __forceinline__ void hoph_bwd(int mu, const SU3H& U, const SpinorH& p, SpinorH& acc) {
+  h2_t h0[3], h1[3], w0[3], w1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     switch (mu) {
@@ -856,7 +849,17 @@ __device__ __forceinline__ void hoph_bwd(int mu, const SU3H& U, const SpinorH& p
   }
   su3h_dag_mul(U, h0, w0);
   su3h_dag_mul(U, h1, w1);
-  bwd_recon(mu, w0, w1, c, acc);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    h_acc<SG>(acc.v[0][a], w0[a]);
+    h_acc<SG>(acc.v[1][a], w1[a]);
+    switch (mu) {
+      case 0: h_acc<-SG>(acc.v[2][a], w0[a]); h_acc<-SG>(acc.v[3][a], w1[a]); break;
+      case 1: h_acc<SG>(acc.v[2][a], h_ti(w1[a])); h_acc<SG>(acc.v[3][a], h_ti(w0[a])); break;
+      case 2: h_acc<SG>(acc.v[2][a], w1[a]); h_acc<-SG>(acc.v[3][a], w0[a]); break;
+      default: h_acc<SG>(acc.v[2][a], h_ti(w0[a])); h_acc<-SG>(acc.v[3][a], h_ti(w1[a])); break;
+    }
+  }
 }
 
 template <class S, class LK, class T, bool STAGE = true, int L16 = 0>
@@ -1146,27 +1149,48 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
     for (int mu = 0; mu < 4; ++mu) {
       const int q = p ? nA[mu] : nB[mu];
       if (q >= 0) {
-        if constexpr (XH) {
-          SU3H U;
-          if (h == 0) link_h(mu, p, j, U);  // U(x, mu) of site j
-          else link_h(mu, 1 - p, q, U);     // U(x - mu, mu) of its neighbour
-          SpinorH nb;
-          spinor_h(p ? evh : odh, q, nb);
-          if (h == 0) hoph_fwd(mu, U, nb, c, acc);
-          else hoph_bwd(mu, U, nb, c, acc);
-        } else {
-          SU3<T> U;
-          if (h == 0) link(mu, p, j, s, U);
-          else link(mu, 1 - p, q, p ? gA[mu] : gB[mu], U);
-          Spinor<T> nb;
+        SU3<T> U;
+        if (h == 0) link(mu, p, j, s, U);
+        else link(mu, 1 - p, q, p ? gA[mu] : gB[mu], U);
+        Spinor<T> nb;
 #pragma unroll
-          for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = p ? ev[k][q] : od[k][q];
-          if (h == 0) hop_fwd(mu, U, nb, c, acc);
-          else hop_bwd(mu, U, nb, c, acc);
-        }
+        for (int k = 0; k < 12; ++k) nb.v[k / 3][k % 3] = p ? ev[k][q] : od[k][q];
+        if (h == 0) hop_fwd(mu, U, nb, c, acc);
+        else hop_bwd(mu, U, nb, c, acc);
       }
     }
   };
+  // the same in the FP16 form, with sign SG and the hop sum in FP16 pairs
+  auto phase_h = [&](auto P, auto sg, SpinorH& acc) {
+    constexpr int p = decltype(P)::value;
+    constexpr int SG = decltype(sg)::value;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc.v[k / 3][k % 3] = h2_t{0, 0};
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const int q = p ? nA[mu] : nB[mu];
+      if (q >= 0) {
+        SU3H U;
+        if (h == 0) link_h(mu, p, j, U);  // U(x, mu) of site j
+        else link_h(mu, 1 - p, q, U);     // U(x - mu, mu) of its neighbour
+        SpinorH nb;
+        spinor_h(p ? evh : odh, q, nb);
+        if (h == 0) hoph_fwd<SG>(mu, U, nb, acc);
+        else hoph_bwd<SG>(mu, U, nb, acc);
+      }
+    }
+  };
+  auto put_h = [&](int E, const SpinorH& v) {
+    uint4(*f)[H] = E ? odh : evh;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[e] = __builtin_bit_cast(uint32_t, v.v[(4 * k + e) / 3][(4 * k + e) % 3]);
+      f[k][j] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  };
+  auto get_h = [&](int E, SpinorH& v) { spinor_h(E ? odh : evh, j, v); };
   auto phase_odd = [&](auto sg, Spinor<T>& acc) { phase(std::integral_constant<int, 1>{}, sg, acc); };
   auto phase_even = [&](auto sg, Spinor<T>& acc) { phase(std::integral_constant<int, 0>{}, sg, acc); };
 
@@ -1187,6 +1211,107 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
   }
   const double stop2 = a.tol > 0 ? a.tol * a.tol * b2 * double(sig) * double(sig) : -1.0;
   zero(d);
+  int it = 0;
+  if constexpr (XH) {
+    using P0 = std::integral_constant<int, 0>;
+    using Q1 = std::integral_constant<int, 1>;
+    SpinorH ah;
+    // even right-hand side rho_e + k H_eo rho_o (lane 0); lane 1 keeps rho_o
+    if (h == 1) put(1, r);
+    __syncthreads();
+    phase_h(P0{}, P1{}, ah);
+    if (h == 1) put_h(0, ah);
+    __syncthreads();
+    if (h == 0) {
+      SpinorH e;
+      get_h(0, e);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const cx<float> z = h_f32(ah.v[k / 3][k % 3] + e.v[k / 3][k % 3]);
+        r.v[k / 3][k % 3] = {r.v[k / 3][k % 3].re + z.re, r.v[k / 3][k % 3].im + z.im};
+      }
+    }
+    if (b2 > 0.0) {
+      for (; it < a.niter; ++it) {
+        // p = (1 - k^2 H_eo H_oe) r on the even sites
+        if (h == 0) put(0, r);
+        __syncthreads();
+        phase_h(Q1{}, P1{}, ah);
+        if (h == 0) put_h(1, ah);
+        __syncthreads();
+        if (h == 1) {
+          SpinorH o;
+          get_h(1, o);
+#pragma unroll
+          for (int k = 0; k < 12; ++k) o.v[k / 3][k % 3] = o.v[k / 3][k % 3] + ah.v[k / 3][k % 3];
+          put_h(1, o);
+        }
+        __syncthreads();
+        phase_h(P0{}, M1{}, ah);
+        if (h == 1) put_h(0, ah);  // ev is free: every read of it was in the odd phase
+        __syncthreads();
+        // inner products summed in FP32 over the lane's twelve components, then in FP64
+        float frr = 0.f, fri = 0.f, fpp = 0.f;
+        if (h == 0) {
+          SpinorH e;
+          get_h(0, e);
+#pragma unroll
+          for (int k = 0; k < 12; ++k) {
+            const cx<float> z = h_f32(ah.v[k / 3][k % 3] + e.v[k / 3][k % 3]);
+            const cx<float> rv = r.v[k / 3][k % 3];
+            const cx<float> pv = {rv.re + z.re, rv.im + z.im};
+            acc.v[k / 3][k % 3] = pv;
+            frr = fmadd(pv.re, rv.re, fmadd(pv.im, rv.im, frr));
+            fri = fmadd(pv.re, rv.im, fmadd(-pv.im, rv.re, fri));
+            fpp = fmadd(pv.re, pv.re, fmadd(pv.im, pv.im, fpp));
+          }
+        }
+        double prr = frr, pri = fri, pp = fpp;
+        wg_sum3(prr, pri, pp, sm);
+        if (!(pp > 0.0)) break;
+        const cx<T> alpha = {T(prr / pp), T(pri / pp)};
+        float frs = 0.f;
+        if (h == 0) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              d.v[q][c] = d.v[q][c] + cmul(alpha, r.v[q][c]);
+              r.v[q][c] = r.v[q][c] - cmul(alpha, acc.v[q][c]);
+            }
+          if (stop2 > 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) frs = fmadd(r.v[q][c].re, r.v[q][c].re, fmadd(r.v[q][c].im, r.v[q][c].im, frs));
+          }
+        }
+        if (stop2 > 0) {
+          const double rr = wg_sum(double(frs), sm[0]);
+          if (rr <= stop2) {
+            ++it;
+            break;
+          }
+        }
+      }
+    }
+    // x_o = rho_o + k H_oe x_e; the odd residual is then zero
+    if (h == 0) put(0, d);
+    __syncthreads();
+    phase_h(Q1{}, P1{}, ah);
+    if (h == 0) put_h(1, ah);
+    __syncthreads();
+    if (h == 1) {
+      SpinorH o;
+      get_h(1, o);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const cx<float> z = h_f32(o.v[k / 3][k % 3] + ah.v[k / 3][k % 3]);
+        d.v[k / 3][k % 3] = {r.v[k / 3][k % 3].re + z.re, r.v[k / 3][k % 3].im + z.im};
+        r.v[k / 3][k % 3] = {T(0), T(0)};
+      }
+    }
+  } else {
 
   // even right-hand side rho_e + k H_eo rho_o (lane 0); lane 1 keeps rho_o
   if (h == 1) put(1, r);
@@ -1201,7 +1326,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
     for (int k = 0; k < 12; ++k) r.v[k / 3][k % 3] = r.v[k / 3][k % 3] + acc.v[k / 3][k % 3] + e.v[k / 3][k % 3];
   }
 
-  int it = 0;
   if (b2 > 0.0) {
     for (; it < a.niter; ++it) {
       // p = (1 - k^2 H_eo H_oe) r on the even sites
@@ -1275,6 +1399,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
       r.v[k / 3][k % 3] = {T(0), T(0)};
     }
   }
+  }
   if constexpr (XH) {  // back to the scale of rho
     const T isig = T(1) / sig;
 #pragma unroll
@@ -1285,8 +1410,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
         d.v[q][c] = scale(isig, d.v[q][c]);
       }
   }
-  S::store(rho + size_t(h) * S::NC * Vh, Vh, s, r);
-  S::store(dl + size_t(h) * S::NC * Vh, Vh, s, d);
+  // the FP16 form's BF16 fields (the preconditioner's own residual, correction and
+  // iterate) take the one-instruction conversion; other forms round to nearest even
+  auto store = [&](unit* f, const Spinor<T>& v) {
+    if constexpr (XH && std::is_same<S, StBF16>::value) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const cx<T> z = v.v[(4 * k + e) / 3][(4 * k + e) % 3];
+          w[e] = bf16_pack2(z.re, z.im);
+        }
+        f[size_t(k) * Vh + s] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    } else {
+      S::store(f, Vh, s, v);
+    }
+  };
+  store(rho + size_t(h) * S::NC * Vh, r);
+  store(dl + size_t(h) * S::NC * Vh, d);
   Spinor<T> xv;
   if (a.x_assign) zero(xv);
   else S::load(x + size_t(h) * S::NC * Vh, Vh, s, xv);
@@ -1294,7 +1437,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < 3; ++c) xv.v[q][c] = xv.v[q][c] + d.v[q][c];
-  S::store(x + size_t(h) * S::NC * Vh, Vh, s, xv);
+  store(x + size_t(h) * S::NC * Vh, xv);
   if (a.iters && threadIdx.x == 0) atomicMax(a.iters, it);
 }
 
