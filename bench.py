@@ -41,9 +41,11 @@ def log(*a):
 
 
 # Schwarz cycles x block iterations where the measured best differs from the library
-# default (4 x 6, best for mixed at 8^4 and for both modes at 16^4 and 32^4): plain
-# FP64 at 8^4 prefers 5 x 6.
-SAP_TUNED = {("8x8x8x8", "plain"): (5, 6)}
+# default (4 x 6, best for mixed at 8^4 and for both modes at 16^4): plain FP64 at 8^4
+# prefers 5 x 6. At 32^4 (s per step of 4 proposals x 32 noise fields): BF16-mixed 4 x 6
+# 3.71, 5 x 6 3.64, 5 x 8 3.58, 6 x 6 3.58, 6 x 8 3.68, 7 x 6 3.75; plain FP64 4 x 6 13.6,
+# 6 x 6 13.1, 5 x 8 12.4.
+SAP_TUNED = {("8x8x8x8", "plain"): (5, 6), ("32x32x32x32", "mixed_bf16"): (6, 6), ("32x32x32x32", "plain"): (5, 8)}
 
 
 def mode_params(psms, mode: str, tol: float, workload: str | None = None):
@@ -464,6 +466,7 @@ def main():
     ap.add_argument("--mode", default="mixed_bf16")
     ap.add_argument("--rhs-chunk", type=int, default=32, help="right-hand sides per solver launch (memory)")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--plain-warmup", type=int, default=1, help="untimed plain steps first (buffers, first launches)")
     ap.add_argument("--plain-rhs-chunk", type=int, default=16, help="FP64 Krylov bases are 4x larger than BF16")
     ap.add_argument("--nprop", type=int, default=None)
     ap.add_argument("--nnoise", type=int, default=None)
@@ -531,7 +534,7 @@ def main():
         _, ctxp, _, _, _, _ = setup(args.workload, inputs=(w, inputs[1], inputs[2], inputs[3][:0]))
         for k, v in tune.items():
             ctxp.set_tuning(k, v)
-        dtp, stp, _, d_plain = run_steps(psms, ctxp, noise, delta, nprop, plain, args.plain_steps, 0)
+        dtp, stp, _, d_plain = run_steps(psms, ctxp, noise, delta, nprop, plain, args.plain_steps, args.plain_warmup)
         s_plain = dtp / args.plain_steps / nest
         log(f"plain f64: {1e3 * dtp / args.plain_steps:.2f} ms/step, solver {stp[-1]}")
         if learned and d_learned is not None and "error" not in learned:
