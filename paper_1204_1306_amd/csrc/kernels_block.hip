@@ -913,7 +913,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L16 ? 
   // in-block neighbours of this lane's four hops: nA for the odd site j (even
   // neighbours), nB for the even site j (odd neighbours); -1 when the hop leaves the block
   int nA[4], nB[4], gA[4], gB[4], lo[4];
-  {
+  if constexpr (XH) {
+    // in-block neighbours from the local coordinates alone: x + dir mu stays in the block
+    // when 0 <= l_mu + dir < b_mu, at in-block index (locallex + dir sl_mu) / 2
+    const uint32_t w1 = g.lcoord[g.Vbh + j], w0 = g.lcoord[j];
+    int l1[4], l0[4], x1 = 0, x0 = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      l1[m] = (w1 >> (8 * m)) & 255;
+      l0[m] = (w0 >> (8 * m)) & 255;
+      x1 += l1[m] * g.sl[m];
+      x0 += l0[m] * g.sl[m];
+    }
+    const int dir = h == 0 ? 1 : -1;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const int t1 = l1[mu] + dir, t0 = l0[mu] + dir;
+      nA[mu] = (t1 >= 0 && t1 < g.b[mu]) ? (x1 + dir * g.sl[mu]) >> 1 : -1;
+      nB[mu] = (t0 >= 0 && t0 < g.b[mu]) ? (x0 + dir * g.sl[mu]) >> 1 : -1;
+      gA[mu] = gB[mu] = 0;  // the L2-link path only
+      lo[mu] = h ? l1[mu] : l0[mu];
+    }
+  } else {
     SiteInfo so, se;
     site_info(g, 1, s, so);
     site_info(g, 0, s, se);

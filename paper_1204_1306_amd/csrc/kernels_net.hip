@@ -323,10 +323,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) k
         // the 8 bf16 of one colour (4 spins x re/im) are contiguous: two 8-byte stores
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+          // the matrix cores' operands round with gfx950's one-instruction conversion (its
+          // last-bit choices on some inputs do not matter at bf16 precision)
           uint32_t w[4];
 #pragma unroll
-          for (int sp = 0; sp < 4; ++sp)
-            w[sp] = uint32_t(uint16_t(to_bf16(v.v[sp][c].re))) | (uint32_t(uint16_t(to_bf16(v.v[sp][c].im))) << 16);
+          for (int sp = 0; sp < 4; ++sp) w[sp] = bf16_pack2(v.v[sp][c].re, v.v[sp][c].im);
           uint2* dst = reinterpret_cast<uint2*>(&Bs[l * 3 + c][ci * 8]);
           dst[0] = make_uint2(w[0], w[1]);
           dst[1] = make_uint2(w[2], w[3]);
