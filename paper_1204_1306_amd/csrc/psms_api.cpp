@@ -2819,12 +2819,12 @@ psms_status psms_autotune(psms_ctx* c, int slot, const char* cache_path) {
       FieldBatch out = field(c, "tune_out", si == 2 ? P_F32 : P, np, nrhs);
       fill(in);
       const int r = si == 0 ? reps : std::max(3, reps / 4);
-      for (int round = 0; round < 4; ++round)  // round 0 only warms up (clocks, first launches)
+      for (int pass = 0; pass < 4; ++pass)  // pass 0 only warms up (clocks, first launches)
         for (int v = 0; v < NVAR; ++v) {
           if (any_clean && spills[v]) continue;
           c->variant[pr] = v;
           const double t = time_dslash(c, L, in, out, r);
-          if (round > 0) tv[v][si] = std::min(tv[v][si], t);
+          if (pass > 0) tv[v][si] = std::min(tv[v][si], t);
         }
     }
     double fastest[3] = {1e30, 1e30, 1e30};
