@@ -217,6 +217,39 @@ def test_solve_schwarz_link_storage(psms, link16):
             assert np.linalg.norm(res) / np.linalg.norm(bvec[r]) <= 1e-10 * 1.01
 
 
+def test_schwarz_sweep_forms_apply_the_same_preconditioner(psms):
+    """The Schwarz sweep's LDS forms against the FP32 form on the same input: after one
+    inner iteration the solution is alpha M b (M the Schwarz preconditioner, alpha the
+    minimal-residual step), so the forms must agree to the rounding of their FP16 links,
+    fields and hop arithmetic (measured: about 1e-5 relative; bound 2e-2), far below the
+    O(1) change that a wrong sign, neighbour or spin projector in a hop would make.
+    Converged, each form meets the FP64 true residual in about the same number of
+    iterations."""
+    L, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kappa = 0.155
+    U = synth.gauge_field(L, 0.6, 2003)
+    bvec = synth.gaussian_noise(L, 2, 44)
+    ctx = make_ctx(psms, L, b, kappa)
+    ctx.gauge_load(0, U)
+    ctx.set_tuning("block_eo_lanes", 2)  # the two-lane form, which stages the links
+    one, iters = {}, {}
+    for form in (0, 1, 2):
+        ctx.set_tuning("sap_link16", form)
+        prm = psms.default_params(tol=1e-12, max_iter=1, prec=psms.MIXED, inner_storage=psms.SPINOR_F32)
+        one[form], _ = ctx.solve(0, bvec, prm, check=False)
+        x, st = ctx.solve(0, bvec, psms.default_params(tol=1e-10, prec=psms.MIXED, inner_storage=psms.SPINOR_F32))
+        iters[form] = st["inner_iters"]
+        for r in range(2):
+            res = bvec[r] - dirac.apply_D(U, x[r], kappa, L)
+            assert np.linalg.norm(res) / np.linalg.norm(bvec[r]) <= 1e-10 * 1.01
+    for form in (1, 2):
+        d = rel(one[form], one[0])
+        say(f"  Schwarz form {form} against FP32: one-iteration solution differs by {d:.2e}; "
+            f"iterations {iters[form]} against {iters[0]}")
+        assert d < 2e-2
+        assert abs(iters[form] - iters[0]) <= max(2, iters[0] // 10)
+
+
 def test_solve_small_against_lu(psms):
     L, b = (4, 4, 4, 4), (2, 2, 2, 2)
     kappa = 0.12
