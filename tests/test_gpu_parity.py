@@ -218,11 +218,12 @@ def test_solve_schwarz_link_storage(psms, link16):
 
 
 def test_schwarz_sweep_forms_apply_the_same_preconditioner(psms):
-    """The Schwarz sweep's LDS forms against the FP32 form on the same input: after one
-    inner iteration the solution is alpha M b (M the Schwarz preconditioner, alpha the
-    minimal-residual step), so the forms must agree to the rounding of their FP16 links,
-    fields and hop arithmetic (measured: about 1e-5 relative; bound 2e-2), far below the
-    O(1) change that a wrong sign, neighbour or spin projector in a hop would make.
+    """The Schwarz sweep's LDS forms against the FP32 form on the same input. A solve cut
+    off at max_iter = 1 (three inner iterations with the lagged convergence check, true
+    residual about 6e-4) depends on the preconditioner through every Krylov vector: the
+    forms must reach the same residual (within 10%) and the same solution (measured: about
+    1e-5 relative; bound 2e-2). A wrong sign, neighbour or spin projector in a hop makes the
+    preconditioner worse, which raises that residual and moves the solution by far more.
     Converged, each form meets the FP64 true residual in about the same number of
     iterations."""
     L, b = (8, 8, 8, 8), (4, 4, 4, 4)
@@ -232,11 +233,13 @@ def test_schwarz_sweep_forms_apply_the_same_preconditioner(psms):
     ctx = make_ctx(psms, L, b, kappa)
     ctx.gauge_load(0, U)
     ctx.set_tuning("block_eo_lanes", 2)  # the two-lane form, which stages the links
-    one, iters = {}, {}
+    one, iters, res1 = {}, {}, {}
     for form in (0, 1, 2):
         ctx.set_tuning("sap_link16", form)
         prm = psms.default_params(tol=1e-12, max_iter=1, prec=psms.MIXED, inner_storage=psms.SPINOR_F32)
-        one[form], _ = ctx.solve(0, bvec, prm, check=False)
+        one[form], st1 = ctx.solve(0, bvec, prm, check=False)
+        res1[form] = st1["true_rel_residual"]
+        say(f"  form {form}: solve cut off at max_iter 1: {st1}")
         x, st = ctx.solve(0, bvec, psms.default_params(tol=1e-10, prec=psms.MIXED, inner_storage=psms.SPINOR_F32))
         iters[form] = st["inner_iters"]
         for r in range(2):
@@ -244,9 +247,10 @@ def test_schwarz_sweep_forms_apply_the_same_preconditioner(psms):
             assert np.linalg.norm(res) / np.linalg.norm(bvec[r]) <= 1e-10 * 1.01
     for form in (1, 2):
         d = rel(one[form], one[0])
-        say(f"  Schwarz form {form} against FP32: one-iteration solution differs by {d:.2e}; "
-            f"iterations {iters[form]} against {iters[0]}")
+        say(f"  Schwarz form {form} against FP32: cut-off solution differs by {d:.2e}, residual "
+            f"{res1[form]:.3e} against {res1[0]:.3e}; iterations {iters[form]} against {iters[0]}")
         assert d < 2e-2
+        assert abs(res1[form] - res1[0]) <= 0.1 * res1[0]
         assert abs(iters[form] - iters[0]) <= max(2, iters[0] // 10)
 
 
