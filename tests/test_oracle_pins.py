@@ -308,6 +308,9 @@ def test_estimator_moments_full():
     assert np.var(d) == pytest.approx(e_var, rel=0.05)
     # and exp of the log-ratio estimate is the mean of e^-Delta
     assert np.exp(estimator.log_ratio_estimate(d)) == pytest.approx(np.mean(np.exp(-d)), rel=1e-12)
+    # the estimate is the log-determinant ratio it stands for: ln det(M^dagger M)^-1, the sum of
+    # the logs of the eigenvalues, within the Monte Carlo error of the mean (delta method)
+    assert abs(estimator.log_ratio_estimate(d) + np.sum(np.log(lam))) < 5 * se / np.mean(np.exp(-d))
 
 
 def test_estimator_schur_quadratic_form_even_odd():
